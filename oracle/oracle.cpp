@@ -1,0 +1,1073 @@
+// FP64 CPU oracle: macrofacet rendering of Gaussian process statistical surfaces.
+// TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain and slow on purpose: every
+// quantity is evaluated from the paper's printed formula in double precision, one
+// path at a time, with no blocking, caching or reordering.
+#include "oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <unordered_map>
+#include <vector>
+
+#include <omp.h>
+
+#include "numerics.hpp"
+
+using namespace orc;
+
+namespace {
+
+struct Grid {
+    int res[3] = {0, 0, 0};
+    std::vector<double> v;
+    bool empty() const { return v.empty(); }
+};
+
+struct Prim {
+    int kind;
+    double c[3];
+    double h[3];
+    double albedo;
+};
+
+}  // namespace
+
+struct oracle_scene {
+    int mean_kind;
+    double mean_const;
+    std::vector<Prim> prims;
+    Grid offset, var;
+    double variance, l, albedo;
+    bool albedo_per_prim;
+    double lo[3], hi[3], ext[3];
+    double R;
+    int M[3];
+    double cw[3];
+    std::vector<double> maj;
+    double dl[4], pl[4], env;
+    int cam_kind;
+    double eye[3], fwd[3], right[3], upc[3];
+    double tan_half, aspect, win[2];
+    int W, H, spp, max_depth;
+    uint32_t key[2];
+};
+
+namespace {
+
+using Scene = oracle_scene;
+
+inline double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+inline void cross3(const double a[3], const double b[3], double r[3]) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+inline void normalize3(double a[3]) {
+    const double n = std::sqrt(dot3(a, a));
+    a[0] /= n; a[1] /= n; a[2] /= n;
+}
+
+// Orthonormal basis around a unit vector n (Duff et al., "Building an orthonormal
+// basis, revisited", JCGT 2017).
+inline void onb(const double n[3], double t[3], double b[3]) {
+    const double sign = std::copysign(1.0, n[2]);
+    const double a = -1.0 / (sign + n[2]);
+    const double bb = n[0] * n[1] * a;
+    t[0] = 1.0 + sign * n[0] * n[0] * a; t[1] = sign * bb; t[2] = -sign * n[0];
+    b[0] = bb; b[1] = sign + n[1] * n[1] * a; b[2] = -n[1];
+}
+
+struct Counters {
+    int64_t c[ORC_C_COUNT] = {};
+    void add(const Counters& o) { for (int i = 0; i < ORC_C_COUNT; ++i) c[i] += o.c[i]; }
+};
+
+// ---------------------------------------------------------------------------
+// Mean function geometry (the parameter-free part of mu and grad mu).
+// ---------------------------------------------------------------------------
+void sdf_prim(const Prim& p, const double x[3], double& f, double g[3]) {
+    if (p.kind == 0) {
+        const double v[3] = {x[0] - p.c[0], x[1] - p.c[1], x[2] - p.c[2]};
+        const double r = std::sqrt(dot3(v, v));
+        f = r - p.h[0];
+        if (r > 0.0) { g[0] = v[0] / r; g[1] = v[1] / r; g[2] = v[2] / r; }
+        else { g[0] = 0.0; g[1] = 0.0; g[2] = 1.0; }
+        return;
+    }
+    // axis-aligned box: exact signed distance
+    double q[3], sg[3];
+    for (int a = 0; a < 3; ++a) {
+        const double dx = x[a] - p.c[a];
+        sg[a] = dx < 0.0 ? -1.0 : 1.0;
+        q[a] = std::fabs(dx) - p.h[a];
+    }
+    const double qmax = std::max(q[0], std::max(q[1], q[2]));
+    if (qmax > 0.0) {
+        double qp[3] = {std::max(q[0], 0.0), std::max(q[1], 0.0), std::max(q[2], 0.0)};
+        const double n = std::sqrt(dot3(qp, qp));
+        f = n;
+        for (int a = 0; a < 3; ++a) g[a] = sg[a] * qp[a] / n;
+    } else {
+        f = qmax;
+        int ax = 0;
+        if (q[1] > q[ax]) ax = 1;
+        if (q[2] > q[ax]) ax = 2;
+        g[0] = g[1] = g[2] = 0.0;
+        g[ax] = sg[ax];
+    }
+}
+
+double sdf_union(const Scene& S, const double x[3], double g[3], int& which) {
+    double best = INFINITY;
+    which = -1;
+    for (size_t i = 0; i < S.prims.size(); ++i) {
+        double f, gi[3];
+        sdf_prim(S.prims[i], x, f, gi);
+        if (f < best) { best = f; which = (int)i; g[0] = gi[0]; g[1] = gi[1]; g[2] = gi[2]; }
+    }
+    return best;
+}
+
+void mean_geom(const Scene& S, const double x[3], double& f, double g[3], int& which) {
+    which = -1;
+    if (S.mean_kind == 0) { f = x[2]; g[0] = 0; g[1] = 0; g[2] = 1; return; }
+    if (S.mean_kind == 2) { f = S.mean_const; g[0] = g[1] = g[2] = 0; return; }
+    f = sdf_union(S, x, g, which);
+}
+
+// Trilinear interpolation on a node-centred grid over the scene box.
+struct Tri {
+    int64_t idx[8];
+    double w[8];
+    double dw[8][3];
+};
+
+void trilinear(const Grid& G, const Scene& S, const double x[3], Tri& t) {
+    int i0[3];
+    double f[3], sc[3];
+    for (int a = 0; a < 3; ++a) {
+        double u = (x[a] - S.lo[a]) / S.ext[a] * (G.res[a] - 1);
+        u = std::min(std::max(u, 0.0), (double)(G.res[a] - 1));
+        int i = (int)std::floor(u);
+        if (i > G.res[a] - 2) i = G.res[a] - 2;
+        i0[a] = i;
+        f[a] = u - i;
+        sc[a] = (G.res[a] - 1) / S.ext[a];
+    }
+    int n = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx, ++n) {
+                const double wx = dx ? f[0] : 1.0 - f[0];
+                const double wy = dy ? f[1] : 1.0 - f[1];
+                const double wz = dz ? f[2] : 1.0 - f[2];
+                t.idx[n] = ((int64_t)(i0[2] + dz) * G.res[1] + (i0[1] + dy)) * G.res[0] + (i0[0] + dx);
+                t.w[n] = wx * wy * wz;
+                t.dw[n][0] = (dx ? 1.0 : -1.0) * sc[0] * wy * wz;
+                t.dw[n][1] = (dy ? 1.0 : -1.0) * sc[1] * wx * wz;
+                t.dw[n][2] = (dz ? 1.0 : -1.0) * sc[2] * wx * wy;
+            }
+}
+
+// ---------------------------------------------------------------------------
+// GP statistics at a point (Sec. 3.1): f(x) ~ N(mu(x), sigma^2) and, independent of it
+// at the same point (Eq. joint_fg), g(x) ~ N(grad mu(x), (sigma/l)^2 I) for the
+// isotropic squared-exponential kernel.
+// ---------------------------------------------------------------------------
+template <class T>
+struct PointQ {
+    T mu;
+    T G[3];
+    T sigma;
+    T s;       // per-axis gradient standard deviation sigma / l
+    T albedo;
+};
+
+template <class T>
+struct Params {
+    const Scene* S = nullptr;
+    const std::unordered_map<int64_t, int>* node_slot = nullptr;
+    int slot_var = -1, slot_l = -1, slot_alb = -1;
+};
+
+template <class T> inline T mk(double v, int slot);
+template <> inline double mk<double>(double v, int) { return v; }
+template <> inline Dual mk<Dual>(double v, int slot) { return Dual::var(v, slot); }
+
+template <class T>
+PointQ<T> eval_point(const Params<T>& P, const double x[3]) {
+    const Scene& S = *P.S;
+    PointQ<T> q;
+    double f, g[3];
+    int which;
+    mean_geom(S, x, f, g, which);
+    q.mu = T(f);
+    for (int a = 0; a < 3; ++a) q.G[a] = T(g[a]);
+    if (!S.offset.empty()) {
+        Tri t;
+        trilinear(S.offset, S, x, t);
+        for (int n = 0; n < 8; ++n) {
+            int slot = -1;
+            if (P.node_slot) {
+                auto it = P.node_slot->find(t.idx[n]);
+                if (it != P.node_slot->end()) slot = it->second;
+            }
+            const T node = mk<T>(S.offset.v[t.idx[n]], slot);
+            q.mu = q.mu + t.w[n] * node;
+            for (int a = 0; a < 3; ++a) q.G[a] = q.G[a] + t.dw[n][a] * node;
+        }
+    }
+    T variance;
+    if (!S.var.empty()) {
+        Tri t;
+        trilinear(S.var, S, x, t);
+        double v = 0.0;
+        for (int n = 0; n < 8; ++n) v += t.w[n] * S.var.v[t.idx[n]];
+        variance = T(v);
+    } else {
+        variance = mk<T>(S.variance, P.slot_var);
+    }
+    q.sigma = t_sqrt(variance);
+    q.s = q.sigma / mk<T>(S.l, P.slot_l);
+    if (S.albedo_per_prim && which >= 0) q.albedo = T(S.prims[which].albedo);
+    else q.albedo = mk<T>(S.albedo, P.slot_alb);
+    return q;
+}
+
+// Density (Sec. 3.2 Eq. h_density with the height mapped to the SDF value, Sec. 4):
+// rho = phi(f; 0, sigma^2) / Phi(f; 0, sigma^2) evaluated at the mean mu(x).
+template <class T>
+T rho_of(const T& mu, const T& sigma) {
+    const T z = mu / sigma;
+    if (val(z) > -30.0) {
+        const T ph = t_exp(-0.5 * z * z) / (kSqrt2Pi * sigma);
+        const T Ph = 0.5 * t_erfc(-z / kSqrt2);
+        return ph / Ph;
+    }
+    // far tail: the same ratio written with erfcx so that Phi does not underflow
+    return std::sqrt(2.0 / kPi) / (sigma * t_erfcx(-z / kSqrt2));
+}
+
+// Eq. generalized_lambda times cos(theta): the projected area of Eq. generalized_sigma_t in
+// the frame of the geometric normal, for a direction with cos(theta) = c and squared
+// tangent components tx2 = sin^2 cos^2 phi, ty2 = sin^2 sin^2 phi.
+//   Lambda(a) c = c e^{-a^2}/(2 a sqrt(pi)) + (erf(a) - 1) c / 2,  a = c / den,
+// written with c / a = den and erf(a) - 1 = -erfc(a).
+template <class T>
+T lambda_cos_general(const T& ax, const T& ay, const T& az, const T& c, const T& tx2, const T& ty2) {
+    const T den = t_sqrt(ax * ax * tx2 + ay * ay * ty2 + az * az * c * c);
+    const T a = c / den;
+    return den * t_exp(-a * a) / (2.0 * kSqrtPi) - 0.5 * t_erfc(a) * c;
+}
+
+// Eq. macro_ndf (Appendix A), in the frame of the geometric normal, for a normal with
+// cos(theta_m) = c and squared tangent components tx2, ty2.
+template <class T>
+T ndf_general(const T& ax, const T& ay, const T& az, const T& c, const T& tx2, const T& ty2) {
+    const T A = tx2 / (ax * ax) + ty2 / (ay * ay) + c * c / (az * az);
+    const T B = c / (az * az);
+    const T C = 1.0 / (az * az);
+    const T BA = B * B / A;
+    const T pre = t_exp(-C + BA) / (kPi * kSqrtPi * ax * ay * az);
+    const T t1 = (1.0 / (2.0 * A * A)) * (BA + 1.0) * t_exp(-BA);
+    const T t2 = B * kSqrtPi / (2.0 * A * A * t_sqrt(A)) * (BA + 1.5) * t_erfc(-B / t_sqrt(A));
+    return pre * (t1 + t2);
+}
+
+// Projected area for travel direction d at a point whose gradient is g ~ N(G, s^2 I):
+// the paper's Lambda(w) cos(theta) about the local geometric normal G/|G| with the
+// isotropic roughness alpha = sqrt(2) s / |G| (Eq. roughness), scaled by |G|, the length
+// of the mean gradient.
+template <class T>
+T sigma_proj(const PointQ<T>& q, const double d[3]) {
+    const T g2 = q.G[0] * q.G[0] + q.G[1] * q.G[1] + q.G[2] * q.G[2];
+    if (val(g2) == 0.0) return q.s / kSqrt2Pi;  // E[max(0, -d.g)] for g ~ N(0, s^2 I)
+    const T gn = t_sqrt(g2);
+    const T c = (q.G[0] * d[0] + q.G[1] * d[1] + q.G[2] * d[2]) / gn;
+    const T alpha = kSqrt2 * q.s / gn;
+    return gn * lambda_cos_general(alpha, alpha, alpha, c, 1.0 - c * c, T(0.0));
+}
+
+// Generalized NDF at normal wm for g ~ N(G, s^2 I): Eq. macro_ndf with
+// alpha_x = alpha_y = alpha_z = sqrt(2) s / |G| about G/|G|, scaled by |G|.
+template <class T>
+T ndf(const PointQ<T>& q, const double wm[3]) {
+    const T g2 = q.G[0] * q.G[0] + q.G[1] * q.G[1] + q.G[2] * q.G[2];
+    if (val(g2) == 0.0) return q.s / (kSqrt2 * kPi * kSqrtPi);  // isotropic limit
+    const T gn = t_sqrt(g2);
+    const T c = (q.G[0] * wm[0] + q.G[1] * wm[1] + q.G[2] * wm[2]) / gn;
+    const T alpha = kSqrt2 * q.s / gn;
+    return gn * ndf_general(alpha, alpha, alpha, c, 1.0 - c * c, T(0.0));
+}
+
+// Beckmann NDF and Smith Lambda (the height-field limit used by the proposal).
+double beckmann_D(double alpha, double cos_m, double sin2_m) {
+    if (cos_m <= 0.0) return 0.0;
+    const double c2 = cos_m * cos_m;
+    return std::exp(-sin2_m / (c2 * alpha * alpha)) / (kPi * alpha * alpha * c2 * c2);
+}
+double beckmann_lambda(double a) {
+    if (std::isinf(a)) return 0.0;
+    return 0.5 * (std::exp(-a * a) / (a * kSqrtPi) - std::erfc(a));
+}
+
+// ---------------------------------------------------------------------------
+// Proposal over half vectors (end of Sec. 4.2.2): with probability R the Beckmann
+// distribution of visible normals (Heitz and d'Eon 2014, slope-space inversion) for
+// alpha_B = sqrt(2) s / |G| about G/|G|; otherwise uniform over the hemisphere about
+// v = -d.  The Beckmann part is used only while v is above the local horizon.
+// ---------------------------------------------------------------------------
+struct Proposal {
+    bool beck;          // Beckmann component available
+    double Reff;
+    double N[3], T[3], B[3];
+    double alpha, cosv, a;  // a = cot(theta_v) in the stretched configuration
+};
+
+Proposal make_proposal(const PointQ<double>& q, double R, const double v[3]) {
+    Proposal p;
+    const double gn = std::sqrt(dot3(q.G, q.G));
+    p.beck = false;
+    p.Reff = 0.0;
+    if (gn > 0.0) {
+        p.N[0] = q.G[0] / gn; p.N[1] = q.G[1] / gn; p.N[2] = q.G[2] / gn;
+        p.cosv = dot3(v, p.N);
+        if (p.cosv > 0.0) {
+            p.beck = true;
+            p.Reff = R;
+            p.alpha = kSqrt2 * q.s / gn;
+            double vt[3] = {v[0] - p.cosv * p.N[0], v[1] - p.cosv * p.N[1], v[2] - p.cosv * p.N[2]};
+            const double st = std::sqrt(dot3(vt, vt));
+            if (st > 1e-7) {
+                p.T[0] = vt[0] / st; p.T[1] = vt[1] / st; p.T[2] = vt[2] / st;
+                p.a = p.cosv / (p.alpha * st);
+            } else {
+                double b[3];
+                onb(p.N, p.T, b);
+                p.a = INFINITY;
+            }
+            cross3(p.N, p.T, p.B);
+        }
+    }
+    return p;
+}
+
+double beckmann_vndf_pdf(const Proposal& p, const double v[3], const double wm[3]) {
+    if (!p.beck) return 0.0;
+    const double cm = dot3(wm, p.N);
+    if (cm <= 0.0) return 0.0;
+    double cr[3];
+    cross3(wm, p.N, cr);
+    const double D = beckmann_D(p.alpha, cm, dot3(cr, cr));
+    const double vm = std::max(0.0, dot3(v, wm));
+    return vm * D / ((1.0 + beckmann_lambda(p.a)) * p.cosv);
+}
+
+double mixture_pdf(const Proposal& p, const double v[3], const double wm[3]) {
+    if (dot3(v, wm) <= 0.0) return 0.0;  // both components live on the hemisphere about v
+    return p.Reff * beckmann_vndf_pdf(p, v, wm) + (1.0 - p.Reff) / (2.0 * kPi);
+}
+
+// Slope along the incidence plane for alpha = 1: solve F(x) = u F(a) on (-8, a] with
+//   F(x) = erfc(-x)/2 + exp(-x^2)/(2 a sqrt(pi)),
+// the unnormalized CDF of (1 - x/a)^+ exp(-x^2)/sqrt(pi).
+double sample_slope_x(double a, double u) {
+    const bool fin = !std::isinf(a);
+    auto F = [a, fin](double x) {
+        return 0.5 * std::erfc(-x) + (fin ? std::exp(-x * x) / (2.0 * a * kSqrtPi) : 0.0);
+    };
+    const double Fa = fin ? F(a) : 1.0;
+    const double target = u * Fa;
+    double lo = -8.0, hi = fin ? std::min(a, 8.0) : 8.0;
+    if (target <= F(lo)) return lo;
+    double x = std::min(std::max(0.0, lo), hi);
+    for (int it = 0; it < 200; ++it) {
+        const double fx = F(x) - target;
+        if (fx == 0.0) break;
+        if (fx > 0.0) hi = x; else lo = x;
+        const double fp = std::exp(-x * x) / kSqrtPi * (fin ? (1.0 - x / a) : 1.0);
+        double xn = (fp > 0.0) ? x - fx / fp : 0.5 * (lo + hi);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        const double step = xn - x;
+        x = xn;
+        if (std::fabs(step) <= 1e-15 * std::max(1.0, std::fabs(x))) break;
+        if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(x))) break;
+    }
+    return x;
+}
+
+// Half vector from the selection uniform and two 24-bit uniforms.
+void sample_half_vector(const Proposal& p, const double v[3], double u_sel, uint32_t ua24,
+                        uint32_t ub24, double wm[3]) {
+    const double ua = ua24 * 0x1p-24, ub = ub24 * 0x1p-24;
+    if (u_sel < p.Reff) {
+        const double xs = sample_slope_x(p.a, ua);
+        const double ys = erfinv_d((2.0 * ub24 + 1.0) * 0x1p-24 - 1.0);
+        const double x = p.alpha * xs, y = p.alpha * ys;
+        const double n = std::sqrt(x * x + y * y + 1.0);
+        for (int k = 0; k < 3; ++k) wm[k] = (-x * p.T[k] - y * p.B[k] + p.N[k]) / n;
+    } else {
+        double t[3], b[3];
+        onb(v, t, b);
+        const double ct = 1.0 - ua;
+        const double st = std::sqrt(ua * (2.0 - ua));
+        const double ph = 2.0 * kPi * ub;
+        const double cp = std::cos(ph), sp = std::sin(ph);
+        for (int k = 0; k < 3; ++k) wm[k] = st * cp * t[k] + st * sp * b[k] + ct * v[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Majorant grid: per cell an upper bound of sigma_t = rho * sigma_proj over the cell and
+// all directions, rounded up to 5 significant bits so that independent double
+// evaluations agree exactly.
+//   rho(mu, sigma) = (1/sigma) r(mu/sigma), r = phi/Phi decreasing (Fig. monotonic_density)
+//   sigma_proj <= E[max(0, X)], X ~ N(|G|max, smax^2) = g Phi(g/s) + s phi(g/s)
+// ---------------------------------------------------------------------------
+double r_ratio(double z) { return std::sqrt(2.0 / kPi) / erfcx_d(-z / kSqrt2); }
+
+double quantize_majorant(double B) {
+    if (std::isnan(B)) return INFINITY;
+    const double Bp = B * (1.0 + 0x1p-10);
+    if (!(Bp >= 0x1p-40)) return 0.0;
+    if (std::isinf(Bp)) return INFINITY;
+    int e;
+    const double f = std::frexp(Bp, &e);
+    const double m = std::ceil(f * 32.0);
+    return std::ldexp(m, e - 5);
+}
+
+void node_range(int k, int M, int R, int& lo, int& hi) {
+    lo = (int)(((int64_t)k * (R - 1)) / M);
+    hi = (int)((((int64_t)(k + 1)) * (R - 1) + M - 1) / M);
+    if (lo < 0) lo = 0;
+    if (hi > R - 1) hi = R - 1;
+}
+
+void build_majorants(Scene& S) {
+    const int64_t n = (int64_t)S.M[0] * S.M[1] * S.M[2];
+    S.maj.assign(n, 0.0);
+    double cwv[3];
+    for (int a = 0; a < 3; ++a) cwv[a] = S.ext[a] / S.M[a];
+    const double hdiag = 0.5 * std::sqrt(cwv[0] * cwv[0] + cwv[1] * cwv[1] + cwv[2] * cwv[2]);
+    for (int kz = 0; kz < S.M[2]; ++kz)
+        for (int ky = 0; ky < S.M[1]; ++ky)
+            for (int kx = 0; kx < S.M[0]; ++kx) {
+                const int k[3] = {kx, ky, kz};
+                // offset grid: minimum and gradient bound over the nodes that reach the cell
+                double off_min = 0.0, off_g = 0.0;
+                if (!S.offset.empty()) {
+                    int lo[3], hi[3];
+                    for (int a = 0; a < 3; ++a) node_range(k[a], S.M[a], S.offset.res[a], lo[a], hi[a]);
+                    off_min = INFINITY;
+                    double md[3] = {0, 0, 0};
+                    const int* r = S.offset.res;
+                    for (int z = lo[2]; z <= hi[2]; ++z)
+                        for (int y = lo[1]; y <= hi[1]; ++y)
+                            for (int x = lo[0]; x <= hi[0]; ++x) {
+                                const double v = S.offset.v[((int64_t)z * r[1] + y) * r[0] + x];
+                                off_min = std::min(off_min, v);
+                                if (x < hi[0]) md[0] = std::max(md[0], std::fabs(S.offset.v[((int64_t)z * r[1] + y) * r[0] + x + 1] - v));
+                                if (y < hi[1]) md[1] = std::max(md[1], std::fabs(S.offset.v[((int64_t)z * r[1] + y + 1) * r[0] + x] - v));
+                                if (z < hi[2]) md[2] = std::max(md[2], std::fabs(S.offset.v[((int64_t)(z + 1) * r[1] + y) * r[0] + x] - v));
+                            }
+                    double gs = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        const double g = md[a] / (S.ext[a] / (S.offset.res[a] - 1));
+                        gs += g * g;
+                    }
+                    off_g = std::sqrt(gs);
+                }
+                double vmin = S.variance, vmax = S.variance;
+                if (!S.var.empty()) {
+                    int lo[3], hi[3];
+                    for (int a = 0; a < 3; ++a) node_range(k[a], S.M[a], S.var.res[a], lo[a], hi[a]);
+                    vmin = INFINITY; vmax = -INFINITY;
+                    const int* r = S.var.res;
+                    for (int z = lo[2]; z <= hi[2]; ++z)
+                        for (int y = lo[1]; y <= hi[1]; ++y)
+                            for (int x = lo[0]; x <= hi[0]; ++x) {
+                                const double v = S.var.v[((int64_t)z * r[1] + y) * r[0] + x];
+                                vmin = std::min(vmin, v);
+                                vmax = std::max(vmax, v);
+                            }
+                }
+                double mu_min, gmax;
+                if (S.mean_kind == 0) {
+                    mu_min = S.lo[2] + k[2] * cwv[2];
+                    gmax = 1.0;
+                } else if (S.mean_kind == 2) {
+                    mu_min = S.mean_const;
+                    gmax = 0.0;
+                } else {
+                    double c[3], g[3];
+                    for (int a = 0; a < 3; ++a) c[a] = S.lo[a] + (k[a] + 0.5) * cwv[a];
+                    int which;
+                    mu_min = sdf_union(S, c, g, which) - hdiag;
+                    gmax = 1.0;
+                }
+                mu_min += off_min;
+                gmax += off_g;
+                const double smin_f = std::sqrt(vmin), smax_f = std::sqrt(vmax);
+                const double s_max = smax_f / S.l;
+                const double rho_max = r_ratio(mu_min / (mu_min > 0.0 ? smax_f : smin_f)) / smin_f;
+                const double z = gmax / s_max;
+                const double proj_max = gmax * Phi_d(z) + s_max * phi_d(z);
+                S.maj[((int64_t)kz * S.M[1] + ky) * S.M[0] + kx] = quantize_majorant(rho_max * proj_max);
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Ray / box and majorant-grid traversal.
+// ---------------------------------------------------------------------------
+bool clip_box(const Scene& S, const double o[3], const double d[3], double& t0, double& t1) {
+    t0 = 0.0;
+    t1 = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (o[a] < S.lo[a] || o[a] > S.hi[a]) return false;
+            continue;
+        }
+        double ta = (S.lo[a] - o[a]) / d[a];
+        double tb = (S.hi[a] - o[a]) / d[a];
+        if (ta > tb) std::swap(ta, tb);
+        t0 = std::max(t0, ta);
+        t1 = std::min(t1, tb);
+    }
+    return t0 < t1;
+}
+
+struct Walker {
+    const Scene* S;
+    const double* o;
+    const double* d;
+    int idx[3];
+    void init(double t) {
+        for (int a = 0; a < 3; ++a) {
+            const double p = o[a] + t * d[a];
+            int i = (int)std::floor((p - S->lo[a]) / S->cw[a]);
+            idx[a] = std::min(std::max(i, 0), S->M[a] - 1);
+        }
+    }
+    double majorant() const { return S->maj[((int64_t)idx[2] * S->M[1] + idx[1]) * S->M[0] + idx[0]]; }
+    // distance at which the ray leaves the current cell, and the axis it leaves through
+    double exit(int& ax) const {
+        double best = INFINITY;
+        ax = 0;
+        for (int a = 0; a < 3; ++a) {
+            double tn = INFINITY;
+            if (d[a] > 0.0) tn = (S->lo[a] + (idx[a] + 1) * S->cw[a] - o[a]) / d[a];
+            else if (d[a] < 0.0) tn = (S->lo[a] + idx[a] * S->cw[a] - o[a]) / d[a];
+            if (tn < best) { best = tn; ax = a; }
+        }
+        return best;
+    }
+    bool step(int ax) {
+        idx[ax] += d[ax] > 0.0 ? 1 : -1;
+        return idx[ax] >= 0 && idx[ax] < S->M[ax];
+    }
+};
+
+constexpr int64_t kStepCap = 1 << 16;
+constexpr double kTrCutoff = 0x1p-40;
+
+template <class T>
+T sigma_t_of(const PointQ<T>& q, const double d[3]) { return rho_of(q.mu, q.sigma) * sigma_proj(q, d); }
+
+enum TrackResult { kEscape = 0, kCollide = 1, kAbsorbed = 2 };
+
+// Delta tracking (null-scattering, Sec. 5) of one segment [t0, t1] through the majorant
+// grid.  Per tentative collision: optical depth tau = -ln(1 - u1) consumed cell by cell,
+// then real iff u2 * majorant < sigma_t.  With `frozen`, decisions use P0 and the
+// returned factor wfac carries the weight ratio of P1 to P0 (null: (m - st1)/(m - st0),
+// real: st1/st0).
+template <class T>
+int delta_track(const Params<double>& P0, const Params<T>& P1, bool frozen, const double o[3],
+                const double d[3], double t0, double t1, Rng& rng, double& t_hit, T& wfac,
+                Counters& C) {
+    Walker w{P0.S, o, d, {0, 0, 0}};
+    w.init(t0);
+    double t = t0;
+    double tau = -std::log(1.0 - rng.uniform());
+    int64_t steps = 0;
+    C.c[ORC_C_CELLS]++;
+    for (;;) {
+        int ax;
+        const double tn = w.exit(ax);
+        const double tc = std::min(tn, t1);
+        const double maj = w.majorant();
+        const double seg = std::max(0.0, tc - t);
+        if (maj > 0.0 && tau < maj * seg) {
+            t += tau / maj;
+            const double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+            C.c[ORC_C_TRACK_STEPS]++;
+            if (++steps > kStepCap) { C.c[ORC_C_CAPPED]++; return kAbsorbed; }
+            const double u2 = rng.uniform();
+            const PointQ<double> q0 = eval_point(P0, x);
+            const double st0 = sigma_t_of(q0, d);
+            if (st0 > maj) C.c[ORC_C_VIOLATIONS]++;
+            if (u2 * maj < st0) {
+                if (frozen) {
+                    const PointQ<T> q1 = eval_point(P1, x);
+                    wfac = wfac * (sigma_t_of(q1, d) / st0);
+                }
+                t_hit = t;
+                return kCollide;
+            }
+            if (frozen) {
+                const PointQ<T> q1 = eval_point(P1, x);
+                wfac = wfac * ((maj - sigma_t_of(q1, d)) / (maj - st0));
+            }
+            tau = -std::log(1.0 - rng.uniform());
+            continue;
+        }
+        if (maj > 0.0) tau -= maj * seg;
+        t = tc;
+        if (tn >= t1) return kEscape;
+        if (!w.step(ax)) return kEscape;
+        C.c[ORC_C_CELLS]++;
+    }
+}
+
+// Ratio tracking transmittance along [0, t1]: product of (1 - sigma_t / majorant) over
+// tentative collisions, one uniform each; stops at 0 once below kTrCutoff.
+template <class T>
+T ratio_track(const Params<double>& P0, const Params<T>& P1, bool frozen, const double o[3],
+              const double d[3], double t1, Rng& rng, Counters& C) {
+    Walker w{P0.S, o, d, {0, 0, 0}};
+    w.init(0.0);
+    double t = 0.0;
+    double Tr0 = 1.0;
+    T Tr1 = T(1.0);
+    double tau = -std::log(1.0 - rng.uniform());
+    int64_t steps = 0;
+    for (;;) {
+        int ax;
+        const double tn = w.exit(ax);
+        const double tc = std::min(tn, t1);
+        const double maj = w.majorant();
+        const double seg = std::max(0.0, tc - t);
+        if (maj > 0.0 && tau < maj * seg) {
+            t += tau / maj;
+            const double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+            C.c[ORC_C_NEE_STEPS]++;
+            if (++steps > kStepCap) { C.c[ORC_C_CAPPED]++; return T(0.0); }
+            const PointQ<double> q0 = eval_point(P0, x);
+            const double st0 = sigma_t_of(q0, d);
+            if (st0 > maj) C.c[ORC_C_VIOLATIONS]++;
+            Tr0 *= (1.0 - st0 / maj);
+            if (frozen) {
+                const PointQ<T> q1 = eval_point(P1, x);
+                Tr1 = Tr1 * (1.0 - sigma_t_of(q1, d) / maj);
+            }
+            if (Tr0 < kTrCutoff) return T(0.0);
+            tau = -std::log(1.0 - rng.uniform());
+            continue;
+        }
+        if (maj > 0.0) tau -= maj * seg;
+        t = tc;
+        if (tn >= t1) break;
+        if (!w.step(ax)) break;
+    }
+    if (frozen) return Tr1;
+    return T(Tr0);
+}
+
+void camera_ray(const Scene& S, uint32_t pixel, double ux, double uy, double o[3], double d[3]) {
+    const int i = (int)(pixel % (uint32_t)S.W), j = (int)(pixel / (uint32_t)S.W);
+    if (S.cam_kind == 0) {
+        const double px = ((i + ux) / S.W - 0.5) * S.win[0];
+        const double py = (0.5 - (j + uy) / S.H) * S.win[1];
+        for (int k = 0; k < 3; ++k) {
+            o[k] = S.eye[k] + px * S.right[k] + py * S.upc[k];
+            d[k] = S.fwd[k];
+        }
+    } else {
+        const double px = (2.0 * (i + ux) / S.W - 1.0) * S.tan_half * S.aspect;
+        const double py = (1.0 - 2.0 * (j + uy) / S.H) * S.tan_half;
+        for (int k = 0; k < 3; ++k) {
+            o[k] = S.eye[k];
+            d[k] = S.fwd[k] + px * S.right[k] + py * S.upc[k];
+        }
+        normalize3(d);
+    }
+}
+
+// Conductor phase function (Eqs. phase and microfacet_vndf) with F = albedo, for travel
+// direction d and scattered direction wi: albedo * D(wm) / (4 sigma_proj(d)), wm the half
+// vector of v = -d and wi.
+template <class T>
+T phase_eval(const PointQ<T>& q, const double d[3], const double wi[3]) {
+    double h[3] = {wi[0] - d[0], wi[1] - d[1], wi[2] - d[2]};
+    const double hn = std::sqrt(dot3(h, h));
+    if (hn < 1e-7) return T(0.0);
+    h[0] /= hn; h[1] /= hn; h[2] /= hn;
+    return q.albedo * ndf(q, h) / (4.0 * sigma_proj(q, d));
+}
+
+// One light path; returns its radiance estimate.
+template <class T>
+T trace_path(const Params<double>& P0, const Params<T>& P1, bool frozen, uint32_t pixel,
+             uint32_t sample, Counters& C, double& trunc_beta) {
+    const Scene& S = *P0.S;
+    Rng rc(S.key, pixel, sample, 0, kCam);
+    const double ux = rc.uniform(), uy = rc.uniform();
+    double o[3], d[3];
+    camera_ray(S, pixel, ux, uy, o, d);
+    T beta = T(1.0), L = T(0.0);
+    int b = 0;
+    for (;;) {
+        double t0, t1;
+        if (!clip_box(S, o, d, t0, t1)) {
+            L = L + beta * S.env;
+            C.c[ORC_C_ESCAPED]++;
+            break;
+        }
+        Rng rt(S.key, pixel, sample, (uint32_t)b, kTrack);
+        double th = 0.0;
+        T wfac = T(1.0);
+        const int res = delta_track(P0, P1, frozen, o, d, t0, t1, rt, th, wfac, C);
+        if (frozen) beta = beta * wfac;
+        if (res == kAbsorbed) break;
+        if (res == kEscape) {
+            L = L + beta * S.env;
+            C.c[ORC_C_ESCAPED]++;
+            break;
+        }
+        C.c[ORC_C_REAL]++;
+        b += 1;
+        if (b > S.max_depth) {
+            trunc_beta += val(beta);
+            C.c[ORC_C_TRUNCATED]++;
+            break;
+        }
+        const double x[3] = {o[0] + th * d[0], o[1] + th * d[1], o[2] + th * d[2]};
+        const PointQ<double> q0 = eval_point(P0, x);
+        PointQ<T> q1;
+        if (frozen) q1 = eval_point(P1, x);
+        // next-event estimation to each delta light (directional = stream kNee0, point = kNee0+1)
+        for (int li = 0; li < 2; ++li) {
+            double wl[3], tend, Le;
+            if (li == 0) {
+                if (!(S.dl[3] > 0.0)) continue;
+                wl[0] = S.dl[0]; wl[1] = S.dl[1]; wl[2] = S.dl[2];
+                double a0, a1;
+                if (!clip_box(S, x, wl, a0, a1)) a1 = 0.0;
+                tend = a1;
+                Le = S.dl[3];
+            } else {
+                if (!(S.pl[3] > 0.0)) continue;
+                double dv[3] = {S.pl[0] - x[0], S.pl[1] - x[1], S.pl[2] - x[2]};
+                const double r = std::sqrt(dot3(dv, dv));
+                wl[0] = dv[0] / r; wl[1] = dv[1] / r; wl[2] = dv[2] / r;
+                double a0, a1;
+                if (!clip_box(S, x, wl, a0, a1)) a1 = 0.0;
+                tend = std::min(a1, r);
+                Le = S.pl[3] / (r * r);
+            }
+            C.c[ORC_C_NEE]++;
+            T p;
+            if (frozen) p = phase_eval(q1, d, wl);
+            else p = T(phase_eval(q0, d, wl));
+            Rng rn(S.key, pixel, sample, (uint32_t)b, kNee0 + (uint32_t)li);
+            const T Tr = ratio_track(P0, P1, frozen, x, wl, tend, rn, C);
+            L = L + beta * p * Tr * Le;
+        }
+        // phase sampling
+        const double v[3] = {-d[0], -d[1], -d[2]};
+        const Proposal prop = make_proposal(q0, S.R, v);
+        Rng rp(S.key, pixel, sample, (uint32_t)b, kPhase);
+        const double usel = rp.uniform();
+        const uint32_t ua = rp.next24(), ub = rp.next24();
+        double wm[3];
+        sample_half_vector(prop, v, usel, ua, ub, wm);
+        const double pdf = mixture_pdf(prop, v, wm);
+        const double vm = dot3(v, wm);
+        double wi[3] = {2.0 * vm * wm[0] - v[0], 2.0 * vm * wm[1] - v[1], 2.0 * vm * wm[2] - v[2]};
+        normalize3(wi);
+        C.c[ORC_C_PHASE]++;
+        // beta *= albedo * D_{w_o}(wm) / pdf, D_{w_o}(wm) = <v, wm> D(wm) / sigma_proj(d)
+        if (frozen) beta = beta * (q1.albedo * vm * ndf(q1, wm) / (sigma_proj(q1, d) * pdf));
+        else beta = beta * T(q0.albedo * vm * ndf(q0, wm) / (sigma_proj(q0, d) * pdf));
+        for (int k = 0; k < 3; ++k) { o[k] = x[k]; d[k] = wi[k]; }
+    }
+    return L;
+}
+
+Params<double> plain_params(const Scene* S) {
+    Params<double> P;
+    P.S = S;
+    return P;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface
+// ===========================================================================
+extern "C" {
+
+int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
+    if (!D || !out) return -1;
+    if (D->width <= 0 || D->height <= 0 || D->spp <= 0 || D->max_depth < 0) return -1;
+    if (!(D->lengthscale > 0.0) || !(D->albedo >= 0.0 && D->albedo <= 1.0)) return -1;
+    if (!D->var_grid && !(D->variance > 0.0)) return -1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(D->bounds[3 + a] > D->bounds[a])) return -1;
+        if (D->maj_res[a] <= 0) return -1;
+        if (D->offset && D->off_res[a] < 2) return -1;
+        if (D->var_grid && D->var_res[a] < 2) return -1;
+    }
+    if (D->mean_kind == 1 && (D->n_prims <= 0 || !D->prims)) return -1;
+    auto* S = new oracle_scene();
+    S->mean_kind = D->mean_kind;
+    S->mean_const = D->mean_const;
+    for (int i = 0; i < (D->mean_kind == 1 ? D->n_prims : 0); ++i) {
+        const float* p = D->prims + 8 * i;
+        Prim q;
+        q.kind = (int)p[0];
+        for (int a = 0; a < 3; ++a) { q.c[a] = p[1 + a]; q.h[a] = p[4 + a]; }
+        q.albedo = p[7];
+        S->prims.push_back(q);
+    }
+    auto load = [](Grid& g, const float* src, const int32_t* res) {
+        if (!src) return;
+        for (int a = 0; a < 3; ++a) g.res[a] = res[a];
+        const int64_t n = (int64_t)res[0] * res[1] * res[2];
+        g.v.assign(src, src + n);
+    };
+    load(S->offset, D->offset, D->off_res);
+    load(S->var, D->var_grid, D->var_res);
+    S->variance = D->variance;
+    S->l = D->lengthscale;
+    S->albedo = D->albedo;
+    S->albedo_per_prim = D->albedo_per_prim != 0;
+    for (int a = 0; a < 3; ++a) {
+        S->lo[a] = D->bounds[a];
+        S->hi[a] = D->bounds[3 + a];
+        S->ext[a] = S->hi[a] - S->lo[a];
+        S->M[a] = D->maj_res[a];
+        S->cw[a] = S->ext[a] / S->M[a];
+    }
+    S->R = D->mix_R;
+    for (int k = 0; k < 4; ++k) { S->dl[k] = D->dir_light[k]; S->pl[k] = D->point_light[k]; }
+    S->env = D->env;
+    S->cam_kind = D->cam_kind;
+    for (int k = 0; k < 3; ++k) { S->eye[k] = D->eye[k]; S->fwd[k] = D->target[k] - D->eye[k]; }
+    normalize3(S->fwd);
+    cross3(S->fwd, D->up, S->right);
+    normalize3(S->right);
+    cross3(S->right, S->fwd, S->upc);
+    S->tan_half = std::tan(0.5 * D->fov_deg * kPi / 180.0);
+    S->aspect = (double)D->width / D->height;
+    S->win[0] = D->window[0];
+    S->win[1] = D->window[1];
+    S->W = D->width; S->H = D->height; S->spp = D->spp; S->max_depth = D->max_depth;
+    S->key[0] = (uint32_t)(D->seed & 0xFFFFFFFFu);
+    S->key[1] = (uint32_t)(D->seed >> 32) ^ D->scene_id;
+    build_majorants(*S);
+    *out = S;
+    return 0;
+}
+
+void oracle_scene_destroy(oracle_scene* s) { delete s; }
+
+int oracle_majorants(const oracle_scene* s, float* out, int64_t n) {
+    if (!s || !out || n != (int64_t)s->maj.size()) return -1;
+    for (int64_t i = 0; i < n; ++i) out[i] = (float)s->maj[i];
+    return 0;
+}
+
+static int render_impl(const oracle_scene* s_dec, const oracle_scene* s_w, bool frozen, int32_t s0,
+                       int32_t s1, double* mean, double* var, double* paths, double* trunc,
+                       int64_t* counters, int32_t nthreads) {
+    if (!s_dec || !s_w || s1 <= s0 || s0 < 0 || !mean) return -1;
+    const int64_t npix = (int64_t)s_dec->W * s_dec->H;
+    const int ns = s1 - s0;
+    Counters total;
+    const Params<double> P0 = plain_params(s_dec);
+    const Params<double> P1 = plain_params(s_w);
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+    {
+        Counters C;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < npix; ++p) {
+            double sum = 0.0, sq = 0.0, tb = 0.0;
+            for (int sidx = s0; sidx < s1; ++sidx) {
+                const double L = trace_path<double>(P0, P1, frozen, (uint32_t)p, (uint32_t)sidx, C, tb);
+                sum += L;
+                sq += L * L;
+                if (paths) paths[p * ns + (sidx - s0)] = L;
+            }
+            mean[p] = sum / ns;
+            if (var) var[p] = ns > 1 ? std::max(0.0, (sq - sum * sum / ns) / (ns - 1)) : 0.0;
+            if (trunc) trunc[p] = tb / ns;
+        }
+#pragma omp critical
+        total.add(C);
+    }
+    if (counters) for (int i = 0; i < ORC_C_COUNT; ++i) counters[i] = total.c[i];
+    return 0;
+}
+
+int oracle_render(const oracle_scene* s, int32_t s0, int32_t s1, double* mean, double* var,
+                  double* paths, double* trunc_beta, int64_t* counters, int32_t nthreads) {
+    return render_impl(s, s, false, s0, s1, mean, var, paths, trunc_beta, counters, nthreads);
+}
+
+int oracle_render_frozen(const oracle_scene* s_dec, const oracle_scene* s_w, int32_t s0,
+                         int32_t s1, double* mean, int64_t* counters, int32_t nthreads) {
+    if (!s_dec || !s_w || s_dec->W != s_w->W || s_dec->H != s_w->H) return -1;
+    return render_impl(s_dec, s_w, true, s0, s1, mean, nullptr, nullptr, nullptr, counters, nthreads);
+}
+
+int oracle_render_grad(const oracle_scene* s, int32_t s0, int32_t s1, const double* dloss,
+                       int32_t n_params, const int64_t* param_ids, double* grad, double* mean,
+                       int32_t nthreads) {
+    if (!s || !dloss || !grad || n_params < 0 || n_params > Dual::N || s1 <= s0 || s0 < 0) return -1;
+    std::unordered_map<int64_t, int> slots;
+    Params<Dual> P1;
+    P1.S = s;
+    for (int j = 0; j < n_params; ++j) {
+        const int64_t id = param_ids[j];
+        if (id >= 0) {
+            if (s->offset.empty() || id >= (int64_t)s->offset.v.size()) return -1;
+            slots[id] = j;
+        } else if (id == -1) P1.slot_var = j;
+        else if (id == -2) P1.slot_l = j;
+        else if (id == -3) P1.slot_alb = j;
+        else return -1;
+    }
+    P1.node_slot = &slots;
+    const Params<double> P0 = plain_params(s);
+    const int64_t npix = (int64_t)s->W * s->H;
+    const int ns = s1 - s0;
+    std::vector<double> g(n_params, 0.0);
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+    {
+        std::vector<double> gl(n_params, 0.0);
+        Counters C;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < npix; ++p) {
+            double tb = 0.0, sum = 0.0;
+            Dual acc(0.0);
+            for (int sidx = s0; sidx < s1; ++sidx) {
+                const Dual L = trace_path<Dual>(P0, P1, true, (uint32_t)p, (uint32_t)sidx, C, tb);
+                acc = acc + L;
+                sum += L.v;
+            }
+            if (mean) mean[p] = sum / ns;
+            for (int j = 0; j < n_params; ++j) gl[j] += dloss[p] * acc.d[j] / ns;
+        }
+#pragma omp critical
+        for (int j = 0; j < n_params; ++j) g[j] += gl[j];
+    }
+    for (int j = 0; j < n_params; ++j) grad[j] = g[j];
+    return 0;
+}
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    philox4x32_10(ctr, key, out);
+}
+
+void oracle_uniforms(uint64_t seed, uint32_t scene_id, uint32_t pixel, uint32_t sample,
+                     uint32_t bounce, uint32_t stream, int32_t n, double* out) {
+    const uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32) ^ scene_id};
+    Rng r(key, pixel, sample, bounce, stream);
+    for (int i = 0; i < n; ++i) out[i] = r.uniform();
+}
+
+double oracle_erfcx(double x) { return erfcx_d(x); }
+double oracle_erfinv(double y) { return erfinv_d(y); }
+double oracle_rho(double mu, double sigma) { return rho_of(mu, sigma); }
+
+static PointQ<double> point_from(const double G[3], double s, double albedo) {
+    PointQ<double> q;
+    q.mu = 0.0;
+    for (int a = 0; a < 3; ++a) q.G[a] = G[a];
+    q.sigma = 0.0;
+    q.s = s;
+    q.albedo = albedo;
+    return q;
+}
+
+double oracle_sigma_proj(const double G[3], double s, const double d[3]) {
+    return sigma_proj(point_from(G, s, 1.0), d);
+}
+double oracle_ndf(const double G[3], double s, const double wm[3]) { return ndf(point_from(G, s, 1.0), wm); }
+double oracle_beckmann_ndf(double alpha, double cos_m) {
+    return beckmann_D(alpha, cos_m, std::max(0.0, 1.0 - cos_m * cos_m));
+}
+double oracle_beckmann_lambda(double a) { return beckmann_lambda(a); }
+double oracle_ndf_aniso(double ax, double ay, double az, const double wm[3]) {
+    return ndf_general<double>(ax, ay, az, wm[2], wm[0] * wm[0], wm[1] * wm[1]);
+}
+double oracle_lambda_aniso(double ax, double ay, double az, const double w[3]) {
+    return lambda_cos_general<double>(ax, ay, az, w[2], w[0] * w[0], w[1] * w[1]) / w[2];
+}
+double oracle_phase_eval(const double G[3], double s, double albedo, const double d[3], const double wi[3]) {
+    return phase_eval(point_from(G, s, albedo), d, wi);
+}
+double oracle_mixture_pdf(const double G[3], double s, double R, const double d[3], const double wm[3]) {
+    const double v[3] = {-d[0], -d[1], -d[2]};
+    const Proposal p = make_proposal(point_from(G, s, 1.0), R, v);
+    return mixture_pdf(p, v, wm);
+}
+int oracle_phase_sample(const double G[3], double s, double albedo, double R, const double d[3],
+                        const double u[3], double* wi, double* wm, double* weight, double* pdf) {
+    const PointQ<double> q = point_from(G, s, albedo);
+    const double v[3] = {-d[0], -d[1], -d[2]};
+    const Proposal p = make_proposal(q, R, v);
+    const uint32_t ua = (uint32_t)(u[1] * 0x1p24), ub = (uint32_t)(u[2] * 0x1p24);
+    sample_half_vector(p, v, u[0], ua, ub, wm);
+    *pdf = mixture_pdf(p, v, wm);
+    const double vm = dot3(v, wm);
+    for (int k = 0; k < 3; ++k) wi[k] = 2.0 * vm * wm[k] - v[k];
+    normalize3(wi);
+    *weight = albedo * vm * ndf(q, wm) / (sigma_proj(q, d) * *pdf);
+    return 0;
+}
+
+int oracle_eval_point(const oracle_scene* sc, const double x[3], double out[7]) {
+    if (!sc) return -1;
+    const PointQ<double> q = eval_point(plain_params(sc), x);
+    out[0] = q.mu; out[1] = q.G[0]; out[2] = q.G[1]; out[3] = q.G[2];
+    out[4] = q.sigma; out[5] = q.s; out[6] = q.albedo;
+    return 0;
+}
+
+double oracle_sigma_t(const oracle_scene* sc, const double x[3], const double d[3]) {
+    return sigma_t_of(eval_point(plain_params(sc), x), d);
+}
+
+int oracle_ratio_tracking(const oracle_scene* sc, const double o[3], const double d[3],
+                          double tmax, int32_t n, double* out_T) {
+    if (!sc || !out_T || n < 0) return -1;
+    const Params<double> P = plain_params(sc);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        Counters C;
+        Rng r(sc->key, (uint32_t)i, 0, 0, kNee0);
+        out_T[i] = ratio_track<double>(P, P, false, o, d, tmax, r, C);
+    }
+    return 0;
+}
+
+int oracle_free_flight(const oracle_scene* sc, const double o[3], const double d[3], double tmax,
+                       int32_t n, double* out_t) {
+    const Params<double> P = plain_params(sc);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        Counters C;
+        Rng r(sc->key, (uint32_t)i, 0, 0, kTrack);
+        double th = 0.0, wf = 1.0;
+        const int res = delta_track<double>(P, P, false, o, d, 0.0, tmax, r, th, wf, C);
+        out_t[i] = res == kCollide ? th : INFINITY;
+    }
+    return 0;
+}
+
+}  // extern "C"
