@@ -1,0 +1,138 @@
+/* gpss: MI355X (gfx950) renderer for Gaussian process statistical surfaces (GPSSes)
+ * under macrofacet theory.
+ *
+ * A GPSS is a Gaussian process f ~ GP(mu, kappa) with a squared-exponential kernel
+ * (Sec. 3.1, Eq. se_kernel) whose zero level set is the surface.  Macrofacet theory
+ * renders it, without realizations, as a classic exponential participating medium with
+ *   extinction  sigma_t(x, w) = rho(x) sigma(w),
+ *               rho = phi(mu; 0, s^2) / Phi(mu; 0, s^2)            (Sec. 4.2.1, Eq. generalized_sigma_t)
+ *               sigma(w) = Lambda(w) cos(theta)                    (Eq. generalized_lambda)
+ *   phase       p(w_o, w_i) = F D_{w_o}(w_m) / (4 |w_o . w_m|)     (Sec. 3.2, Eqs. phase, microfacet_vndf)
+ *               with the generalized NDF D of Sec. 4.2.2 (Eq. macro_ndf) and F = albedo,
+ * and is rendered by null-scattering volumetric path tracing (Sec. 5).
+ *
+ * Conventions used by every entry point
+ *   - All calls return GPSS_OK (0) or a negative GPSS_ERR_* code; gpss_last_error() gives a
+ *     thread-local message for the last failure on the calling thread.  Invalid arguments
+ *     are rejected before any device work is enqueued.  No C++ exception crosses the ABI.
+ *   - "host" pointers are read during the call only; "device" pointers are device memory
+ *     owned by the caller, which must stay valid until the enqueued work completes.
+ *   - Rendering calls are asynchronous and ordered on the given HIP stream (NULL = the
+ *     default stream); the caller synchronizes.  A scene must not be used by two
+ *     overlapping calls at once (it owns per-scene scratch memory).
+ *   - Random numbers: Philox4x32-10 with key (seed_lo32, seed_hi32 ^ scene_id) and counter
+ *     (pixel, sample, bounce | stream << 16, block); results are a deterministic function
+ *     of the scene and the sample range.
+ */
+#ifndef GPSS_H
+#define GPSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gpss_scene* gpss_scene_t;
+typedef struct ihipStream_t* gpss_stream_t; /* hipStream_t */
+
+enum {
+    GPSS_OK = 0,
+    GPSS_ERR_INVALID_ARG = -1,
+    GPSS_ERR_HIP = -2,
+    GPSS_ERR_OOM = -3,
+    GPSS_ERR_UNSUPPORTED = -4
+};
+
+enum { GPSS_MEAN_PLANE = 0, GPSS_MEAN_SDF = 1, GPSS_MEAN_CONST = 2 };
+enum { GPSS_PRIM_SPHERE = 0, GPSS_PRIM_BOX = 1 };
+enum { GPSS_CAM_ORTHO = 0, GPSS_CAM_PINHOLE = 1 };
+
+/* Statement of one rendering problem (all host memory, copied by gpss_scene_create).
+ * Grids are float32, x fastest, node-centred over `bounds` (node i at lo + i/(res-1)*ext). */
+typedef struct {
+    uint32_t struct_size;          /* sizeof(gpss_scene_desc): ABI version check */
+    /* GP mean mu(x) (Sec. 3.1) */
+    int32_t mean_kind;             /* GPSS_MEAN_*: plane mu = z, union of SDF primitives, constant */
+    float mean_const;              /* value of the constant mean */
+    const float* prims;            /* n_prims x 8: kind, cx, cy, cz, a (radius | half x), b, c, albedo */
+    uint32_t n_prims;              /* 1..64 for GPSS_MEAN_SDF */
+    const float* mean_offset;      /* nullable: trilinear offset grid added to mu */
+    uint32_t off_res[3];
+    /* squared-exponential kernel (Eq. se_kernel, isotropic) */
+    float variance;                /* sigma^2 > 0, used when variance_grid is NULL */
+    const float* variance_grid;    /* nullable: trilinear grid of sigma^2 (locally stationary) */
+    uint32_t var_res[3];
+    float lengthscale;             /* l > 0; gradient std is sigma / l (Eq. roughness) */
+    /* medium */
+    float albedo;                  /* F of the conductor phase function, in [0, 1] */
+    int32_t albedo_per_prim;       /* nonzero: albedo of the primitive with the smallest SDF */
+    float bounds[6];               /* support box lo xyz, hi xyz */
+    float mix_R;                   /* probability of the Beckmann visible-normal proposal */
+    uint32_t majorant_res[3];      /* majorant grid cells per axis (1..256) */
+    /* lights */
+    float dir_light[4];            /* unit direction toward the light, irradiance E (0 = none) */
+    float point_light[4];          /* position, intensity I (0 = none) */
+    float env_radiance;            /* constant environment radiance (escaped paths) */
+    /* camera */
+    int32_t cam_kind;              /* GPSS_CAM_* */
+    float cam_eye[3], cam_target[3], cam_up[3];
+    float cam_fov_deg;             /* pinhole vertical field of view, degrees */
+    float cam_window[2];           /* orthographic window width, height */
+    /* sampler */
+    uint32_t width, height;        /* pixels; row 0 at the top */
+    uint32_t spp;                  /* samples per pixel of a full render */
+    uint32_t max_depth;            /* maximum number of real scattering events per path */
+    uint64_t seed;
+    uint32_t scene_id;
+} gpss_scene_desc;
+
+/* Create a scene: validates `desc`, uploads primitives and grids, and builds the
+ * conservative majorant grid on the device (double precision, rounded up to five
+ * significant bits).  Synchronous.  *out receives the handle. */
+int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out);
+int gpss_scene_destroy(gpss_scene_t scene);
+
+/* Copy the majorant grid (majorant_res[0]*[1]*[2] floats, x fastest) to host memory `out`
+ * of capacity n floats.  Synchronous. */
+int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n);
+
+/* Forward render (Sec. 5, null-scattering path tracing) of samples [s0, s1) of every
+ * pixel into image_dev (device, width*height floats, overwritten with the mean radiance
+ * over those samples).  0 <= s0 < s1. */
+int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1,
+                gpss_stream_t stream);
+
+/* As gpss_render but writes the per-path radiance to paths_dev (device,
+ * width*height*(s1-s0) floats, pixel-major, then sample).  counters_dev (device, nullable)
+ * receives GPSS_NCOUNTERS uint64 event counts added to its current contents. */
+enum {
+    GPSS_CNT_TRACK_STEPS = 0, GPSS_CNT_REAL = 1, GPSS_CNT_NEE_STEPS = 2,
+    GPSS_CNT_VIOLATIONS = 3, GPSS_CNT_CAPPED = 4, GPSS_CNT_ESCAPED = 5,
+    GPSS_CNT_TRUNCATED = 6, GPSS_CNT_CELLS = 7, GPSS_CNT_PHASE = 8, GPSS_CNT_NEE = 9,
+    GPSS_NCOUNTERS = 16
+};
+int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_dev,
+                      uint32_t s0, uint32_t s1, gpss_stream_t stream);
+
+/* Evaluate the medium at n points for n directions (diagnostics and tests).
+ * points_dev, dirs_dev: device, n x 3 floats.  out_dev: device, n x 8 floats:
+ * mu, sigma (std), s = sigma/l, rho, sigma_proj(dir), sigma_t, ndf(dir as normal), albedo. */
+int gpss_eval_medium(gpss_scene_t scene, const float* points_dev, const float* dirs_dev,
+                     float* out_dev, uint64_t n, gpss_stream_t stream);
+
+/* Trace n listed paths (diagnostics).  ids_dev: device, n x 2 uint32 (pixel, sample).
+ * out_dev: device, n x (kmax * 16 + 1) floats; per real collision k < kmax, 16 floats:
+ * position xyz, distance along the segment, tentative collisions of the segment,
+ * (phase value, transmittance) for the directional then the point light, sampled half
+ * vector xyz, its mixture pdf, the throughput weight, throughput after the vertex and
+ * radiance after its next-event estimates; the last float is the path radiance. */
+int gpss_debug_trace(gpss_scene_t scene, const uint32_t* ids_dev, uint32_t n, float* out_dev,
+                     uint32_t kmax, gpss_stream_t stream);
+
+const char* gpss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPSS_H */

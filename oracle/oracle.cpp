@@ -707,9 +707,14 @@ T phase_eval(const PointQ<T>& q, const double d[3], const double wi[3]) {
 }
 
 // One light path; returns its radiance estimate.
+// With rec != nullptr, vertex k < kmax writes 16 values to rec[16 k ...]: position,
+// distance along the segment, tentative collisions of the segment, (phase, Tr) per light,
+// half vector, mixture pdf, throughput weight, throughput after the vertex, radiance after
+// its next-event estimates.
 template <class T>
 T trace_path(const Params<double>& P0, const Params<T>& P1, bool frozen, uint32_t pixel,
-             uint32_t sample, Counters& C, double& trunc_beta) {
+             uint32_t sample, Counters& C, double& trunc_beta, double* rec = nullptr,
+             int kmax = 0) {
     const Scene& S = *P0.S;
     Rng rc(S.key, pixel, sample, 0, kCam);
     const double ux = rc.uniform(), uy = rc.uniform();
@@ -727,7 +732,9 @@ T trace_path(const Params<double>& P0, const Params<T>& P1, bool frozen, uint32_
         Rng rt(S.key, pixel, sample, (uint32_t)b, kTrack);
         double th = 0.0;
         T wfac = T(1.0);
+        const int64_t steps_before = C.c[ORC_C_TRACK_STEPS];
         const int res = delta_track(P0, P1, frozen, o, d, t0, t1, rt, th, wfac, C);
+        double* r = (rec && b < kmax) ? rec + 16 * b : nullptr;
         if (frozen) beta = beta * wfac;
         if (res == kAbsorbed) break;
         if (res == kEscape) {
@@ -746,6 +753,10 @@ T trace_path(const Params<double>& P0, const Params<T>& P1, bool frozen, uint32_
         const PointQ<double> q0 = eval_point(P0, x);
         PointQ<T> q1;
         if (frozen) q1 = eval_point(P1, x);
+        if (r) {
+            r[0] = x[0]; r[1] = x[1]; r[2] = x[2]; r[3] = th;
+            r[4] = (double)(C.c[ORC_C_TRACK_STEPS] - steps_before);
+        }
         // next-event estimation to each delta light (directional = stream kNee0, point = kNee0+1)
         for (int li = 0; li < 2; ++li) {
             double wl[3], tend, Le;
@@ -773,6 +784,7 @@ T trace_path(const Params<double>& P0, const Params<T>& P1, bool frozen, uint32_
             Rng rn(S.key, pixel, sample, (uint32_t)b, kNee0 + (uint32_t)li);
             const T Tr = ratio_track(P0, P1, frozen, x, wl, tend, rn, C);
             L = L + beta * p * Tr * Le;
+            if (r) { r[5 + 2 * li] = val(p); r[6 + 2 * li] = val(Tr); }
         }
         // phase sampling
         const double v[3] = {-d[0], -d[1], -d[2]};
@@ -784,12 +796,19 @@ T trace_path(const Params<double>& P0, const Params<T>& P1, bool frozen, uint32_
         sample_half_vector(prop, v, usel, ua, ub, wm);
         const double pdf = mixture_pdf(prop, v, wm);
         const double vm = dot3(v, wm);
+        C.c[ORC_C_PHASE]++;
+        if (!(pdf > 0.0) || !(vm > 0.0)) break;  // degenerate sample: the path ends
         double wi[3] = {2.0 * vm * wm[0] - v[0], 2.0 * vm * wm[1] - v[1], 2.0 * vm * wm[2] - v[2]};
         normalize3(wi);
-        C.c[ORC_C_PHASE]++;
         // beta *= albedo * D_{w_o}(wm) / pdf, D_{w_o}(wm) = <v, wm> D(wm) / sigma_proj(d)
-        if (frozen) beta = beta * (q1.albedo * vm * ndf(q1, wm) / (sigma_proj(q1, d) * pdf));
-        else beta = beta * T(q0.albedo * vm * ndf(q0, wm) / (sigma_proj(q0, d) * pdf));
+        T wgt;
+        if (frozen) wgt = q1.albedo * vm * ndf(q1, wm) / (sigma_proj(q1, d) * pdf);
+        else wgt = T(q0.albedo * vm * ndf(q0, wm) / (sigma_proj(q0, d) * pdf));
+        beta = beta * wgt;
+        if (r) {
+            r[9] = wm[0]; r[10] = wm[1]; r[11] = wm[2]; r[12] = pdf; r[13] = val(wgt);
+            r[14] = val(beta); r[15] = val(L);
+        }
         for (int k = 0; k < 3; ++k) { o[k] = x[k]; d[k] = wi[k]; }
     }
     return L;
@@ -966,6 +985,17 @@ int oracle_render_grad(const oracle_scene* s, int32_t s0, int32_t s1, const doub
         for (int j = 0; j < n_params; ++j) g[j] += gl[j];
     }
     for (int j = 0; j < n_params; ++j) grad[j] = g[j];
+    return 0;
+}
+
+int oracle_debug_trace(const oracle_scene* s, uint32_t pixel, uint32_t sample, int32_t kmax,
+                       double* out) {
+    if (!s || !out || kmax < 1) return -1;
+    for (int k = 0; k < 16 * kmax + 1; ++k) out[k] = 0.0;
+    Counters C;
+    double tb = 0.0;
+    const Params<double> P = plain_params(s);
+    out[16 * kmax] = trace_path<double>(P, P, false, pixel, sample, C, tb, out, kmax);
     return 0;
 }
 

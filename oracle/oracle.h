@@ -103,6 +103,11 @@ int oracle_render_grad(const oracle_scene* s, int32_t s0, int32_t s1, const doub
                        int32_t n_params, const int64_t* param_ids, double* grad,
                        double* mean, int32_t nthreads);
 
+/* Per-vertex record of one path (16 doubles per real collision k < kmax, then the path
+ * radiance at out[16 kmax]); same fields as the GPU library's debug trace. */
+int oracle_debug_trace(const oracle_scene* s, uint32_t pixel, uint32_t sample, int32_t kmax,
+                       double* out);
+
 /* ---- point functions (used by the closed-form pins) ---- */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void oracle_uniforms(uint64_t seed, uint32_t scene_id, uint32_t pixel, uint32_t sample,

@@ -60,6 +60,7 @@ def lib():
                                            C.POINTER(C.c_int64), C.c_int32]
         L.oracle_render_grad.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp, C.c_int32,
                                          C.POINTER(C.c_int64), dp, dp, C.c_int32]
+        L.oracle_debug_trace.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int32, dp]
         L.oracle_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.oracle_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                       C.c_uint32, C.c_int32, dp]
@@ -217,6 +218,12 @@ class OracleScene:
                                       nthreads)
         assert rc == 0
         return g, mean.reshape(s.height, s.width)
+
+    def debug_trace(self, pixel: int, sample: int, kmax: int = 32):
+        out = np.zeros(16 * kmax + 1)
+        rc = lib().oracle_debug_trace(self.handle, pixel, sample, kmax, _dp(out))
+        assert rc == 0
+        return out[:-1].reshape(kmax, 16), out[-1]
 
     # ---- point functions ----
     def eval_point(self, x):

@@ -1,0 +1,327 @@
+// C-ABI entry points of libgpss: argument validation, scene upload, scratch management and
+// the host side of every call.  No exception leaves this file.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "gpss_internal.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+
+bool finite3(const float* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+}  // namespace
+
+namespace gpss {
+
+int set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return GPSS_OK;
+    if (e == hipErrorOutOfMemory) return set_error(GPSS_ERR_OOM, "%s: %s", what, hipGetErrorString(e));
+    return set_error(GPSS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ensure_scratch(gpss_scene* s, size_t floats) {
+    if (s->scratch_floats >= floats) return GPSS_OK;
+    if (s->d_scratch) {
+        int rc = check_hip(hipFree(s->d_scratch), "hipFree(scratch)");
+        s->d_scratch = nullptr;
+        s->scratch_floats = 0;
+        if (rc) return rc;
+    }
+    int rc = check_hip(hipMalloc(&s->d_scratch, floats * sizeof(float)), "hipMalloc(scratch)");
+    if (rc) return rc;
+    s->scratch_floats = floats;
+    return GPSS_OK;
+}
+
+}  // namespace gpss
+
+using gpss::check_hip;
+using gpss::set_error;
+
+namespace {
+
+int validate_desc(const gpss_scene_desc* D) {
+    if (!D) return set_error(GPSS_ERR_INVALID_ARG, "desc is NULL");
+    if (D->struct_size != sizeof(gpss_scene_desc))
+        return set_error(GPSS_ERR_INVALID_ARG, "desc.struct_size %u != %zu", D->struct_size, sizeof(gpss_scene_desc));
+    if (D->mean_kind < 0 || D->mean_kind > 2) return set_error(GPSS_ERR_INVALID_ARG, "mean_kind %d", D->mean_kind);
+    if (D->mean_kind == GPSS_MEAN_SDF) {
+        if (!D->prims || D->n_prims < 1 || D->n_prims > (uint32_t)gpss::kMaxPrims)
+            return set_error(GPSS_ERR_INVALID_ARG, "SDF mean needs 1..%d primitives", gpss::kMaxPrims);
+        for (uint32_t i = 0; i < D->n_prims; ++i) {
+            const float* p = D->prims + 8 * i;
+            if (!finite3(p, 8)) return set_error(GPSS_ERR_INVALID_ARG, "primitive %u not finite", i);
+            if (p[0] != 0.0f && p[0] != 1.0f) return set_error(GPSS_ERR_INVALID_ARG, "primitive %u kind", i);
+            const int nr = p[0] == 0.0f ? 1 : 3;
+            for (int k = 0; k < nr; ++k)
+                if (!(p[4 + k] > 0.0f)) return set_error(GPSS_ERR_INVALID_ARG, "primitive %u size", i);
+            if (!(p[7] >= 0.0f && p[7] <= 1.0f)) return set_error(GPSS_ERR_INVALID_ARG, "primitive %u albedo", i);
+        }
+    }
+    if (!std::isfinite(D->mean_const)) return set_error(GPSS_ERR_INVALID_ARG, "mean_const");
+    auto grid_ok = [](const float* g, const uint32_t* res, bool positive, const char* name) -> int {
+        for (int a = 0; a < 3; ++a)
+            if (res[a] < 2 || res[a] > 1024) return set_error(GPSS_ERR_INVALID_ARG, "%s resolution", name);
+        const uint64_t n = (uint64_t)res[0] * res[1] * res[2];
+        for (uint64_t i = 0; i < n; ++i)
+            if (!std::isfinite(g[i]) || (positive && !(g[i] > 0.0f)))
+                return set_error(GPSS_ERR_INVALID_ARG, "%s value %llu", name, (unsigned long long)i);
+        return GPSS_OK;
+    };
+    if (D->mean_offset) {
+        int rc = grid_ok(D->mean_offset, D->off_res, false, "mean_offset");
+        if (rc) return rc;
+    }
+    if (D->variance_grid) {
+        int rc = grid_ok(D->variance_grid, D->var_res, true, "variance_grid");
+        if (rc) return rc;
+    } else if (!(D->variance > 0.0f) || !std::isfinite(D->variance)) {
+        return set_error(GPSS_ERR_INVALID_ARG, "variance must be > 0");
+    }
+    if (!(D->lengthscale > 0.0f) || !std::isfinite(D->lengthscale))
+        return set_error(GPSS_ERR_INVALID_ARG, "lengthscale must be > 0");
+    if (!(D->albedo >= 0.0f && D->albedo <= 1.0f)) return set_error(GPSS_ERR_INVALID_ARG, "albedo not in [0,1]");
+    if (!(D->mix_R >= 0.0f && D->mix_R <= 1.0f)) return set_error(GPSS_ERR_INVALID_ARG, "mix_R not in [0,1]");
+    if (!finite3(D->bounds, 6)) return set_error(GPSS_ERR_INVALID_ARG, "bounds not finite");
+    for (int a = 0; a < 3; ++a) {
+        if (!(D->bounds[3 + a] > D->bounds[a])) return set_error(GPSS_ERR_INVALID_ARG, "empty bounds");
+        if (D->majorant_res[a] < 1 || D->majorant_res[a] > 256)
+            return set_error(GPSS_ERR_INVALID_ARG, "majorant_res must be 1..256");
+    }
+    if (!finite3(D->dir_light, 4) || !finite3(D->point_light, 4) || !std::isfinite(D->env_radiance))
+        return set_error(GPSS_ERR_INVALID_ARG, "light values not finite");
+    if (D->dir_light[3] < 0.0f || D->point_light[3] < 0.0f || D->env_radiance < 0.0f)
+        return set_error(GPSS_ERR_INVALID_ARG, "negative light");
+    if (D->dir_light[3] > 0.0f) {
+        const float n = std::sqrt(D->dir_light[0] * D->dir_light[0] + D->dir_light[1] * D->dir_light[1] +
+                                  D->dir_light[2] * D->dir_light[2]);
+        if (std::fabs(n - 1.0f) > 1e-3f) return set_error(GPSS_ERR_INVALID_ARG, "dir_light direction not unit");
+    }
+    if (D->cam_kind != GPSS_CAM_ORTHO && D->cam_kind != GPSS_CAM_PINHOLE)
+        return set_error(GPSS_ERR_INVALID_ARG, "cam_kind");
+    if (!finite3(D->cam_eye, 3) || !finite3(D->cam_target, 3) || !finite3(D->cam_up, 3))
+        return set_error(GPSS_ERR_INVALID_ARG, "camera not finite");
+    if (D->cam_kind == GPSS_CAM_PINHOLE && !(D->cam_fov_deg > 0.0f && D->cam_fov_deg < 180.0f))
+        return set_error(GPSS_ERR_INVALID_ARG, "cam_fov_deg");
+    if (D->cam_kind == GPSS_CAM_ORTHO && !(D->cam_window[0] > 0.0f && D->cam_window[1] > 0.0f))
+        return set_error(GPSS_ERR_INVALID_ARG, "cam_window");
+    if (D->width < 1 || D->height < 1 || D->width > 16384 || D->height > 16384)
+        return set_error(GPSS_ERR_INVALID_ARG, "resolution");
+    if (D->spp < 1) return set_error(GPSS_ERR_INVALID_ARG, "spp must be >= 1");
+    if (D->max_depth > 65534) return set_error(GPSS_ERR_INVALID_ARG, "max_depth > 65534");
+    return GPSS_OK;
+}
+
+int upload(const float* src, size_t n, float** dst) {
+    int rc = check_hip(hipMalloc(dst, n * sizeof(float)), "hipMalloc");
+    if (rc) return rc;
+    return check_hip(hipMemcpy(*dst, src, n * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy H2D");
+}
+
+void free_scene(gpss_scene* s) {
+    if (!s) return;
+    (void)hipFree(s->d_prims);
+    (void)hipFree(s->d_offset);
+    (void)hipFree(s->d_var);
+    (void)hipFree(s->d_maj);
+    (void)hipFree(s->d_scratch);
+    delete s;
+}
+
+void fill_dev(gpss_scene* s) {
+    const gpss_scene_desc& D = s->desc;
+    gpss::SceneDev& V = s->dev;
+    V.mean_kind = D.mean_kind;
+    V.mean_const = D.mean_const;
+    V.n_prims = D.mean_kind == GPSS_MEAN_SDF ? (int)D.n_prims : 0;
+    V.prims = reinterpret_cast<const float4*>(s->d_prims);
+    V.offset = s->d_offset;
+    V.var_grid = s->d_var;
+    V.variance = D.variance;
+    V.lengthscale = D.lengthscale;
+    V.albedo = D.albedo;
+    V.albedo_per_prim = D.albedo_per_prim ? 1 : 0;
+    for (int a = 0; a < 3; ++a) {
+        const double lo = D.bounds[a], hi = D.bounds[3 + a], ext = hi - lo;
+        V.lo[a] = D.bounds[a];
+        V.hi[a] = D.bounds[3 + a];
+        V.M[a] = (int)D.majorant_res[a];
+        V.cw[a] = (float)(ext / D.majorant_res[a]);
+        V.inv_cw[a] = (float)(D.majorant_res[a] / ext);
+        V.lo_d[a] = lo;
+        V.hi_d[a] = hi;
+        V.cw_d[a] = ext / D.majorant_res[a];
+        V.inv_cw_d[a] = D.majorant_res[a] / ext;
+        V.off_res[a] = (int)D.off_res[a];
+        V.off_scale[a] = D.mean_offset || s->d_offset ? (float)((D.off_res[a] - 1) / ext) : 0.0f;
+        V.var_res[a] = (int)D.var_res[a];
+        V.var_scale[a] = s->d_var ? (float)((D.var_res[a] - 1) / ext) : 0.0f;
+    }
+    V.maj = s->d_maj;
+    V.R = D.mix_R;
+    for (int k = 0; k < 4; ++k) {
+        V.dl[k] = D.dir_light[k];
+        V.pl[k] = D.point_light[k];
+    }
+    V.env = D.env_radiance;
+    V.cam_kind = D.cam_kind;
+    // camera frame in double from the float inputs
+    double eye[3], fwd[3], up[3], right[3], upc[3];
+    for (int k = 0; k < 3; ++k) {
+        eye[k] = D.cam_eye[k];
+        fwd[k] = (double)D.cam_target[k] - (double)D.cam_eye[k];
+        up[k] = D.cam_up[k];
+    }
+    auto nrm = [](double* v) {
+        const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        v[0] /= n; v[1] /= n; v[2] /= n;
+    };
+    auto crs = [](const double* a, const double* b, double* r) {
+        r[0] = a[1] * b[2] - a[2] * b[1];
+        r[1] = a[2] * b[0] - a[0] * b[2];
+        r[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    nrm(fwd);
+    crs(fwd, up, right);
+    nrm(right);
+    crs(right, fwd, upc);
+    for (int k = 0; k < 3; ++k) {
+        V.eye[k] = eye[k];
+        V.fwd[k] = fwd[k];
+        V.right[k] = right[k];
+        V.upc[k] = upc[k];
+    }
+    V.tan_half = std::tan(0.5 * (double)D.cam_fov_deg * 3.14159265358979323846 / 180.0);
+    V.aspect = (double)D.width / D.height;
+    V.win[0] = D.cam_window[0];
+    V.win[1] = D.cam_window[1];
+    V.W = (int)D.width;
+    V.H = (int)D.height;
+    V.max_depth = (int)D.max_depth;
+    V.key0 = (uint32_t)(D.seed & 0xFFFFFFFFull);
+    V.key1 = (uint32_t)(D.seed >> 32) ^ D.scene_id;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gpss_last_error(void) { return g_last_error.c_str(); }
+
+int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out) {
+    try {
+        if (!out) return set_error(GPSS_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        int rc = validate_desc(desc);
+        if (rc) return rc;
+        gpss_scene* s = new (std::nothrow) gpss_scene();
+        if (!s) return set_error(GPSS_ERR_OOM, "host allocation");
+        s->desc = *desc;
+        rc = check_hip(hipGetDevice(&s->device), "hipGetDevice");
+        const gpss_scene_desc& D = *desc;
+        if (!rc && D.mean_kind == GPSS_MEAN_SDF) {
+            s->prims_h.assign(D.prims, D.prims + 8 * D.n_prims);
+            rc = upload(s->prims_h.data(), s->prims_h.size(), &s->d_prims);
+        }
+        if (!rc && D.mean_offset) {
+            const size_t n = (size_t)D.off_res[0] * D.off_res[1] * D.off_res[2];
+            s->offset_h.assign(D.mean_offset, D.mean_offset + n);
+            rc = upload(s->offset_h.data(), n, &s->d_offset);
+        }
+        if (!rc && D.variance_grid) {
+            const size_t n = (size_t)D.var_res[0] * D.var_res[1] * D.var_res[2];
+            s->var_h.assign(D.variance_grid, D.variance_grid + n);
+            rc = upload(s->var_h.data(), n, &s->d_var);
+        }
+        const size_t nmaj = (size_t)D.majorant_res[0] * D.majorant_res[1] * D.majorant_res[2];
+        if (!rc) rc = check_hip(hipMalloc(&s->d_maj, nmaj * sizeof(float)), "hipMalloc(majorants)");
+        s->desc.prims = nullptr;
+        s->desc.mean_offset = nullptr;
+        s->desc.variance_grid = nullptr;
+        if (!rc) {
+            fill_dev(s);
+            rc = gpss::launch_majorants(s, nullptr);
+        }
+        if (!rc) {
+            s->maj_h.resize(nmaj);
+            rc = check_hip(hipMemcpy(s->maj_h.data(), s->d_maj, nmaj * sizeof(float), hipMemcpyDeviceToHost),
+                           "hipMemcpy majorants");
+        }
+        if (rc) {
+            free_scene(s);
+            return rc;
+        }
+        s->spp = D.spp;
+        *out = s;
+        return GPSS_OK;
+    } catch (...) {
+        return set_error(GPSS_ERR_OOM, "unexpected host exception in gpss_scene_create");
+    }
+}
+
+int gpss_scene_destroy(gpss_scene_t scene) {
+    if (!scene) return set_error(GPSS_ERR_INVALID_ARG, "scene is NULL");
+    free_scene(scene);
+    return GPSS_OK;
+}
+
+int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n) {
+    if (!scene || !out) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
+    if (n < scene->maj_h.size()) return set_error(GPSS_ERR_INVALID_ARG, "output holds %llu < %zu floats",
+                                                  (unsigned long long)n, scene->maj_h.size());
+    std::memcpy(out, scene->maj_h.data(), scene->maj_h.size() * sizeof(float));
+    return GPSS_OK;
+}
+
+int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_dev, uint32_t s0, uint32_t s1,
+                      gpss_stream_t stream) {
+    if (!scene || !paths_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
+    if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
+    return gpss::launch_render_paths(scene, paths_dev, counters_dev, s0, s1 - s0,
+                                     reinterpret_cast<hipStream_t>(stream));
+}
+
+int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream) {
+    if (!scene || !image_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
+    if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
+    const uint32_t ns = s1 - s0;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int rc = gpss::ensure_scratch(scene, (size_t)scene->n_pixels() * ns);
+    if (rc) return rc;
+    rc = gpss::launch_render_paths(scene, scene->d_scratch, nullptr, s0, ns, st);
+    if (rc) return rc;
+    return gpss::launch_reduce(scene, scene->d_scratch, image_dev, ns, st);
+}
+
+int gpss_eval_medium(gpss_scene_t scene, const float* points_dev, const float* dirs_dev, float* out_dev,
+                     uint64_t n, gpss_stream_t stream) {
+    if (!scene || !points_dev || !dirs_dev || !out_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
+    if (n == 0) return GPSS_OK;
+    return gpss::launch_eval(scene, points_dev, dirs_dev, out_dev, n, reinterpret_cast<hipStream_t>(stream));
+}
+
+int gpss_debug_trace(gpss_scene_t scene, const uint32_t* ids_dev, uint32_t n, float* out_dev, uint32_t kmax,
+                     gpss_stream_t stream) {
+    if (!scene || !ids_dev || !out_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
+    if (kmax < 1 || kmax > 65535) return set_error(GPSS_ERR_INVALID_ARG, "kmax must be 1..65535");
+    if (n == 0) return GPSS_OK;
+    return gpss::launch_debug_trace(scene, ids_dev, n, out_dev, (int)kmax, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,493 @@
+// Device-side building blocks of the gfx950 GPSS path tracer: scene record, counter-based
+// random numbers, GP statistics at a point, the macrofacet medium (density, projected
+// area, generalized NDF, phase function and its mixture proposal) and majorant-grid
+// traversal.  Single precision; every function is inlined into the kernels that use it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpss {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvSqrt2 = 0.70710678118654752440f;
+constexpr float kInvSqrt2Pi = 0.39894228040143267794f;     // 1 / sqrt(2 pi)
+constexpr float kSqrt2Pi = 2.50662827463100050242f;
+constexpr float kSqrtHalfPi = 1.25331413731550025121f;     // sqrt(pi / 2)
+constexpr float kSqrt2OverPi = 0.79788456080286535588f;    // sqrt(2 / pi)
+constexpr float kInvSqrtPi = 0.56418958354775628695f;
+constexpr float kInv2PiPow1p5 = 0.06349363593424096978f;   // (2 pi)^(-3/2)
+constexpr float kSqrt2 = 1.41421356237309504880f;
+
+constexpr int kMaxPrims = 64;
+constexpr int kStepCap = 1 << 16;           // tentative collisions per segment
+constexpr float kTrCutoff = 0x1p-40f;       // ratio tracking stops (returns 0) below this
+
+enum : uint32_t { kStreamCam = 0, kStreamTrack = 1, kStreamPhase = 2, kStreamNee0 = 3 };
+
+// ---------------------------------------------------------------------------
+// Scene record, passed by value as a kernel argument.
+// ---------------------------------------------------------------------------
+struct SceneDev {
+    int mean_kind;
+    float mean_const;
+    int n_prims;
+    const float4* prims;          // 2 per primitive: (kind, cx, cy, cz), (a, b, c, albedo)
+    const float* offset;          // nullable
+    int off_res[3];
+    float off_scale[3];           // (res - 1) / extent
+    float variance;
+    const float* var_grid;        // nullable
+    int var_res[3];
+    float var_scale[3];
+    float lengthscale;
+    float albedo;
+    int albedo_per_prim;
+    float lo[3], hi[3];
+    float cw[3];                  // majorant cell size
+    float inv_cw[3];
+    double lo_d[3], hi_d[3], cw_d[3], inv_cw_d[3];  // the same box and cells in double
+    int M[3];
+    const float* maj;             // majorant grid, x fastest
+    float R;
+    float dl[4], pl[4], env;
+    int cam_kind;
+    double eye[3], fwd[3], right[3], upc[3];
+    double tan_half, aspect, win[2];
+    int W, H, max_depth;
+    uint32_t key0, key1;
+};
+
+// ---------------------------------------------------------------------------
+// float3 helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator-(float3 a) { return f3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ float3 operator*(float s, float3 a) { return f3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross(float3 a, float3 b) {
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 normalize(float3 a) { return (1.0f / sqrtf(dot(a, a))) * a; }
+__device__ __forceinline__ float comp(float3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+
+// Ray geometry (origins, directions, distances, cell boundaries) is kept in double
+// precision so that where a tentative collision falls relative to a majorant-cell
+// boundary does not depend on single-precision rounding of the path's position.
+struct D3 {
+    double x, y, z;
+};
+__device__ __forceinline__ D3 d3(double x, double y, double z) { return D3{x, y, z}; }
+__device__ __forceinline__ D3 d3(float3 a) { return D3{(double)a.x, (double)a.y, (double)a.z}; }
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return d3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return d3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ D3 operator-(D3 a) { return d3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ D3 operator*(double s, D3 a) { return d3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ D3 normalize(D3 a) { return (1.0 / sqrt(dot(a, a))) * a; }
+__device__ __forceinline__ float3 to_f3(D3 a) { return make_float3((float)a.x, (float)a.y, (float)a.z); }
+__device__ __forceinline__ double comp(D3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+
+// Orthonormal basis around unit n (Duff et al., JCGT 2017).
+__device__ __forceinline__ void onb(float3 n, float3& t, float3& b) {
+    const float sign = copysignf(1.0f, n.z);
+    const float a = -1.0f / (sign + n.z);
+    const float bb = n.x * n.y * a;
+    t = f3(1.0f + sign * n.x * n.x * a, sign * bb, -sign * n.x);
+    b = f3(bb, sign + n.y * n.y * a, -n.y);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, each two 32x32 -> 64-bit products,
+// key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Draws of one (pixel, sample, bounce, stream) address, consumed in order; counter word w
+// numbers blocks of four draws.  Uniforms keep the top 24 bits (exact in float).
+struct Rng {
+    uint4 ctr;
+    uint4 buf;
+    uint2 key;
+    int pos;
+    __device__ __forceinline__ void init(uint32_t k0, uint32_t k1, uint32_t pixel, uint32_t sample,
+                                         uint32_t bounce, uint32_t stream) {
+        key = make_uint2(k0, k1);
+        ctr = make_uint4(pixel, sample, (bounce & 0xFFFFu) | (stream << 16), 0u);
+        pos = 4;
+    }
+    __device__ __forceinline__ uint32_t next() {
+        if (pos == 4) {
+            buf = philox4x32_10(ctr, key);
+            ctr.w += 1u;
+            pos = 0;
+        }
+        const uint32_t r = pos == 0 ? buf.x : (pos == 1 ? buf.y : (pos == 2 ? buf.z : buf.w));
+        ++pos;
+        return r;
+    }
+    __device__ __forceinline__ uint32_t next24() { return next() >> 8; }
+    __device__ __forceinline__ float uniform() { return (float)next24() * 0x1p-24f; }
+};
+
+// ---------------------------------------------------------------------------
+// Mean-function geometry and grids.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float sdf_prim(float4 a, float4 b, float3 x, float3& g) {
+    const float3 v = f3(x.x - a.y, x.y - a.z, x.z - a.w);
+    if (a.x < 0.5f) {  // sphere
+        const float r = sqrtf(dot(v, v));
+        g = r > 0.0f ? (1.0f / r) * v : f3(0.0f, 0.0f, 1.0f);
+        return r - b.x;
+    }
+    const float sx = v.x < 0.0f ? -1.0f : 1.0f, sy = v.y < 0.0f ? -1.0f : 1.0f,
+                sz = v.z < 0.0f ? -1.0f : 1.0f;
+    const float qx = fabsf(v.x) - b.x, qy = fabsf(v.y) - b.y, qz = fabsf(v.z) - b.z;
+    const float qmax = fmaxf(qx, fmaxf(qy, qz));
+    if (qmax > 0.0f) {
+        const float px = fmaxf(qx, 0.0f), py = fmaxf(qy, 0.0f), pz = fmaxf(qz, 0.0f);
+        const float n = sqrtf(px * px + py * py + pz * pz);
+        const float in = 1.0f / n;
+        g = f3(sx * px * in, sy * py * in, sz * pz * in);
+        return n;
+    }
+    int ax = 0;
+    if (qy > qx) ax = 1;
+    if (qz > fmaxf(qx, qy)) ax = 2;
+    g = f3(ax == 0 ? sx : 0.0f, ax == 1 ? sy : 0.0f, ax == 2 ? sz : 0.0f);
+    return qmax;
+}
+
+__device__ __forceinline__ void mean_geom(const SceneDev& S, float3 x, float& f, float3& g, int& which) {
+    which = -1;
+    if (S.mean_kind == 0) { f = x.z; g = f3(0.0f, 0.0f, 1.0f); return; }
+    if (S.mean_kind == 2) { f = S.mean_const; g = f3(0.0f, 0.0f, 0.0f); return; }
+    float best = INFINITY;
+    float3 bg = f3(0.0f, 0.0f, 1.0f);
+    for (int i = 0; i < S.n_prims; ++i) {
+        float3 gi;
+        const float fi = sdf_prim(S.prims[2 * i], S.prims[2 * i + 1], x, gi);
+        if (fi < best) { best = fi; bg = gi; which = i; }
+    }
+    f = best;
+    g = bg;
+}
+
+// Trilinear cell lookup on a node-centred grid over the scene box.
+struct TriCell {
+    int base;        // flat index of the (i, j, k) corner
+    float fx, fy, fz;
+};
+
+__device__ __forceinline__ TriCell tri_cell(const int res[3], const float scale[3], const float lo[3], float3 x) {
+    TriCell c;
+    float u[3] = {(x.x - lo[0]) * scale[0], (x.y - lo[1]) * scale[1], (x.z - lo[2]) * scale[2]};
+    int i[3];
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float ua = fminf(fmaxf(u[a], 0.0f), (float)(res[a] - 1));
+        int ia = (int)floorf(ua);
+        ia = min(ia, res[a] - 2);
+        i[a] = ia;
+        f[a] = ua - (float)ia;
+    }
+    c.base = (i[2] * res[1] + i[1]) * res[0] + i[0];
+    c.fx = f[0]; c.fy = f[1]; c.fz = f[2];
+    return c;
+}
+
+// value and gradient (w.r.t. x) of the trilinear interpolant
+__device__ __forceinline__ float tri_eval(const float* __restrict__ g, const int res[3], const float scale[3],
+                                          const TriCell& c, float3* grad) {
+    const int sx = 1, sy = res[0], sz = res[0] * res[1];
+    const float v000 = g[c.base], v100 = g[c.base + sx], v010 = g[c.base + sy], v110 = g[c.base + sx + sy];
+    const float v001 = g[c.base + sz], v101 = g[c.base + sx + sz], v011 = g[c.base + sy + sz],
+                v111 = g[c.base + sx + sy + sz];
+    const float fx = c.fx, fy = c.fy, fz = c.fz;
+    const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+    const float x00 = gx * v000 + fx * v100, x10 = gx * v010 + fx * v110;
+    const float x01 = gx * v001 + fx * v101, x11 = gx * v011 + fx * v111;
+    const float y0 = gy * x00 + fy * x10, y1 = gy * x01 + fy * x11;
+    if (grad) {
+        const float dx = gy * gz * (v100 - v000) + fy * gz * (v110 - v010) + gy * fz * (v101 - v001) +
+                         fy * fz * (v111 - v011);
+        const float dy = gz * (x10 - x00) + fz * (x11 - x01);
+        const float dz = y1 - y0;
+        *grad = f3(dx * scale[0], dy * scale[1], dz * scale[2]);
+    }
+    return gz * y0 + fz * y1;
+}
+
+// GP statistics at x (Sec. 3.1, Eq. joint_fg): f ~ N(mu, sigma^2) and, independent at the
+// same point, g ~ N(grad mu, s^2 I) with s = sigma / l for the isotropic SE kernel.
+struct PointQ {
+    float mu;
+    float3 G;
+    float sigma;
+    float s;
+    float albedo;
+};
+
+__device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
+    PointQ q;
+    int which;
+    mean_geom(S, x, q.mu, q.G, which);
+    if (S.offset) {
+        float3 go;
+        const TriCell c = tri_cell(S.off_res, S.off_scale, S.lo, x);
+        q.mu += tri_eval(S.offset, S.off_res, S.off_scale, c, &go);
+        q.G = q.G + go;
+    }
+    float var = S.variance;
+    if (S.var_grid) {
+        const TriCell c = tri_cell(S.var_res, S.var_scale, S.lo, x);
+        var = tri_eval(S.var_grid, S.var_res, S.var_scale, c, nullptr);
+    }
+    q.sigma = sqrtf(var);
+    q.s = q.sigma / S.lengthscale;
+    q.albedo = (S.albedo_per_prim && which >= 0) ? S.prims[2 * which + 1].w : S.albedo;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// Macrofacet medium.
+// ---------------------------------------------------------------------------
+// Density rho = phi(mu; 0, sigma^2) / Phi(mu; 0, sigma^2) = sqrt(2/pi) / (sigma erfcx(-mu/(sigma sqrt2))).
+__device__ __forceinline__ float rho_of(float mu, float sigma) {
+    const float z = mu / sigma;
+    return kSqrt2OverPi / (sigma * erfcxf(-z * kInvSqrt2));
+}
+
+// Projected area sigma(d) = E[max(0, -d.g)], g ~ N(G, s^2 I): with m = d.G, z = m / s,
+//   s phi(z) - m Phi(-z);  for z > 0 written as s phi(z) (1 - z sqrt(pi/2) erfcx(z/sqrt2)).
+// Equals the paper's Lambda(w) cos(theta) for G of unit length; scales with |G| otherwise.
+__device__ __forceinline__ float sigma_proj(float3 G, float s, float3 d) {
+    const float m = dot(d, G);
+    const float z = m / s;
+    const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
+    if (z <= 0.0f) return s * ph - m * (1.0f - 0.5f * erfcf(-z * kInvSqrt2));
+    return s * ph * (1.0f - z * kSqrtHalfPi * erfcxf(z * kInvSqrt2));
+}
+
+// Generalized NDF (Sec. 4.2.2) for g ~ N(G, s^2 I): int_0^inf P(t wm) t^3 dt in closed form,
+//   D = s (2 pi)^(-3/2) [ (k^2 + 2) e^{-|G|^2/(2 s^2)} + sqrt(2 pi) k (k^2 + 3) e^{-q/2} Phi(k) ],
+// k = G.wm / s, q = |G x wm|^2 / s^2; for k < 0, e^{-q/2} Phi(k) = e^{-|G|^2/(2s^2)} erfcx(-k/sqrt2)/2.
+__device__ __forceinline__ float ndf(float3 G, float s, float3 wm) {
+    const float is = 1.0f / s;
+    const float k = dot(G, wm) * is;
+    const float3 c = cross(G, wm);
+    const float q = dot(c, c) * is * is;
+    const float g2 = dot(G, G) * is * is;
+    const float eG = expf(-0.5f * g2);
+    const float pre = s * kInv2PiPow1p5;
+    const float k2 = k * k;
+    if (k >= 0.0f) {
+        const float E = expf(-0.5f * q) * (1.0f - 0.5f * erfcf(k * kInvSqrt2));
+        return pre * ((k2 + 2.0f) * eG + kSqrt2Pi * k * (k2 + 3.0f) * E);
+    }
+    const float b = (k2 + 2.0f) + kSqrtHalfPi * k * (k2 + 3.0f) * erfcxf(-k * kInvSqrt2);
+    return pre * eG * fmaxf(b, 0.0f);
+}
+
+__device__ __forceinline__ float sigma_t_of(const PointQ& q, float3 d) {
+    return rho_of(q.mu, q.sigma) * sigma_proj(q.G, q.s, d);
+}
+
+// Conductor phase function with F = albedo for travel direction d, scattered direction wi.
+__device__ __forceinline__ float phase_eval(const PointQ& q, float3 d, float3 wi) {
+    float3 h = wi - d;
+    const float hn = sqrtf(dot(h, h));
+    if (hn < 1e-7f) return 0.0f;
+    h = (1.0f / hn) * h;
+    return q.albedo * ndf(q.G, q.s, h) / (4.0f * sigma_proj(q.G, q.s, d));
+}
+
+// ---------------------------------------------------------------------------
+// Mixture proposal over half vectors: Beckmann visible normals with probability R (while v
+// is above the local horizon), uniform over the hemisphere about v otherwise.
+// ---------------------------------------------------------------------------
+struct Proposal {
+    float3 N, T, B;
+    float alpha, cosv, a;   // a = cot(theta_v) after stretching to unit roughness
+    float Reff;
+    bool beck;
+};
+
+__device__ __forceinline__ Proposal make_proposal(const PointQ& q, float R, float3 v) {
+    Proposal p;
+    p.beck = false;
+    p.Reff = 0.0f;
+    const float g2 = dot(q.G, q.G);
+    if (g2 > 0.0f) {
+        const float gn = sqrtf(g2);
+        p.N = (1.0f / gn) * q.G;
+        p.cosv = dot(v, p.N);
+        if (p.cosv > 0.0f) {
+            p.beck = true;
+            p.Reff = R;
+            p.alpha = kSqrt2 * q.s / gn;
+            const float3 vt = v - p.cosv * p.N;
+            const float st = sqrtf(dot(vt, vt));
+            if (st > 1e-7f) {
+                p.T = (1.0f / st) * vt;
+                p.a = p.cosv / (p.alpha * st);
+            } else {
+                float3 b;
+                onb(p.N, p.T, b);
+                p.a = INFINITY;
+            }
+            p.B = cross(p.N, p.T);
+        }
+    }
+    return p;
+}
+
+__device__ __forceinline__ float beckmann_lambda(float a) {
+    if (isinf(a)) return 0.0f;
+    return 0.5f * (expf(-a * a) * kInvSqrtPi / a - erfcf(a));
+}
+
+__device__ __forceinline__ float mixture_pdf(const Proposal& p, float3 v, float3 wm) {
+    const float vm = dot(v, wm);
+    if (vm <= 0.0f) return 0.0f;
+    float pb = 0.0f;
+    if (p.beck) {
+        const float cm = dot(wm, p.N);
+        if (cm > 0.0f) {
+            const float3 cr = cross(wm, p.N);
+            const float c2 = cm * cm, a2 = p.alpha * p.alpha;
+            const float D = expf(-dot(cr, cr) / (c2 * a2)) / (kPi * a2 * c2 * c2);
+            pb = vm * D / ((1.0f + beckmann_lambda(p.a)) * p.cosv);
+        }
+    }
+    return p.Reff * pb + (1.0f - p.Reff) * (0.5f / kPi);
+}
+
+// Slope along the incidence plane at unit roughness: solve F(x) = u F(a) on [-8, a],
+// F(x) = erfc(-x)/2 + exp(-x^2)/(2 a sqrt(pi)), by bracketed Newton iterations.
+__device__ __forceinline__ float sample_slope_x(float a, float u) {
+    const bool fin = !isinf(a);
+    const float c2 = fin ? 0.5f * kInvSqrtPi / a : 0.0f;
+    const float ia = fin ? 1.0f / a : 0.0f;
+    const float Fa = fin ? 0.5f * erfcf(-a) + expf(-a * a) * c2 : 1.0f;
+    const float target = u * Fa;
+    float lo = -8.0f, hi = fin ? fminf(a, 8.0f) : 8.0f;
+    if (target <= 0.5f * erfcf(8.0f) + expf(-64.0f) * c2) return lo;
+    float x = fminf(fmaxf(0.0f, lo), hi);
+    for (int it = 0; it < 48; ++it) {
+        const float e = expf(-x * x);
+        const float fx = 0.5f * erfcf(-x) + e * c2 - target;
+        if (fx == 0.0f) break;
+        if (fx > 0.0f) hi = x; else lo = x;
+        const float fp = e * kInvSqrtPi * (1.0f - x * ia);
+        float xn = fp > 0.0f ? x - fx / fp : 0.5f * (lo + hi);
+        if (!(xn > lo && xn < hi)) xn = 0.5f * (lo + hi);
+        const float step = xn - x;
+        x = xn;
+        const float tol = 2e-7f * fmaxf(1.0f, fabsf(x));
+        if (fabsf(step) <= tol || hi - lo <= tol) break;
+    }
+    return x;
+}
+
+__device__ __forceinline__ float3 sample_half_vector(const Proposal& p, float3 v, float usel, uint32_t ua24,
+                                                     uint32_t ub24) {
+    const float ua = (float)ua24 * 0x1p-24f, ub = (float)ub24 * 0x1p-24f;
+    if (usel < p.Reff) {
+        const float xs = sample_slope_x(p.a, ua);
+        // (2 k + 1) / 2^24 - 1, exact in float
+        const float ys = erfinvf((float)((int)(2u * ub24 + 1u) - (1 << 24)) * 0x1p-24f);
+        const float x = p.alpha * xs, y = p.alpha * ys;
+        const float in = 1.0f / sqrtf(x * x + y * y + 1.0f);
+        return f3((-x * p.T.x - y * p.B.x + p.N.x) * in, (-x * p.T.y - y * p.B.y + p.N.y) * in,
+                  (-x * p.T.z - y * p.B.z + p.N.z) * in);
+    }
+    float3 t, b;
+    onb(v, t, b);
+    const float ct = 1.0f - ua;
+    const float st = sqrtf(ua * (2.0f - ua));
+    float sp, cp;
+    sincosf(2.0f * kPi * ub, &sp, &cp);
+    return (st * cp) * t + (st * sp) * b + ct * v;
+}
+
+// ---------------------------------------------------------------------------
+// Ray / box clipping and majorant-grid walking.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool clip_box(const SceneDev& S, D3 o, D3 d, double& t0, double& t1) {
+    t0 = 0.0;
+    t1 = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double oa = comp(o, a), da = comp(d, a);
+        if (da == 0.0) {
+            if (oa < S.lo_d[a] || oa > S.hi_d[a]) return false;
+            continue;
+        }
+        double ta = (S.lo_d[a] - oa) / da, tb = (S.hi_d[a] - oa) / da;
+        if (ta > tb) { const double tmp = ta; ta = tb; tb = tmp; }
+        t0 = fmax(t0, ta);
+        t1 = fmin(t1, tb);
+    }
+    return t0 < t1;
+}
+
+struct Walker {
+    D3 o, d;
+    int ix, iy, iz;
+    __device__ __forceinline__ void init(const SceneDev& S, D3 o_, D3 d_, double t) {
+        o = o_;
+        d = d_;
+        const D3 p = o + t * d;
+        ix = min(max((int)floor((p.x - S.lo_d[0]) * S.inv_cw_d[0]), 0), S.M[0] - 1);
+        iy = min(max((int)floor((p.y - S.lo_d[1]) * S.inv_cw_d[1]), 0), S.M[1] - 1);
+        iz = min(max((int)floor((p.z - S.lo_d[2]) * S.inv_cw_d[2]), 0), S.M[2] - 1);
+    }
+    __device__ __forceinline__ float majorant(const SceneDev& S) const {
+        return S.maj[(iz * S.M[1] + iy) * S.M[0] + ix];
+    }
+    // distance along the ray to the exit of the current cell and the axis crossed
+    __device__ __forceinline__ double exit(const SceneDev& S, int& ax) const {
+        double tx = INFINITY, ty = INFINITY, tz = INFINITY;
+        if (d.x > 0.0) tx = (S.lo_d[0] + (double)(ix + 1) * S.cw_d[0] - o.x) / d.x;
+        else if (d.x < 0.0) tx = (S.lo_d[0] + (double)ix * S.cw_d[0] - o.x) / d.x;
+        if (d.y > 0.0) ty = (S.lo_d[1] + (double)(iy + 1) * S.cw_d[1] - o.y) / d.y;
+        else if (d.y < 0.0) ty = (S.lo_d[1] + (double)iy * S.cw_d[1] - o.y) / d.y;
+        if (d.z > 0.0) tz = (S.lo_d[2] + (double)(iz + 1) * S.cw_d[2] - o.z) / d.z;
+        else if (d.z < 0.0) tz = (S.lo_d[2] + (double)iz * S.cw_d[2] - o.z) / d.z;
+        ax = 0;
+        double best = tx;
+        if (ty < best) { best = ty; ax = 1; }
+        if (tz < best) { best = tz; ax = 2; }
+        return best;
+    }
+    __device__ __forceinline__ bool step(const SceneDev& S, int ax) {
+        if (ax == 0) { ix += d.x > 0.0 ? 1 : -1; return ix >= 0 && ix < S.M[0]; }
+        if (ax == 1) { iy += d.y > 0.0 ? 1 : -1; return iy >= 0 && iy < S.M[1]; }
+        iz += d.z > 0.0 ? 1 : -1;
+        return iz >= 0 && iz < S.M[2];
+    }
+};
+
+// Per-thread event counts (kept in registers, flushed once per path when requested).
+struct PathStats {
+    uint32_t track_steps, real, nee_steps, violations, capped, escaped, truncated, cells, phase, nee;
+    __device__ __forceinline__ void clear() {
+        track_steps = real = nee_steps = violations = capped = escaped = truncated = cells = phase = nee = 0;
+    }
+};
+
+}  // namespace gpss

@@ -1,0 +1,278 @@
+// Forward kernels: majorant-grid construction, one-thread-per-path rendering, the ordered
+// per-pixel reduction and pointwise medium evaluation.
+#include "gpss_internal.hpp"
+#include "gpss_trace.hpp"
+
+namespace gpss {
+
+// ---------------------------------------------------------------------------
+// Majorant grid (double precision).  Per cell an upper bound of
+// sigma_t = rho(mu, sigma) * sigma_proj over the cell and all directions:
+//   rho(mu, sigma) = r(mu / sigma) / sigma with r = phi / Phi decreasing, so
+//     rho <= r(mu_min / (mu_min > 0 ? sigma_max : sigma_min)) / sigma_min;
+//   sigma_proj <= E[max(0, X)], X ~ N(gmax, s_max^2) = g Phi(g/s) + s phi(g/s);
+//   mu_min = mu(centre) - half diagonal for 1-Lipschitz SDF unions (exact for the plane),
+//   plus the minimum offset node reaching the cell, gmax = |grad sdf| + bound of the
+//   trilinear offset gradient.
+// The bound times (1 + 2^-10) is rounded up to five significant bits; bounds below
+// 2^-40 give 0 (the cell is skipped).
+// ---------------------------------------------------------------------------
+struct MajArgs {
+    int mean_kind;
+    float mean_const;
+    int n_prims;
+    const float4* prims;
+    const float* offset;
+    int off_res[3];
+    const float* var_grid;
+    int var_res[3];
+    float variance;
+    float lengthscale;
+    float lo[3], hi[3];
+    int M[3];
+};
+
+__device__ double sdf_prim_d(float4 a, float4 b, const double x[3]) {
+    const double v[3] = {x[0] - (double)a.y, x[1] - (double)a.z, x[2] - (double)a.w};
+    if (a.x < 0.5f) return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - (double)b.x;
+    const double q[3] = {fabs(v[0]) - (double)b.x, fabs(v[1]) - (double)b.y, fabs(v[2]) - (double)b.z};
+    const double qmax = fmax(q[0], fmax(q[1], q[2]));
+    if (qmax > 0.0) {
+        const double p0 = fmax(q[0], 0.0), p1 = fmax(q[1], 0.0), p2 = fmax(q[2], 0.0);
+        return sqrt(p0 * p0 + p1 * p1 + p2 * p2);
+    }
+    return qmax;
+}
+
+__device__ double quantize_majorant(double B) {
+    if (isnan(B)) return INFINITY;
+    const double Bp = B * (1.0 + 0x1p-10);
+    if (!(Bp >= 0x1p-40)) return 0.0;
+    if (isinf(Bp)) return INFINITY;
+    int e;
+    const double f = frexp(Bp, &e);
+    return ldexp(ceil(f * 32.0), e - 5);
+}
+
+__device__ __forceinline__ void node_range(int k, int M, int R, int& lo, int& hi) {
+    lo = (int)(((long long)k * (R - 1)) / M);
+    hi = (int)((((long long)(k + 1)) * (R - 1) + M - 1) / M);
+    lo = max(lo, 0);
+    hi = min(hi, R - 1);
+}
+
+__global__ void majorant_kernel(MajArgs A, float* __restrict__ out) {
+    const int n = A.M[0] * A.M[1] * A.M[2];
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= n) return;
+    const int k[3] = {cell % A.M[0], (cell / A.M[0]) % A.M[1], cell / (A.M[0] * A.M[1])};
+    double ext[3], cw[3];
+    for (int a = 0; a < 3; ++a) {
+        ext[a] = (double)A.hi[a] - (double)A.lo[a];
+        cw[a] = ext[a] / A.M[a];
+    }
+    const double hdiag = 0.5 * sqrt(cw[0] * cw[0] + cw[1] * cw[1] + cw[2] * cw[2]);
+    double off_min = 0.0, off_g = 0.0;
+    if (A.offset) {
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) node_range(k[a], A.M[a], A.off_res[a], lo[a], hi[a]);
+        const int* r = A.off_res;
+        off_min = INFINITY;
+        double md[3] = {0.0, 0.0, 0.0};
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    const long long idx = ((long long)z * r[1] + y) * r[0] + x;
+                    const double v = A.offset[idx];
+                    off_min = fmin(off_min, v);
+                    if (x < hi[0]) md[0] = fmax(md[0], fabs((double)A.offset[idx + 1] - v));
+                    if (y < hi[1]) md[1] = fmax(md[1], fabs((double)A.offset[idx + r[0]] - v));
+                    if (z < hi[2]) md[2] = fmax(md[2], fabs((double)A.offset[idx + (long long)r[0] * r[1]] - v));
+                }
+        double gs = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double g = md[a] / (ext[a] / (A.off_res[a] - 1));
+            gs += g * g;
+        }
+        off_g = sqrt(gs);
+    }
+    double vmin = A.variance, vmax = A.variance;
+    if (A.var_grid) {
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) node_range(k[a], A.M[a], A.var_res[a], lo[a], hi[a]);
+        const int* r = A.var_res;
+        vmin = INFINITY;
+        vmax = -INFINITY;
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    const double v = A.var_grid[((long long)z * r[1] + y) * r[0] + x];
+                    vmin = fmin(vmin, v);
+                    vmax = fmax(vmax, v);
+                }
+    }
+    double mu_min, gmax;
+    if (A.mean_kind == 0) {
+        mu_min = (double)A.lo[2] + k[2] * cw[2];
+        gmax = 1.0;
+    } else if (A.mean_kind == 2) {
+        mu_min = (double)A.mean_const;
+        gmax = 0.0;
+    } else {
+        double c[3];
+        for (int a = 0; a < 3; ++a) c[a] = (double)A.lo[a] + (k[a] + 0.5) * cw[a];
+        double best = INFINITY;
+        for (int i = 0; i < A.n_prims; ++i) best = fmin(best, sdf_prim_d(A.prims[2 * i], A.prims[2 * i + 1], c));
+        mu_min = best - hdiag;
+        gmax = 1.0;
+    }
+    mu_min += off_min;
+    gmax += off_g;
+    const double smin = sqrt(vmin), smax = sqrt(vmax);
+    const double s_max = smax / (double)A.lengthscale;
+    const double zr = mu_min / (mu_min > 0.0 ? smax : smin);
+    const double rho_max = sqrt(2.0 / 3.14159265358979323846) / erfcx(-zr / 1.41421356237309504880) / smin;
+    const double z = gmax / s_max;
+    const double Phi = 0.5 * erfc(-z / 1.41421356237309504880);
+    const double phi = exp(-0.5 * z * z) / 2.50662827463100050242;
+    out[cell] = (float)quantize_majorant(rho_max * (gmax * Phi + s_max * phi));
+}
+
+int launch_majorants(gpss_scene* s, hipStream_t stream) {
+    const gpss_scene_desc& D = s->desc;
+    MajArgs A{};
+    A.mean_kind = D.mean_kind;
+    A.mean_const = D.mean_const;
+    A.n_prims = (int)D.n_prims;
+    A.prims = reinterpret_cast<const float4*>(s->d_prims);
+    A.offset = s->d_offset;
+    A.var_grid = s->d_var;
+    for (int a = 0; a < 3; ++a) {
+        A.off_res[a] = (int)D.off_res[a];
+        A.var_res[a] = (int)D.var_res[a];
+        A.lo[a] = D.bounds[a];
+        A.hi[a] = D.bounds[3 + a];
+        A.M[a] = (int)D.majorant_res[a];
+    }
+    A.variance = D.variance;
+    A.lengthscale = D.lengthscale;
+    const int n = A.M[0] * A.M[1] * A.M[2];
+    hipLaunchKernelGGL(majorant_kernel, dim3((n + 127) / 128), dim3(128), 0, stream, A, s->d_maj);
+    return check_hip(hipGetLastError(), "majorant_kernel launch");
+}
+
+// ---------------------------------------------------------------------------
+// One thread per path: thread p renders (pixel p / ns, sample s0 + p % ns).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void flush_stats(const PathStats& st, unsigned long long* counters) {
+    const uint32_t vals[10] = {st.track_steps, st.real, st.nee_steps, st.violations, st.capped,
+                               st.escaped, st.truncated, st.cells, st.phase, st.nee};
+    const bool lead = (threadIdx.x & 63) == 0;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t t = wave_sum(vals[i]);
+        if (lead && t) atomicAdd(&counters[i], (unsigned long long)t);
+    }
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void render_paths_kernel(SceneDev S, float* __restrict__ paths,
+                                                           unsigned long long* counters, uint32_t s0,
+                                                           uint32_t ns, uint64_t npaths) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    PathStats st;
+    st.clear();
+    if (p < npaths) {
+        const uint32_t pixel = (uint32_t)(p / ns);
+        const uint32_t sample = s0 + (uint32_t)(p % ns);
+        paths[p] = trace_path<STATS>(S, pixel, sample, st);
+    }
+    if (STATS) flush_stats(st, counters);
+}
+
+int launch_render_paths(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns,
+                        hipStream_t stream) {
+    const uint64_t npaths = s->n_pixels() * ns;
+    const uint64_t blocks = (npaths + 255) / 256;
+    if (blocks > 0x7FFFFFFFull) return set_error(GPSS_ERR_INVALID_ARG, "too many paths in one launch");
+    if (counters)
+        hipLaunchKernelGGL(render_paths_kernel<true>, dim3((uint32_t)blocks), dim3(256), 0, stream, s->dev,
+                           paths, reinterpret_cast<unsigned long long*>(counters), s0, ns, npaths);
+    else
+        hipLaunchKernelGGL(render_paths_kernel<false>, dim3((uint32_t)blocks), dim3(256), 0, stream, s->dev,
+                           paths, nullptr, s0, ns, npaths);
+    return check_hip(hipGetLastError(), "render_paths_kernel launch");
+}
+
+// Diagnostics: trace listed (pixel, sample) paths and keep their per-vertex records.
+__global__ void debug_trace_kernel(SceneDev S, const uint32_t* __restrict__ ids, uint32_t n,
+                                   float* __restrict__ out, int kmax) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    PathStats st;
+    st.clear();
+    float* rec = out + (size_t)i * (kmax * kRecFields + 1);
+    for (int k = 0; k < kmax * kRecFields; ++k) rec[k] = 0.0f;
+    rec[kmax * kRecFields] = trace_path<false, true>(S, ids[2 * i], ids[2 * i + 1], st, rec, kmax);
+}
+
+int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* out, int kmax,
+                       hipStream_t stream) {
+    hipLaunchKernelGGL(debug_trace_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, s->dev, ids, n, out, kmax);
+    return check_hip(hipGetLastError(), "debug_trace_kernel launch");
+}
+
+// Per-pixel mean over the sample range, summed in sample order (deterministic).
+__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ paths, float* __restrict__ image,
+                                                     uint32_t ns, uint64_t npix) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const float* src = paths + p * ns;
+    float acc = 0.0f;
+    for (uint32_t k = 0; k < ns; ++k) acc += src[k];
+    image[p] = acc / (float)ns;
+}
+
+int launch_reduce(gpss_scene* s, const float* paths, float* image, uint32_t ns, hipStream_t stream) {
+    const uint64_t npix = s->n_pixels();
+    hipLaunchKernelGGL(reduce_kernel, dim3((uint32_t)((npix + 255) / 256)), dim3(256), 0, stream, paths, image,
+                       ns, npix);
+    return check_hip(hipGetLastError(), "reduce_kernel launch");
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise medium evaluation.
+// ---------------------------------------------------------------------------
+__global__ void eval_kernel(SceneDev S, const float* __restrict__ pts, const float* __restrict__ dirs,
+                            float* __restrict__ out, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float3 x = f3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
+    const float3 d = f3(dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]);
+    const PointQ q = eval_point(S, x);
+    const float r = rho_of(q.mu, q.sigma);
+    const float sp = sigma_proj(q.G, q.s, d);
+    float* o = out + 8 * i;
+    o[0] = q.mu;
+    o[1] = q.sigma;
+    o[2] = q.s;
+    o[3] = r;
+    o[4] = sp;
+    o[5] = r * sp;
+    o[6] = ndf(q.G, q.s, d);
+    o[7] = q.albedo;
+}
+
+int launch_eval(gpss_scene* s, const float* pts, const float* dirs, float* out, uint64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, s->dev, pts, dirs,
+                       out, n);
+    return check_hip(hipGetLastError(), "eval_kernel launch");
+}
+
+}  // namespace gpss

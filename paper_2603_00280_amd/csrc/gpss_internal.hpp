@@ -1,0 +1,45 @@
+// Host-side scene object and helpers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gpss.h"
+#include "gpss_device.hpp"
+
+struct gpss_scene {
+    gpss_scene_desc desc{};            // host pointers cleared after create
+    gpss::SceneDev dev{};              // device view (pointers into the buffers below)
+    std::vector<float> prims_h, offset_h, var_h, maj_h;
+    float* d_prims = nullptr;
+    float* d_offset = nullptr;
+    float* d_var = nullptr;
+    float* d_maj = nullptr;
+    float* d_scratch = nullptr;        // per-path radiance of the last render
+    size_t scratch_floats = 0;
+    int device = 0;
+    uint32_t spp = 0;
+    uint64_t n_pixels() const { return (uint64_t)desc.width * desc.height; }
+};
+
+namespace gpss {
+
+int set_error(int code, const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+int ensure_scratch(gpss_scene* s, size_t floats);
+
+// kernel launchers (gpss_forward.hip)
+int launch_majorants(gpss_scene* s, hipStream_t stream);
+int launch_render_paths(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns,
+                        hipStream_t stream);
+int launch_reduce(gpss_scene* s, const float* paths, float* image, uint32_t ns, hipStream_t stream);
+int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* out, int kmax,
+                       hipStream_t stream);
+int launch_eval(gpss_scene* s, const float* pts, const float* dirs, float* out, uint64_t n,
+                hipStream_t stream);
+
+}  // namespace gpss

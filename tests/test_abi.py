@@ -1,0 +1,98 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry point,
+and rejects invalid scene descriptions before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from gpss_inputs import scenes as sc
+from paper_2603_00280_amd import gpss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"\b(gpss_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gpss.lib()
+    declared = _declared_symbols()
+    assert "gpss_render" in declared and "gpss_scene_create" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(gpss.EXPORTED) <= set(declared)
+
+
+def test_desc_layout_matches_header_order():
+    # the header's field order is mirrored by the ctypes structure
+    txt = open(os.path.join(ROOT, "include", "gpss.h")).read()
+    body = txt[txt.index("uint32_t struct_size;"):txt.index("} gpss_scene_desc;")]
+    hdr = re.findall(r"\b([A-Za-z_0-9]+)\s*(?:\[[0-9]+\])?\s*[;,]", re.sub(r"/\*.*?\*/", "", body,
+                                                                         flags=re.S))
+    fields = [f[0] for f in gpss.gpss_scene_desc._fields_]
+    assert hdr == fields
+
+
+def _create(scene, **mut):
+    desc, keep = gpss.make_desc(scene)
+    for k, v in mut.items():
+        setattr(desc, k, v)
+    h = ctypes.c_void_p()
+    rc = gpss.lib().gpss_scene_create(ctypes.byref(desc), ctypes.byref(h))
+    return rc, gpss.gpss_last_error()
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("struct_size", 12, "struct_size"),
+    ("mean_kind", 7, "mean_kind"),
+    ("variance", 0.0, "variance"),
+    ("variance", float("nan"), "variance"),
+    ("lengthscale", -1.0, "lengthscale"),
+    ("albedo", 1.5, "albedo"),
+    ("mix_R", -0.1, "mix_R"),
+    ("spp", 0, "spp"),
+    ("width", 0, "resolution"),
+    ("max_depth", 70000, "max_depth"),
+    ("cam_kind", 3, "cam_kind"),
+    ("cam_fov_deg", 190.0, "fov"),
+])
+def test_invalid_descriptions_are_rejected(field, value, needle):
+    rc, msg = _create(sc.sphere_scene(0.1, width=8, height=8), **{field: value})
+    assert rc == gpss.GPSS_ERR_INVALID_ARG
+    assert needle in msg
+
+
+def test_invalid_grids_and_prims_are_rejected():
+    s = sc.offset_sphere_scene(True, width=8, height=8, grid_res=8)
+    bad = s.offset_grid.copy()
+    bad[1, 2, 3] = np.nan
+    rc, msg = _create(s.replace(offset_grid=bad))
+    assert rc == gpss.GPSS_ERR_INVALID_ARG and "mean_offset" in msg
+    s3 = sc.mixed_scene(width=8, height=8, var_res=8)
+    var = s3.variance_grid.copy()
+    var[0, 0, 0] = -1.0
+    rc, msg = _create(s3.replace(variance_grid=var))
+    assert rc == gpss.GPSS_ERR_INVALID_ARG and "variance_grid" in msg
+    prims = s3.prims.copy()
+    prims[0, 4] = 0.0
+    rc, msg = _create(s3.replace(prims=prims))
+    assert rc == gpss.GPSS_ERR_INVALID_ARG and "primitive" in msg
+    rc, msg = _create(sc.sphere_scene(0.1, width=8, height=8), n_prims=0)
+    assert rc == gpss.GPSS_ERR_INVALID_ARG
+
+
+def test_null_arguments_are_rejected():
+    L = gpss.lib()
+    assert L.gpss_scene_create(None, None) == gpss.GPSS_ERR_INVALID_ARG
+    assert L.gpss_render(None, None, 0, 1, None) == gpss.GPSS_ERR_INVALID_ARG
+    assert L.gpss_render_paths(None, None, None, 0, 1, None) == gpss.GPSS_ERR_INVALID_ARG
+    assert L.gpss_scene_destroy(None) == gpss.GPSS_ERR_INVALID_ARG
+    assert L.gpss_scene_get_majorants(None, None, 0) == gpss.GPSS_ERR_INVALID_ARG

@@ -1,0 +1,154 @@
+"""GPU parity of the forward renderer against the FP64 oracle (through the C-ABI).
+
+Both sides draw the same Philox numbers, so images agree path by path up to float
+rounding, except for the rare branch flips that rounding causes (bounded below)."""
+import math
+
+import numpy as np
+import pytest
+
+from gpss_inputs import scenes as sc
+from oracle import oracle as orc
+from tests import gpu_helpers as gh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_00280_amd import gpss
+    return gpss
+
+
+def _render(G, s, s0=0, s1=None):
+    g = G.GpssScene(s)
+    img = g.render(s0, s1).cpu().numpy()
+    torch.cuda.synchronize()
+    return g, img
+
+
+def _parity(G, s, label, s0=0, s1=None):
+    s1 = s.spp if s1 is None else s1
+    print(f"[parity] {label} {s.width}x{s.height} spp[{s0},{s1}) depth {s.max_depth}", flush=True)
+    g, img = _render(G, s, s0, s1)
+    ref = orc.OracleScene(s).render(s0, s1)
+    st = gh.compare_images(img, ref, s1 - s0, label)
+    print("   ", gh.fmt(st), flush=True)
+    assert ref["counters"]["violations"] == 0
+    gh.assert_parity(st)
+    return g, img, ref
+
+
+def _small_mixed(**kw):
+    return sc.mixed_scene(**{**dict(width=48, height=48, spp=2, max_depth=64), **kw})
+
+
+def test_majorants_match_oracle_bitwise(G):
+    cases = [sc.plane_scene(), sc.sphere_scene(0.005, width=8, height=8),
+             sc.sphere_scene(0.5, width=8, height=8), sc.mixed_scene(width=8, height=8),
+             sc.offset_sphere_scene(True, width=8, height=8),
+             sc.plane_scene(majorant_res=(3, 5, 7)).replace(mean_kind=sc.MEAN_CONST, mean_const=0.1)]
+    for s in cases:
+        gm = G.GpssScene(s).majorants()
+        om = orc.OracleScene(s).majorants()
+        assert gm.shape == om.shape
+        diff = np.flatnonzero(gm.view(np.uint32) != om.view(np.uint32))
+        assert diff.size == 0, (s.name, diff[:5], gm[diff[:5]], om[diff[:5]])
+
+
+def test_medium_evaluation_matches_oracle(G):
+    rng = np.random.default_rng(0)
+    for s in (sc.plane_scene(), sc.sphere_scene(0.02, width=8, height=8),
+              sc.sphere_scene(0.5, width=8, height=8), sc.mixed_scene(width=8, height=8),
+              sc.offset_sphere_scene(True, width=8, height=8)):
+        n = 4000
+        lo, hi = s.bounds[:3], s.bounds[3:]
+        pts = (lo + rng.random((n, 3)) * (hi - lo)).astype(np.float32)
+        dirs = rng.normal(size=(n, 3))
+        dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+        out = G.GpssScene(s).eval_medium(pts, dirs).cpu().numpy().astype(np.float64)
+        o = orc.OracleScene(s)
+        worst = {}
+        for i in range(n):
+            e = o.eval_point(pts[i].astype(np.float64))
+            st = o.sigma_t(pts[i].astype(np.float64), dirs[i].astype(np.float64))
+            D = orc.ndf(e["G"], e["s"], dirs[i].astype(np.float64))
+            sp = orc.sigma_proj(e["G"], e["s"], dirs[i].astype(np.float64))
+            for name, gv, ov, scale in (("mu", out[i, 0], e["mu"], 1.0), ("sigma", out[i, 1], e["sigma"], 0),
+                                        ("proj", out[i, 4], sp, 1e-3), ("sigma_t", out[i, 5], st, 1e-3),
+                                        ("ndf", out[i, 6], D, 1e-3)):
+                err = abs(gv - ov) / max(abs(ov), scale * 1e-3 if scale else 1e-30)
+                worst[name] = max(worst.get(name, 0.0), err)
+            assert out[i, 7] == pytest.approx(e["albedo"], rel=1e-6)
+        print(s.name, {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+        assert worst["sigma"] < 5e-6
+        assert worst["proj"] < 1e-4 and worst["sigma_t"] < 1e-4 and worst["ndf"] < 1e-4
+
+
+def test_parity_plane_full_size(G):
+    """The tiny planar workload at its full size: 64x64, 16 spp, depth 8."""
+    _parity(G, sc.plane_scene(), "plane")
+
+
+def test_parity_plane_paths_and_counters(G):
+    s = sc.plane_scene()
+    g = G.GpssScene(s)
+    paths, cnt = g.render_paths(counters=True)
+    ref = orc.OracleScene(s).render(want_paths=True)
+    st = gh.compare_paths(paths.cpu().numpy(), ref["paths"])
+    c = G.counters_dict(cnt)
+    print("   paths", gh.fmt(st), flush=True)
+    print("   gpu counters", c, "\n   oracle counters", ref["counters"], flush=True)
+    assert c["violations"] == 0 and c["capped"] == 0
+    assert st["path_flip_fraction"] < 1e-3
+    for k in ("track_steps", "real", "nee_steps", "escaped", "phase", "nee"):
+        assert c[k] == pytest.approx(ref["counters"][k], rel=2e-3)
+
+
+@pytest.mark.parametrize("l", sc.SPHERE_LENGTHSCALES)
+def test_parity_sphere_reduced(G, l):
+    """Single-object sphere across the surface-to-volume lengthscale sweep, reduced size."""
+    _parity(G, sc.sphere_scene(l, width=64, height=64, spp=4), f"sphere l={l}")
+
+
+def test_parity_mixed_reduced(G):
+    """Union of 16 primitives with the full 128^3 variance grid, reduced image size."""
+    _parity(G, _small_mixed(), "mixed16")
+
+
+@pytest.mark.parametrize("target", [True, False])
+def test_parity_offset_sphere(G, target):
+    s = sc.offset_sphere_scene(target, width=64, height=64, spp=4)
+    _parity(G, s, "offset_sphere target" if target else "offset_sphere theta0")
+
+
+def test_chunked_equals_monolithic_and_deterministic(G):
+    s = sc.sphere_scene(0.1, width=40, height=24, spp=12, max_depth=8)
+    g = G.GpssScene(s)
+    full = g.render_paths(0, 12).cpu().numpy()
+    a = g.render_paths(0, 5).cpu().numpy()
+    b = g.render_paths(5, 12).cpu().numpy()
+    assert np.array_equal(np.concatenate([a, b], axis=2), full)
+    img1 = g.render().cpu().numpy()
+    img2 = g.render().cpu().numpy()
+    assert np.array_equal(img1, img2)
+    # the image is the per-pixel mean of the path radiances, in sample order
+    assert np.allclose(img1, full.mean(axis=2), rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("w,h,spp,s0", [(1, 1, 1, 0), (37, 23, 3, 2), (5, 7, 1, 9)])
+def test_ragged_and_tiny_sizes(G, w, h, spp, s0):
+    s = sc.sphere_scene(0.02, width=w, height=h, spp=spp + s0, max_depth=8)
+    _parity(G, s, f"ragged {w}x{h}", s0, s0 + spp)
+
+
+def test_white_furnace_gpu(G):
+    s = sc.plane_scene(width=32, height=32, spp=32, max_depth=64, albedo=1.0, env=1.0, light_E=0.0)
+    _, img = _render(G, s)
+    ref = orc.OracleScene(s).render()
+    tot = img.mean() + ref["trunc"].mean()
+    assert abs(tot - 1.0) < 5 * math.sqrt(ref["var"].mean() / (s.spp * s.n_pixels)) + 1e-3
