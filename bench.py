@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the GPSS forward renderer on one MI355X.
+
+Workload (default "sphere"): the single-object sphere of the lengthscale sweep -- unit
+sphere SDF mean, squared-exponential kernel variance 0.0025, lengthscales
+{0.005, 0.02, 0.1, 0.5}, albedo 0.8, point light plus constant environment, pinhole
+512x512, 64 spp, max depth 32.  One step renders all four lengthscales (4 x 16.78 M
+paths) with the scenes already resident on the GPU.
+
+Prints one JSON line: Mpaths/s, the roofline entry of the dominant kernel (algorithmic
+FP32 FLOPs per launch / the launch time measured with HIP events on the render stream),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpaths/s forward + adjoint at fixed image MSE vs oracle; % FP32 VALU peak"
+FP32_PEAK_TFLOPS = 157.3      # MI355X vector FP32 (packed); non-packed FMA issue gives 78.6
+
+WORKLOADS = {
+    "sphere": "unit-sphere SDF mean, SE kernel variance 0.0025, lengthscales 0.005/0.02/0.1/0.5, "
+              "albedo 0.8, point light + environment, pinhole 512x512, 64 spp, max depth 32",
+    "plane": "planar GPSS m(x)=z, variance 0.01, lengthscale 0.05, |z|<0.4, albedo 0.9, "
+             "directional light 30 deg, ortho 64x64 at 45 deg, 16 spp, max depth 8",
+    "mixed": "union SDF of 16 seeded spheres/boxes, 128^3 value-noise variance grid in "
+             "[1e-4,1e-2], lengthscale 0.03, 1024x1024, 256 spp, max depth 64",
+}
+
+
+def make_scenes(name):
+    from gpss_inputs import scenes as sc
+    if name == "sphere":
+        return [sc.sphere_scene(l) for l in sc.SPHERE_LENGTHSCALES]
+    if name == "plane":
+        return [sc.plane_scene()]
+    if name == "mixed":
+        return [sc.mixed_scene()]
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(scenes, spp: int):
+    """FP64 oracle on a bounded sample: every pixel of every scene at `spp` samples."""
+    from oracle.oracle import OracleScene
+    n = 0
+    t0 = time.perf_counter()
+    for s in scenes:
+        OracleScene(s).render(0, spp)
+        n += s.n_pixels * spp
+    dt = time.perf_counter() - t0
+    try:
+        import psutil
+        cores = len(psutil.Process().cpu_affinity())
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": n / dt / 1e6, "unit": "Mpaths/s", "cores": cores, "kind": "oracle",
+            "sample": f"all pixels of each scene at {spp} spp ({n} paths, {dt:.1f} s)",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sphere", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-spp", type=int, default=16, help="spp of the oracle CPU sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the renderer shards by sample range across GPUs only by design, not in this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_00280_amd import flops, gpss
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    scenes = make_scenes(args.workload)
+    gs = [gpss.GpssScene(s) for s in scenes]
+    imgs = [torch.empty(s.height, s.width, dtype=torch.float32, device=dev) for s in scenes]
+    stream = torch.cuda.current_stream()
+    print(f"[bench] workload {args.workload}: {len(scenes)} scene(s), "
+          f"{sum(s.n_paths for s in scenes) / 1e6:.1f} M paths per step", file=sys.stderr, flush=True)
+
+    # algorithmic work per launch from the event counts (deterministic: same paths)
+    work = []
+    for s, g in zip(scenes, gs):
+        _, cnt = g.render_paths(counters=True)
+        torch.cuda.synchronize()
+        c = gpss.counters_dict(cnt)
+        work.append((flops.flops_from_counters(s, c), c))
+    print("[bench] counters", [w[1] for w in work], file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        for g, im in zip(gs, imgs):
+            g.render(out=im)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for g, im in zip(gs, imgs):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g.render(out=im)
+            e1.record(stream)
+            evs.append((e0, e1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    paths = args.steps * sum(s.n_paths for s in scenes)
+    launch_ms = [a.elapsed_time(b) for a, b in evs]
+    per_scene_ms = [sum(launch_ms[i::len(scenes)]) / args.steps for i in range(len(scenes))]
+    # roofline of the render kernel: algorithmic FLOPs of each launch / its duration
+    flop_rate = sum(w[0] for w in work) / (sum(per_scene_ms) / 1e3)
+    avg_launch_ms = sum(launch_ms) / len(launch_ms)
+    result = {
+        "metric": METRIC,
+        "value": paths / wall / 1e6,
+        "unit": "Mpaths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload + ": " + WORKLOADS[args.workload],
+                   "paths_per_step": sum(s.n_paths for s in scenes), "kernel": "render_paths_kernel"},
+        "roofline": {"bound": "alu", "achieved": flop_rate / 1e12, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flop_rate / 1e12 / FP32_PEAK_TFLOPS, "traffic": None,
+                     "avg_launch_ms": avg_launch_ms,
+                     "flops_per_launch": [w[0] for w in work]},
+        "per_scene_mpaths_s": [s.n_paths / (ms / 1e3) / 1e6 for s, ms in zip(scenes, per_scene_ms)],
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the CPU", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(scenes, args.cpu_spp)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -642,6 +642,7 @@ T ratio_track(const Params<double>& P0, const Params<T>& P1, bool frozen, const 
     T Tr1 = T(1.0);
     double tau = -std::log(1.0 - rng.uniform());
     int64_t steps = 0;
+    C.c[ORC_C_CELLS]++;
     for (;;) {
         int ax;
         const double tn = w.exit(ax);
@@ -669,6 +670,7 @@ T ratio_track(const Params<double>& P0, const Params<T>& P1, bool frozen, const 
         t = tc;
         if (tn >= t1) break;
         if (!w.step(ax)) break;
+        C.c[ORC_C_CELLS]++;
     }
     if (frozen) return Tr1;
     return T(Tr0);

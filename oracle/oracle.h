@@ -70,7 +70,7 @@ enum {
     ORC_C_CAPPED = 4,       /* segments that hit the step cap */
     ORC_C_ESCAPED = 5,      /* paths that left the medium */
     ORC_C_TRUNCATED = 6,    /* paths stopped by the depth limit */
-    ORC_C_CELLS = 7,        /* majorant cells visited during tracking */
+    ORC_C_CELLS = 7,        /* majorant cells visited by delta and ratio tracking */
     ORC_C_PHASE = 8,        /* phase-function samples */
     ORC_C_NEE = 9,          /* next-event estimates (light connections) */
     ORC_C_COUNT = 16

@@ -445,29 +445,45 @@ __device__ __forceinline__ bool clip_box(const SceneDev& S, D3 o, D3 d, double& 
     return t0 < t1;
 }
 
+// Majorant-grid walker (3D DDA).  Boundary distances are computed once per segment with
+// one reciprocal per axis and then advanced by the per-axis cell width in distance.
 struct Walker {
-    D3 o, d;
     int ix, iy, iz;
-    __device__ __forceinline__ void init(const SceneDev& S, D3 o_, D3 d_, double t) {
-        o = o_;
-        d = d_;
+    double tx, ty, tz;      // distance to the next boundary on each axis
+    double dtx, dty, dtz;   // distance between successive boundaries on each axis
+    int sx, sy, sz;
+    __device__ __forceinline__ void init(const SceneDev& S, D3 o, D3 d, double t) {
         const D3 p = o + t * d;
         ix = min(max((int)floor((p.x - S.lo_d[0]) * S.inv_cw_d[0]), 0), S.M[0] - 1);
         iy = min(max((int)floor((p.y - S.lo_d[1]) * S.inv_cw_d[1]), 0), S.M[1] - 1);
         iz = min(max((int)floor((p.z - S.lo_d[2]) * S.inv_cw_d[2]), 0), S.M[2] - 1);
+        axis(S.lo_d[0], S.cw_d[0], o.x, d.x, ix, tx, dtx, sx);
+        axis(S.lo_d[1], S.cw_d[1], o.y, d.y, iy, ty, dty, sy);
+        axis(S.lo_d[2], S.cw_d[2], o.z, d.z, iz, tz, dtz, sz);
+    }
+    __device__ __forceinline__ static void axis(double lo, double cw, double o, double d, int i, double& tn,
+                                                double& dt, int& s) {
+        if (d > 0.0) {
+            const double inv = 1.0 / d;
+            tn = (lo + (double)(i + 1) * cw - o) * inv;
+            dt = cw * inv;
+            s = 1;
+        } else if (d < 0.0) {
+            const double inv = 1.0 / d;
+            tn = (lo + (double)i * cw - o) * inv;
+            dt = -cw * inv;
+            s = -1;
+        } else {
+            tn = INFINITY;
+            dt = 0.0;
+            s = 0;
+        }
     }
     __device__ __forceinline__ float majorant(const SceneDev& S) const {
         return S.maj[(iz * S.M[1] + iy) * S.M[0] + ix];
     }
     // distance along the ray to the exit of the current cell and the axis crossed
-    __device__ __forceinline__ double exit(const SceneDev& S, int& ax) const {
-        double tx = INFINITY, ty = INFINITY, tz = INFINITY;
-        if (d.x > 0.0) tx = (S.lo_d[0] + (double)(ix + 1) * S.cw_d[0] - o.x) / d.x;
-        else if (d.x < 0.0) tx = (S.lo_d[0] + (double)ix * S.cw_d[0] - o.x) / d.x;
-        if (d.y > 0.0) ty = (S.lo_d[1] + (double)(iy + 1) * S.cw_d[1] - o.y) / d.y;
-        else if (d.y < 0.0) ty = (S.lo_d[1] + (double)iy * S.cw_d[1] - o.y) / d.y;
-        if (d.z > 0.0) tz = (S.lo_d[2] + (double)(iz + 1) * S.cw_d[2] - o.z) / d.z;
-        else if (d.z < 0.0) tz = (S.lo_d[2] + (double)iz * S.cw_d[2] - o.z) / d.z;
+    __device__ __forceinline__ double exit(int& ax) const {
         ax = 0;
         double best = tx;
         if (ty < best) { best = ty; ax = 1; }
@@ -475,9 +491,10 @@ struct Walker {
         return best;
     }
     __device__ __forceinline__ bool step(const SceneDev& S, int ax) {
-        if (ax == 0) { ix += d.x > 0.0 ? 1 : -1; return ix >= 0 && ix < S.M[0]; }
-        if (ax == 1) { iy += d.y > 0.0 ? 1 : -1; return iy >= 0 && iy < S.M[1]; }
-        iz += d.z > 0.0 ? 1 : -1;
+        if (ax == 0) { ix += sx; tx += dtx; return ix >= 0 && ix < S.M[0]; }
+        if (ax == 1) { iy += sy; ty += dty; return iy >= 0 && iy < S.M[1]; }
+        iz += sz;
+        tz += dtz;
         return iz >= 0 && iz < S.M[2];
     }
 };

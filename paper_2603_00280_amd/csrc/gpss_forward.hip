@@ -181,8 +181,13 @@ __device__ __forceinline__ void flush_stats(const PathStats& st, unsigned long l
     }
 }
 
+// Minimum waves per SIMD the one-thread-per-path kernel is compiled for (register budget).
+#ifndef GPSS_MEGA_MIN_WAVES
+#define GPSS_MEGA_MIN_WAVES 4
+#endif
+
 template <bool STATS>
-__global__ __launch_bounds__(256) void render_paths_kernel(SceneDev S, float* __restrict__ paths,
+__global__ __launch_bounds__(256, GPSS_MEGA_MIN_WAVES) void render_paths_kernel(SceneDev S, float* __restrict__ paths,
                                                            unsigned long long* counters, uint32_t s0,
                                                            uint32_t ns, uint64_t npaths) {
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

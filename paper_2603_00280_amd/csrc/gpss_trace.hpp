@@ -23,7 +23,7 @@ __device__ __forceinline__ int delta_track(const SceneDev& S, D3 o, D3 d, float3
     if (STATS) st.cells++;
     for (;;) {
         int ax;
-        const double tn = w.exit(S, ax);
+        const double tn = w.exit(ax);
         const double tc = fmin(tn, t1);
         const float maj = w.majorant(S);
         const double seg = fmax(0.0, tc - t);
@@ -65,9 +65,10 @@ __device__ __forceinline__ float ratio_track(const SceneDev& S, D3 o, D3 d, floa
     float Tr = 1.0f;
     double tau = -(double)logf(1.0f - rng.uniform());
     int steps = 0;
+    if (STATS) st.cells++;
     for (;;) {
         int ax;
-        const double tn = w.exit(S, ax);
+        const double tn = w.exit(ax);
         const double tc = fmin(tn, t1);
         const float maj = w.majorant(S);
         const double seg = fmax(0.0, tc - t);
@@ -91,6 +92,7 @@ __device__ __forceinline__ float ratio_track(const SceneDev& S, D3 o, D3 d, floa
         t = tc;
         if (tn >= t1) break;
         if (!w.step(S, ax)) break;
+        if (STATS) st.cells++;
     }
     return Tr;
 }
