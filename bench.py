@@ -74,6 +74,10 @@ def main():
     ap.add_argument("--workload", default="sphere", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-spp", type=int, default=16, help="spp of the oracle CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "mega", "wavefront"],
+                    help="tracer form timed for the headline value")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time one step of the other tracer form")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -88,7 +92,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     scenes = make_scenes(args.workload)
-    gs = [gpss.GpssScene(s) for s in scenes]
+    gs = [gpss.GpssScene(s, kernel=args.kernel) for s in scenes]
     imgs = [torch.empty(s.height, s.width, dtype=torch.float32, device=dev) for s in scenes]
     stream = torch.cuda.current_stream()
     print(f"[bench] workload {args.workload}: {len(scenes)} scene(s), "
@@ -143,13 +147,25 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + WORKLOADS[args.workload],
-                   "paths_per_step": sum(s.n_paths for s in scenes), "kernel": "render_paths_kernel"},
+                   "paths_per_step": sum(s.n_paths for s in scenes),
+                   "tracer": "one thread per path" if args.kernel == "mega" else "wavefront"},
         "roofline": {"bound": "alu", "achieved": flop_rate / 1e12, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flop_rate / 1e12 / FP32_PEAK_TFLOPS, "traffic": None,
                      "avg_launch_ms": avg_launch_ms,
                      "flops_per_launch": [w[0] for w in work]},
         "per_scene_mpaths_s": [s.n_paths / (ms / 1e3) / 1e6 for s, ms in zip(scenes, per_scene_ms)],
     }
+    if args.compare:
+        other = "mega" if args.kernel != "mega" else "wavefront"
+        for g in gs:
+            g.set_kernel(other)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g, im in zip(gs, imgs):
+            g.render(out=im)
+        torch.cuda.synchronize()
+        result["compare"] = {"tracer": other,
+                             "mpaths_s": sum(s.n_paths for s in scenes) / (time.perf_counter() - t0) / 1e6}
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the CPU", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(scenes, args.cpu_spp)

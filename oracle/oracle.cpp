@@ -570,7 +570,10 @@ struct Walker {
 };
 
 constexpr int64_t kStepCap = 1 << 16;
-constexpr double kTrCutoff = 0x1p-40;
+// Russian roulette on shadow-ray transmittance (as in the null-scattering path tracer of
+// the paper's implementation platform): below kRRThreshold the estimate survives with
+// probability 1/2 and is doubled.
+constexpr double kRRThreshold = 0.0625;
 
 template <class T>
 T sigma_t_of(const PointQ<T>& q, const double d[3]) { return rho_of(q.mu, q.sigma) * sigma_proj(q, d); }
@@ -631,7 +634,8 @@ int delta_track(const Params<double>& P0, const Params<T>& P1, bool frozen, cons
 }
 
 // Ratio tracking transmittance along [0, t1]: product of (1 - sigma_t / majorant) over
-// tentative collisions, one uniform each; stops at 0 once below kTrCutoff.
+// tentative collisions (one uniform each for the free flight), with Russian roulette once
+// the product falls below kRRThreshold (one more uniform).
 template <class T>
 T ratio_track(const Params<double>& P0, const Params<T>& P1, bool frozen, const double o[3],
               const double d[3], double t1, Rng& rng, Counters& C) {
@@ -662,7 +666,11 @@ T ratio_track(const Params<double>& P0, const Params<T>& P1, bool frozen, const 
                 const PointQ<T> q1 = eval_point(P1, x);
                 Tr1 = Tr1 * (1.0 - sigma_t_of(q1, d) / maj);
             }
-            if (Tr0 < kTrCutoff) return T(0.0);
+            if (Tr0 < kRRThreshold) {
+                if (rng.uniform() < 0.5) return T(0.0);
+                Tr0 *= 2.0;
+                Tr1 = Tr1 * 2.0;
+            }
             tau = -std::log(1.0 - rng.uniform());
             continue;
         }

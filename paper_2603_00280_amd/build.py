@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpss.so")
-SOURCES = ["gpss_api.hip", "gpss_forward.hip"]
+SOURCES = ["gpss_api.hip", "gpss_forward.hip", "gpss_wavefront.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GPSS_OFFLOAD_ARCH", "gfx950")
 
@@ -14,6 +14,9 @@ FLAGS = [
     "-std=c++17", "-O3", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse multiply-adds only within a source expression: the one-thread-per-path and the
+    # wavefront kernels then round every shared computation identically
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 

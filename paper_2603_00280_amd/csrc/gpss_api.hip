@@ -35,6 +35,55 @@ int check_hip(hipError_t e, const char* what) {
     return set_error(GPSS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+int ensure_wavefront(gpss_scene* s, uint64_t npaths) {
+    if (s->wf_cap >= npaths && s->wf_mem) return GPSS_OK;
+    if (s->wf_mem) {
+        int rc = check_hip(hipFree(s->wf_mem), "hipFree(wavefront)");
+        s->wf_mem = nullptr;
+        s->wf_cap = 0;
+        if (rc) return rc;
+    }
+    // 6 doubles + 3 floats + 1 word + 6 floats + 5 queue words per path, plus counters
+    const uint64_t n = npaths;
+    const size_t bytes = n * (6 * 8 + 3 * 4 + 4 + 6 * 4 + 5 * 4) + 256 + 64 * 16;
+    int rc = check_hip(hipMalloc(&s->wf_mem, bytes), "hipMalloc(wavefront)");
+    if (rc) return rc;
+    char* m = static_cast<char*>(s->wf_mem);
+    auto take = [&m](size_t b) {
+        char* r = m;
+        m += (b + 255) & ~size_t(255);
+        return r;
+    };
+    WfState& W = s->wf;
+    W.ox = reinterpret_cast<double*>(take(8 * n));
+    W.oy = reinterpret_cast<double*>(take(8 * n));
+    W.oz = reinterpret_cast<double*>(take(8 * n));
+    W.dx = reinterpret_cast<double*>(take(8 * n));
+    W.dy = reinterpret_cast<double*>(take(8 * n));
+    W.dz = reinterpret_cast<double*>(take(8 * n));
+    W.beta = reinterpret_cast<float*>(take(4 * n));
+    W.L = reinterpret_cast<float*>(take(4 * n));
+    W.bounce = reinterpret_cast<uint32_t*>(take(4 * n));
+    W.nee_c = reinterpret_cast<float*>(take(8 * n));
+    W.nee_bp = reinterpret_cast<float*>(take(8 * n));
+    W.nee_le = reinterpret_cast<float*>(take(8 * n));
+    W.q_a = reinterpret_cast<uint32_t*>(take(4 * n));
+    W.q_b = reinterpret_cast<uint32_t*>(take(4 * n));
+    W.q_scatter = reinterpret_cast<uint32_t*>(take(4 * n));
+    W.q_nee = reinterpret_cast<uint32_t*>(take(8 * n));
+    W.cnt = reinterpret_cast<uint32_t*>(take(4 * kQNum));
+    W.out = nullptr;
+    s->wf_cap = npaths;
+    if (!s->wf_grid) {
+        int cus = 0;
+        rc = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device),
+                       "hipDeviceGetAttribute");
+        if (rc) return rc;
+        s->wf_grid = (uint32_t)(cus > 0 ? cus : 1) * 4u;
+    }
+    return GPSS_OK;
+}
+
 int ensure_scratch(gpss_scene* s, size_t floats) {
     if (s->scratch_floats >= floats) return GPSS_OK;
     if (s->d_scratch) {
@@ -53,6 +102,8 @@ int ensure_scratch(gpss_scene* s, size_t floats) {
 
 using gpss::check_hip;
 using gpss::set_error;
+using gpss::WfState;
+using gpss::kQNum;
 
 namespace {
 
@@ -141,6 +192,7 @@ void free_scene(gpss_scene* s) {
     (void)hipFree(s->d_var);
     (void)hipFree(s->d_maj);
     (void)hipFree(s->d_scratch);
+    (void)hipFree(s->wf_mem);
     delete s;
 }
 
@@ -278,6 +330,14 @@ int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out) {
 int gpss_scene_destroy(gpss_scene_t scene) {
     if (!scene) return set_error(GPSS_ERR_INVALID_ARG, "scene is NULL");
     free_scene(scene);
+    return GPSS_OK;
+}
+
+int gpss_scene_set_kernel(gpss_scene_t scene, int32_t kernel) {
+    if (!scene) return set_error(GPSS_ERR_INVALID_ARG, "scene is NULL");
+    if (kernel != GPSS_KERNEL_AUTO && kernel != GPSS_KERNEL_MEGA && kernel != GPSS_KERNEL_WAVEFRONT)
+        return set_error(GPSS_ERR_INVALID_ARG, "unknown kernel %d", kernel);
+    scene->kernel = kernel;
     return GPSS_OK;
 }
 

@@ -21,7 +21,7 @@ constexpr float kSqrt2 = 1.41421356237309504880f;
 
 constexpr int kMaxPrims = 64;
 constexpr int kStepCap = 1 << 16;           // tentative collisions per segment
-constexpr float kTrCutoff = 0x1p-40f;       // ratio tracking stops (returns 0) below this
+constexpr float kRRThreshold = 0.0625f;     // shadow-ray Russian roulette below this transmittance
 
 enum : uint32_t { kStreamCam = 0, kStreamTrack = 1, kStreamPhase = 2, kStreamNee0 = 3 };
 
@@ -89,6 +89,18 @@ __device__ __forceinline__ double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y
 __device__ __forceinline__ D3 normalize(D3 a) { return (1.0 / sqrt(dot(a, a))) * a; }
 __device__ __forceinline__ float3 to_f3(D3 a) { return make_float3((float)a.x, (float)a.y, (float)a.z); }
 __device__ __forceinline__ double comp(D3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+
+// Single roundings that the compiler may not fuse into neighbouring operations: the
+// radiance and throughput accumulations use them so that the one-thread-per-path and the
+// wavefront kernels (which store these values between kernels) round identically.
+__device__ __forceinline__ float add_rn(float a, float b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+__device__ __forceinline__ float mul_rn(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
 
 // Orthonormal basis around unit n (Duff et al., JCGT 2017).
 __device__ __forceinline__ void onb(float3 n, float3& t, float3& b) {

@@ -201,8 +201,8 @@ __global__ __launch_bounds__(256, GPSS_MEGA_MIN_WAVES) void render_paths_kernel(
     if (STATS) flush_stats(st, counters);
 }
 
-int launch_render_paths(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns,
-                        hipStream_t stream) {
+int mega_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns,
+                hipStream_t stream) {
     const uint64_t npaths = s->n_pixels() * ns;
     const uint64_t blocks = (npaths + 255) / 256;
     if (blocks > 0x7FFFFFFFull) return set_error(GPSS_ERR_INVALID_ARG, "too many paths in one launch");
@@ -231,6 +231,12 @@ int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* ou
                        hipStream_t stream) {
     hipLaunchKernelGGL(debug_trace_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, s->dev, ids, n, out, kmax);
     return check_hip(hipGetLastError(), "debug_trace_kernel launch");
+}
+
+int launch_render_paths(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns,
+                        hipStream_t stream) {
+    if (s->kernel == GPSS_KERNEL_MEGA) return mega_render(s, paths, counters, s0, ns, stream);
+    return wf_render(s, paths, counters, s0, ns, stream);
 }
 
 // Per-pixel mean over the sample range, summed in sample order (deterministic).

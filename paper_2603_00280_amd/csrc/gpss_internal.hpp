@@ -11,6 +11,21 @@
 #include "../../include/gpss.h"
 #include "gpss_device.hpp"
 
+namespace gpss {
+// Structure-of-arrays path state and queues of the wavefront tracer (device pointers).
+struct WfState {
+    double *ox, *oy, *oz, *dx, *dy, *dz;   // ray origin (collision point after track) and direction
+    float *beta, *L, *out;                 // throughput, radiance so far, final radiance per slot
+    uint32_t* bounce;                      // real collisions so far (high bit: path ended)
+    float *nee_c, *nee_bp, *nee_le;        // per slot and light: contribution, beta*phase, Le
+    uint32_t *q_a, *q_b, *q_scatter, *q_nee;
+    uint32_t* cnt;                         // queue counters, indexed by kQ*
+    uint32_t s0, ns;
+    uint64_t npaths;
+};
+enum { kQInCount = 0, kQInHead, kQOutCount, kQScatterCount, kQScatterHead, kQNeeCount, kQNeeHead, kQNum };
+}  // namespace gpss
+
 struct gpss_scene {
     gpss_scene_desc desc{};            // host pointers cleared after create
     gpss::SceneDev dev{};              // device view (pointers into the buffers below)
@@ -23,6 +38,11 @@ struct gpss_scene {
     size_t scratch_floats = 0;
     int device = 0;
     uint32_t spp = 0;
+    int kernel = 0;                    // GPSS_KERNEL_*
+    gpss::WfState wf{};                // wavefront buffers (allocated on first use)
+    void* wf_mem = nullptr;
+    uint64_t wf_cap = 0;               // paths the wavefront buffers hold
+    uint32_t wf_grid = 0;              // persistent workgroups per wavefront launch
     uint64_t n_pixels() const { return (uint64_t)desc.width * desc.height; }
 };
 
@@ -37,6 +57,9 @@ int launch_majorants(gpss_scene* s, hipStream_t stream);
 int launch_render_paths(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns,
                         hipStream_t stream);
 int launch_reduce(gpss_scene* s, const float* paths, float* image, uint32_t ns, hipStream_t stream);
+int ensure_wavefront(gpss_scene* s, uint64_t npaths);
+int wf_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
+int mega_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
 int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* out, int kmax,
                        hipStream_t stream);
 int launch_eval(gpss_scene* s, const float* pts, const float* dirs, float* out, uint64_t n,

@@ -8,93 +8,117 @@
 namespace gpss {
 
 enum TrackResult : int { kEscape = 0, kCollide = 1, kAbsorbed = 2 };
+enum WalkEvent : int { kCell = 0, kTentative = 1, kEnd = 2 };
 
-// Delta tracking over [t0, t1]: per tentative collision an optical depth tau = -ln(1 - u1)
-// is consumed cell by cell through the majorant grid; the collision is real iff
-// u2 * majorant < sigma_t.
+// Free-flight walk of one segment [t0, t1] of a ray through the majorant grid: tentative
+// collisions of the null-scattering process with the piecewise-constant majorant, an
+// optical depth tau = -ln(1 - u) being consumed cell by cell per tentative collision.
+struct Segment {
+    D3 o, d;
+    double t, t1, tau;
+    Walker w;
+    float maj;      // majorant of the cell holding the current tentative collision
+    int steps;      // tentative collisions so far
+    template <bool STATS>
+    __device__ __forceinline__ void begin(const SceneDev& S, D3 o_, D3 d_, double t0, double t1_, Rng& rng,
+                                          PathStats& st) {
+        o = o_;
+        d = d_;
+        t = t0;
+        t1 = t1_;
+        w.init(S, o, d, t0);
+        tau = -(double)logf(1.0f - rng.uniform());
+        steps = 0;
+        if (STATS) st.cells++;
+    }
+    __device__ __forceinline__ void redraw(Rng& rng) { tau = -(double)logf(1.0f - rng.uniform()); }
+    __device__ __forceinline__ float3 pos() const { return to_f3(o + t * d); }
+    // One event of the walk: reach the next tentative collision in the current cell
+    // (kTentative; t and maj updated), cross into the next cell (kCell), or reach the end of
+    // the segment (kEnd).  Callers loop over events, so that lanes of a wave crossing cells
+    // and lanes evaluating collisions progress in the same iterations.
+    template <bool STATS>
+    __device__ __forceinline__ int step(const SceneDev& S, PathStats& st) {
+        int ax;
+        const double tn = w.exit(ax);
+        const double tc = fmin(tn, t1);
+        const float m = w.majorant(S);
+        const double seg = fmax(0.0, tc - t);
+        if (m > 0.0f && tau < (double)m * seg) {
+            t += tau / (double)m;
+            maj = m;
+            return kTentative;
+        }
+        if (m > 0.0f) tau -= (double)m * seg;
+        t = tc;
+        if (tn >= t1) return kEnd;
+        if (!w.step(S, ax)) return kEnd;
+        if (STATS) st.cells++;
+        return kCell;
+    }
+};
+
+// Delta tracking over [t0, t1]: the tentative collision is real iff u2 * majorant < sigma_t.
 template <bool STATS>
 __device__ __forceinline__ int delta_track(const SceneDev& S, D3 o, D3 d, float3 df, double t0, double t1,
                                            Rng& rng, double& t_hit, PathStats& st) {
-    Walker w;
-    w.init(S, o, d, t0);
-    double t = t0;
-    double tau = -(double)logf(1.0f - rng.uniform());
-    int steps = 0;
-    if (STATS) st.cells++;
+    Segment sg;
+    sg.begin<STATS>(S, o, d, t0, t1, rng, st);
     for (;;) {
-        int ax;
-        const double tn = w.exit(ax);
-        const double tc = fmin(tn, t1);
-        const float maj = w.majorant(S);
-        const double seg = fmax(0.0, tc - t);
-        if (maj > 0.0f && tau < (double)maj * seg) {
-            t += tau / (double)maj;
-            const float3 x = to_f3(o + t * d);
-            if (STATS) st.track_steps++;
-            if (++steps > kStepCap) {
-                if (STATS) st.capped++;
-                return kAbsorbed;
-            }
-            const float u2 = rng.uniform();
-            const PointQ q = eval_point(S, x);
-            const float sig = sigma_t_of(q, df);
-            if (STATS && sig > maj) st.violations++;
-            if (u2 * maj < sig) {
-                t_hit = t;
-                return kCollide;
-            }
-            tau = -(double)logf(1.0f - rng.uniform());
-            continue;
+        const int ev = sg.step<STATS>(S, st);
+        if (ev == kCell) continue;
+        if (ev == kEnd) return kEscape;
+        if (STATS) st.track_steps++;
+        if (++sg.steps > kStepCap) {
+            if (STATS) st.capped++;
+            return kAbsorbed;
         }
-        if (maj > 0.0f) tau -= (double)maj * seg;
-        t = tc;
-        if (tn >= t1) return kEscape;
-        if (!w.step(S, ax)) return kEscape;
-        if (STATS) st.cells++;
+        const float u2 = rng.uniform();
+        const PointQ q = eval_point(S, sg.pos());
+        const float sig = sigma_t_of(q, df);
+        if (STATS && sig > sg.maj) st.violations++;
+        if (u2 * sg.maj < sig) {
+            t_hit = sg.t;
+            return kCollide;
+        }
+        sg.redraw(rng);
     }
 }
 
+// Russian roulette on a shadow ray's running transmittance: below kRRThreshold it survives
+// with probability 1/2 (one uniform) and is doubled.  Returns false when terminated.
+__device__ __forceinline__ bool roulette(float& Tr, Rng& rng) {
+    if (Tr < kRRThreshold) {
+        if (rng.uniform() < 0.5f) return false;
+        Tr = Tr * 2.0f;
+    }
+    return true;
+}
+
 // Ratio tracking transmittance over [0, t1]: product of (1 - sigma_t / majorant) at
-// tentative collisions (one uniform each), 0 once below kTrCutoff.
+// tentative collisions (one uniform each for the free flight), with Russian roulette.
 template <bool STATS>
 __device__ __forceinline__ float ratio_track(const SceneDev& S, D3 o, D3 d, float3 df, double t1, Rng& rng,
                                              PathStats& st) {
-    Walker w;
-    w.init(S, o, d, 0.0);
-    double t = 0.0;
+    Segment sg;
+    sg.begin<STATS>(S, o, d, 0.0, t1, rng, st);
     float Tr = 1.0f;
-    double tau = -(double)logf(1.0f - rng.uniform());
-    int steps = 0;
-    if (STATS) st.cells++;
     for (;;) {
-        int ax;
-        const double tn = w.exit(ax);
-        const double tc = fmin(tn, t1);
-        const float maj = w.majorant(S);
-        const double seg = fmax(0.0, tc - t);
-        if (maj > 0.0f && tau < (double)maj * seg) {
-            t += tau / (double)maj;
-            const float3 x = to_f3(o + t * d);
-            if (STATS) st.nee_steps++;
-            if (++steps > kStepCap) {
-                if (STATS) st.capped++;
-                return 0.0f;
-            }
-            const PointQ q = eval_point(S, x);
-            const float sig = sigma_t_of(q, df);
-            if (STATS && sig > maj) st.violations++;
-            Tr *= 1.0f - sig / maj;
-            if (Tr < kTrCutoff) return 0.0f;
-            tau = -(double)logf(1.0f - rng.uniform());
-            continue;
+        const int ev = sg.step<STATS>(S, st);
+        if (ev == kCell) continue;
+        if (ev == kEnd) return Tr;
+        if (STATS) st.nee_steps++;
+        if (++sg.steps > kStepCap) {
+            if (STATS) st.capped++;
+            return 0.0f;
         }
-        if (maj > 0.0f) tau -= (double)maj * seg;
-        t = tc;
-        if (tn >= t1) break;
-        if (!w.step(S, ax)) break;
-        if (STATS) st.cells++;
+        const PointQ q = eval_point(S, sg.pos());
+        const float sig = sigma_t_of(q, df);
+        if (STATS && sig > sg.maj) st.violations++;
+        Tr *= 1.0f - sig / sg.maj;
+        if (!roulette(Tr, rng)) return 0.0f;
+        sg.redraw(rng);
     }
-    return Tr;
 }
 
 __device__ __forceinline__ void camera_ray(const SceneDev& S, uint32_t pixel, float ux, float uy, D3& o, D3& d) {
@@ -139,6 +163,31 @@ __device__ __forceinline__ bool light_sample(const SceneDev& S, int li, D3 x, D3
     return true;
 }
 
+// Phase-function sampling at a real collision (Sec. 4.2.2 proposal): draws (select, a, b)
+// from the PHASE stream, returns the scattered direction and the throughput weight
+// albedo <v, w_m> D(w_m) / (sigma(d) pdf(w_m)); false for a degenerate sample.
+__device__ __forceinline__ bool sample_scatter(const SceneDev& S, const PointQ& q, D3 d, float3 df, Rng& rng,
+                                               D3& wi, float& wgt, float3& wm, float& pdf) {
+    const float3 v = -df;
+    const Proposal prop = make_proposal(q, S.R, v);
+    const float usel = rng.uniform();
+    const uint32_t ua = rng.next24(), ub = rng.next24();
+    wm = sample_half_vector(prop, v, usel, ua, ub);
+    pdf = mixture_pdf(prop, v, wm);
+    const float vm = dot(v, wm);
+    if (!(pdf > 0.0f) || !(vm > 0.0f)) return false;
+    const D3 wmd = d3(wm);
+    const D3 vd = -d;
+    wi = normalize((2.0 * dot(vd, wmd)) * wmd - vd);
+    wgt = q.albedo * vm * ndf(q.G, q.s, wm) / (sigma_proj(q.G, q.s, df) * pdf);
+    return true;
+}
+
+// Radiance added by one light connection: ((beta * phase) * Tr) * Le.
+__device__ __forceinline__ float nee_contribution(float beta_phase, float Tr, float Le) {
+    return mul_rn(mul_rn(beta_phase, Tr), Le);
+}
+
 // Per-vertex record of a traced path (diagnostics): kRecFields floats per real collision.
 constexpr int kRecFields = 16;
 
@@ -158,7 +207,7 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
     for (;;) {
         double t0, t1;
         if (!clip_box(S, o, d, t0, t1)) {
-            L += beta * S.env;
+            L = add_rn(L, mul_rn(beta, S.env));
             if (STATS) st.escaped++;
             break;
         }
@@ -166,11 +215,11 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         double th = 0.0;
         const uint32_t steps_before = st.track_steps;
         const float3 df = to_f3(d);
-        const int res = delta_track<STATS || REC>(S, o, d, df, t0, t1, rng, th, st);
+                const int res = delta_track<STATS || REC>(S, o, d, df, t0, t1, rng, th, st);
         float* r = (REC && b < kmax) ? rec + b * kRecFields : nullptr;
         if (res == kAbsorbed) break;
         if (res == kEscape) {
-            L += beta * S.env;
+            L = add_rn(L, mul_rn(beta, S.env));
             if (STATS) st.escaped++;
             break;
         }
@@ -198,26 +247,18 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
             const float p = phase_eval(q, df, wlf);
             Rng rn;
             rn.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
-            const float Tr = ratio_track<STATS>(S, x, wl, wlf, tend, rn, st);
-            L += beta * p * Tr * Le;
+                        const float Tr = ratio_track<STATS>(S, x, wl, wlf, tend, rn, st);
+            L = add_rn(L, nee_contribution(mul_rn(beta, p), Tr, Le));
             if (REC && r) { r[5 + 2 * li] = p; r[6 + 2 * li] = Tr; }
         }
         // phase sampling
-        const float3 v = -df;
-        const Proposal prop = make_proposal(q, S.R, v);
         rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamPhase);
-        const float usel = rng.uniform();
-        const uint32_t ua = rng.next24(), ub = rng.next24();
-        const float3 wm = sample_half_vector(prop, v, usel, ua, ub);
-        const float pdf = mixture_pdf(prop, v, wm);
-        const float vm = dot(v, wm);
+        D3 wi;
+        float wgt, pdf;
+        float3 wm;
         if (STATS) st.phase++;
-        if (!(pdf > 0.0f) || !(vm > 0.0f)) break;  // degenerate sample: the path ends
-        const D3 wmd = d3(wm);
-        const D3 vd = -d;
-        const D3 wi = normalize((2.0 * dot(vd, wmd)) * wmd - vd);
-        const float wgt = q.albedo * vm * ndf(q.G, q.s, wm) / (sigma_proj(q.G, q.s, df) * pdf);
-        beta *= wgt;
+        if (!sample_scatter(S, q, d, df, rng, wi, wgt, wm, pdf)) break;  // degenerate: the path ends
+        beta = mul_rn(beta, wgt);
         if (REC && r) {
             r[9] = wm.x; r[10] = wm.y; r[11] = wm.z; r[12] = pdf; r[13] = wgt; r[14] = beta; r[15] = L;
         }

@@ -25,7 +25,10 @@ COUNTER_NAMES = ["track_steps", "real", "nee_steps", "violations", "capped", "es
                  "truncated", "cells", "phase", "nee"]
 
 EXPORTED = ["gpss_scene_create", "gpss_scene_destroy", "gpss_scene_get_majorants", "gpss_render",
-            "gpss_render_paths", "gpss_eval_medium", "gpss_debug_trace", "gpss_last_error"]
+            "gpss_render_paths", "gpss_eval_medium", "gpss_debug_trace", "gpss_scene_set_kernel",
+            "gpss_last_error"]
+GPSS_KERNEL_AUTO, GPSS_KERNEL_MEGA, GPSS_KERNEL_WAVEFRONT = 0, 1, 2
+KERNELS = {"auto": GPSS_KERNEL_AUTO, "mega": GPSS_KERNEL_MEGA, "wavefront": GPSS_KERNEL_WAVEFRONT}
 REC_FIELDS = 16
 
 
@@ -72,6 +75,7 @@ def lib():
         L.gpss_render_paths.argtypes = [vp, vp, vp, C.c_uint32, C.c_uint32, vp]
         L.gpss_eval_medium.argtypes = [vp, vp, vp, vp, C.c_uint64, vp]
         L.gpss_debug_trace.argtypes = [vp, vp, C.c_uint32, vp, C.c_uint32, vp]
+        L.gpss_scene_set_kernel.argtypes = [vp, C.c_int32]
         L.gpss_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name != "gpss_last_error":
@@ -177,6 +181,10 @@ def gpss_eval_medium(handle: int, pts_ptr: int, dirs_ptr: int, out_ptr: int, n: 
     _check(lib().gpss_eval_medium(handle, pts_ptr, dirs_ptr, out_ptr, n, _stream_ptr(stream)))
 
 
+def gpss_scene_set_kernel(handle: int, kernel: int) -> None:
+    _check(lib().gpss_scene_set_kernel(handle, kernel))
+
+
 def gpss_debug_trace(handle: int, ids_ptr: int, n: int, out_ptr: int, kmax: int, stream=None):
     _check(lib().gpss_debug_trace(handle, ids_ptr, n, out_ptr, kmax, _stream_ptr(stream)))
 
@@ -187,7 +195,7 @@ def gpss_debug_trace(handle: int, ids_ptr: int, n: int, out_ptr: int, kmax: int,
 class GpssScene:
     """A scene created in libgpss from a gpss_inputs.Scene."""
 
-    def __init__(self, scene):
+    def __init__(self, scene, kernel: str = "auto"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libgpss needs a HIP device")
@@ -195,6 +203,11 @@ class GpssScene:
         desc, keep = make_desc(scene)
         self.handle = gpss_scene_create(desc)
         del keep
+        self.set_kernel(kernel)
+
+    def set_kernel(self, kernel: str) -> None:
+        gpss_scene_set_kernel(self.handle, KERNELS[kernel])
+        self.kernel = kernel
 
     def close(self):
         if getattr(self, "handle", None):
