@@ -121,6 +121,25 @@ enum {
 int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_dev,
                       uint32_t s0, uint32_t s1, gpss_stream_t stream);
 
+/* Gradient of a scalar image loss (Sec. 5 estimator, differentiated by path replay).
+ * dloss_dimage_dev: device, width*height floats, d loss / d image for the image of
+ * gpss_render over [s0, s1).  grad_offset_dev: device, off_res[0]*[1]*[2] floats,
+ * overwritten with d loss / d (mean-offset grid nodes); required iff the scene has an offset
+ * grid.  grad_scalars_dev: device, 3 floats, overwritten with d loss / d (kernel variance,
+ * lengthscale, albedo); the variance entry is 0 when the scene has a variance grid and the
+ * albedo entry when albedo is per primitive.  The estimator is the forward one with every
+ * sampling decision frozen at the current parameters; each path is traced, then replayed
+ * from its random-number streams (no per-path storage).  Gradients are accumulated with
+ * floating-point atomics, so their last bits depend on scheduling. */
+int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float* grad_offset_dev,
+                        float* grad_scalars_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream);
+
+/* Replace the differentiable parameters: mean-offset grid (device, nullable = unchanged),
+ * kernel variance (> 0), lengthscale (> 0), albedo (in [0, 1]); rebuilds the majorant grid.
+ * Asynchronous on `stream`. */
+int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, float variance,
+                          float lengthscale, float albedo, gpss_stream_t stream);
+
 /* Evaluate the medium at n points for n directions (diagnostics and tests).
  * points_dev, dirs_dev: device, n x 3 floats.  out_dev: device, n x 8 floats:
  * mu, sigma (std), s = sigma/l, rho, sigma_proj(dir), sigma_t, ndf(dir as normal), albedo. */

@@ -981,6 +981,7 @@ int oracle_render_grad(const oracle_scene* s, int32_t s0, int32_t s1, const doub
         Counters C;
 #pragma omp for schedule(dynamic, 16)
         for (int64_t p = 0; p < npix; ++p) {
+            if (dloss[p] == 0.0 && !mean) continue;  // pixels without loss weight add nothing
             double tb = 0.0, sum = 0.0;
             Dual acc(0.0);
             for (int sidx = s0; sidx < s1; ++sidx) {

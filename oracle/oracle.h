@@ -98,7 +98,8 @@ int oracle_render_frozen(const oracle_scene* s_dec, const oracle_scene* s_w, int
 /* Gradient of sum_p dloss[p] * I_p w.r.t. the selected parameters, by forward-mode
  * dual numbers through the frozen-sampling estimator at the scene's parameters.
  * param_ids[j] >= 0 selects offset-grid node j (flat index), -1 the kernel variance,
- * -2 the lengthscale, -3 the albedo.  n_params <= 32. Also writes the image (nullable). */
+ * -2 the lengthscale, -3 the albedo.  n_params <= 32. Also writes the image (nullable);
+ * when mean is NULL, pixels with dloss == 0 are skipped. */
 int oracle_render_grad(const oracle_scene* s, int32_t s0, int32_t s1, const double* dloss,
                        int32_t n_params, const int64_t* param_ids, double* grad,
                        double* mean, int32_t nthreads);

@@ -206,18 +206,20 @@ class OracleScene:
         return mean.reshape(s.height, s.width)
 
     def render_grad(self, dloss: np.ndarray, param_ids: Sequence[int], s0: int = 0,
-                    s1: Optional[int] = None, nthreads: int = 0):
+                    s1: Optional[int] = None, nthreads: int = 0, want_image: bool = True):
+        """Gradient of sum(dloss * image) at the selected parameters (and the image, unless
+        want_image is False, in which case pixels with zero dloss are not traced)."""
         s = self.scene
         s1 = s.spp if s1 is None else s1
         dl = _vec(dloss).ravel()
         ids = np.ascontiguousarray(np.asarray(param_ids, np.int64))
         g = np.zeros(ids.size)
-        mean = np.zeros(s.width * s.height)
+        mean = np.zeros(s.width * s.height) if want_image else None
         rc = lib().oracle_render_grad(self.handle, s0, s1, _dp(dl), int(ids.size),
-                                      ids.ctypes.data_as(C.POINTER(C.c_int64)), _dp(g), _dp(mean),
-                                      nthreads)
+                                      ids.ctypes.data_as(C.POINTER(C.c_int64)), _dp(g),
+                                      _dp(mean) if want_image else None, nthreads)
         assert rc == 0
-        return g, mean.reshape(s.height, s.width)
+        return g, (mean.reshape(s.height, s.width) if want_image else None)
 
     def debug_trace(self, pixel: int, sample: int, kmax: int = 32):
         out = np.zeros(16 * kmax + 1)

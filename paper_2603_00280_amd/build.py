@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpss.so")
-SOURCES = ["gpss_api.hip", "gpss_forward.hip", "gpss_wavefront.hip"]
+SOURCES = ["gpss_api.hip", "gpss_forward.hip", "gpss_wavefront.hip", "gpss_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GPSS_OFFLOAD_ARCH", "gfx950")
 
@@ -17,6 +17,8 @@ FLAGS = [
     # fuse multiply-adds only within a source expression: the one-thread-per-path and the
     # wavefront kernels then round every shared computation identically
     "-ffp-contract=on",
+    # hardware floating-point atomics for gradient accumulation (device memory from hipMalloc)
+    "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 

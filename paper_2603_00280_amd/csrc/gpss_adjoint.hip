@@ -1,0 +1,307 @@
+// Path-replay adjoint of the forward tracer.
+//
+// The estimator differentiated is the frozen-sampling form of the forward tracer: every
+// sampling decision (tentative-collision positions, real/null choices, Russian roulette,
+// phase samples) is taken at the current parameters theta0, and only the weights depend
+// on theta.  At theta0 it equals the forward estimator.  A path's radiance is a sum of
+// contributions C_k, each a product of factors:
+//   null collision        (m - sigma_t) / (m - sigma_t0)
+//   real collision        sigma_t / sigma_t0
+//   phase weight          albedo <v, w_m> D(w_m) / (sigma(d) pdf0)
+//   light connection      albedo D(w_h) / (4 sigma(d)) * prod (1 - sigma_t / m) * Le
+// (sigma(d) of a real collision cancels against the phase weight and the light
+// connection).  d C_k = C_k sum over its factors of d log(factor), so a factor contributes
+// d log(factor) times the radiance of all contributions that contain it.  Each thread
+// traces its path once to get the radiance L, then replays the same random streams while
+// carrying the remaining radiance L_rem = L - (contributions already passed), and adds
+//   nulls before vertex k:   -sigma_t / (m - sigma_t) d log sigma_t        x L_rem
+//   vertex k:                d log rho + d log albedo                      x L_rem
+//                            d log D(w_h, light)                           x C_k,light
+//                            sum over the shadow ray -sigma_t/(m-sigma_t) d log sigma_t  x C_k,light
+//                            d log D(w_m)                                  x (L_rem - C_k)
+// to the gradient, weighted by dloss/dimage of the pixel over the number of samples.
+// Memory is O(pixels): no path is stored.
+#include "gpss_internal.hpp"
+#include "gpss_trace.hpp"
+
+namespace gpss {
+
+struct GradAcc {
+    float var, len, alb;   // d loss / d (variance, lengthscale, albedo), this thread's share
+};
+
+// d log rho = dmu * dmu_coef + dsigma * dsig_coef,  rho = phi(z)/(sigma Phi(z)), z = mu/sigma
+__device__ __forceinline__ void dlog_rho(float mu, float sigma, float& dmu, float& dsig) {
+    const float z = mu / sigma;
+    const float r = kSqrt2OverPi / erfcxf(-z * kInvSqrt2);   // phi(z) / Phi(z)
+    dmu = -(z + r) / sigma;
+    dsig = (z * z - 1.0f + z * r) / sigma;
+}
+
+// d log sigma_proj: sigma_proj = s phi(z) - m Phi(-z), m = d . G, z = m / s;
+// d/dm = -Phi(-z), d/ds = phi(z).  Written with the Mills ratio for z > 0.
+__device__ __forceinline__ void dlog_proj(float3 G, float s, float3 d, float3& dG, float& ds) {
+    const float m = dot(d, G);
+    const float z = m / s;
+    float a, b;
+    if (z <= 0.0f) {
+        const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
+        const float Phm = 1.0f - 0.5f * erfcf(-z * kInvSqrt2);
+        const float proj = s * ph - m * Phm;
+        a = Phm / proj;
+        b = ph / proj;
+    } else {
+        const float R = kSqrtHalfPi * erfcxf(z * kInvSqrt2);   // Phi(-z) / phi(z)
+        const float q = fmaxf(1.0f - z * R, 1e-30f);            // sigma_proj = s phi(z) q
+        a = R / (s * q);
+        b = 1.0f / (s * q);
+    }
+    dG = (-a) * d;
+    ds = b;
+}
+
+// d log D for g ~ N(G, s^2 I): with M_n = int_0^inf t^n exp(-(t - k)^2 / 2) dt, k = G.w / s,
+//   d log D / dG = (w s M4/M3 - G) / s^2,
+//   d log D / ds = (M5/M3 - 2 k M4/M3 + |G|^2/s^2 - 3) / s.
+// M_n by the recurrence M_n = k M_{n-1} + (n-1) M_{n-2}; scaled by exp(k^2/2) for k < 0.
+__device__ __forceinline__ bool dlog_ndf(float3 G, float s, float3 w, float3& dG, float& ds) {
+    const float is = 1.0f / s;
+    const float k = dot(G, w) * is;
+    float m0, m1;
+    if (k >= 0.0f) {
+        m0 = kSqrt2Pi * (1.0f - 0.5f * erfcf(k * kInvSqrt2));
+        m1 = expf(-0.5f * k * k) + k * m0;
+    } else {
+        m0 = kSqrtHalfPi * erfcxf(-k * kInvSqrt2);
+        m1 = 1.0f + k * m0;
+    }
+    const float m2 = k * m1 + m0;
+    const float m3 = k * m2 + 2.0f * m1;
+    const float m4 = k * m3 + 3.0f * m2;
+    const float m5 = k * m4 + 4.0f * m3;
+    if (!(m3 > 0.0f)) return false;
+    const float r4 = m4 / m3, r5 = m5 / m3;
+    dG = (is * is) * ((s * r4) * w - G);
+    ds = (r5 - 2.0f * k * r4 + dot(G, G) * is * is - 3.0f) * is;
+    return true;
+}
+
+// Add coefficients (of d mu, d grad mu, d sigma, d s at point x) to the parameter gradient.
+__device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const PointQ& q, float cmu, float3 cG,
+                                             float csig, float cs, float* __restrict__ grad_off, GradAcc& acc) {
+    if (S.offset && grad_off) {
+        const TriCell c = tri_cell(S.off_res, S.off_scale, S.lo, x);
+        const int sy = S.off_res[0], sz = S.off_res[0] * S.off_res[1];
+        const float fx = c.fx, fy = c.fy, fz = c.fz;
+        const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+        const float ax = cG.x * S.off_scale[0], ay = cG.y * S.off_scale[1], az = cG.z * S.off_scale[2];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            const int dx = n & 1, dy = (n >> 1) & 1, dz = n >> 2;
+            const float wx = dx ? fx : gx, wy = dy ? fy : gy, wz = dz ? fz : gz;
+            const float sxg = dx ? 1.0f : -1.0f, syg = dy ? 1.0f : -1.0f, szg = dz ? 1.0f : -1.0f;
+            const float v = cmu * (wx * wy * wz) + ax * (sxg * wy * wz) + ay * (syg * wx * wz) + az * (szg * wx * wy);
+            if (v != 0.0f) atomicAdd(&grad_off[c.base + dx + dy * sy + dz * sz], v);
+        }
+    }
+    if (!S.var_grid) {
+        // sigma = sqrt(variance), s = sigma / l
+        const float inv2sig = 0.5f / q.sigma;
+        acc.var += csig * inv2sig + cs * inv2sig / S.lengthscale;
+    }
+    acc.len -= cs * q.s / S.lengthscale;
+}
+
+// coefficient c on d log sigma_t(x, d) = d log rho + d log sigma_proj(d)
+__device__ __forceinline__ void add_dlog_sigma_t(const SceneDev& S, float3 x, const PointQ& q, float3 d, float c,
+                                                 float* grad_off, GradAcc& acc) {
+    float dmu, dsig, ds;
+    float3 dG;
+    dlog_rho(q.mu, q.sigma, dmu, dsig);
+    dlog_proj(q.G, q.s, d, dG, ds);
+    scatter_grad(S, x, q, c * dmu, c * dG, c * dsig, c * ds, grad_off, acc);
+}
+
+// Replay of one shadow ray: coefficient coef on d log of its transmittance estimate.
+__device__ void ratio_track_grad(const SceneDev& S, D3 o, D3 d, float3 df, double t1, Rng& rng, float coef,
+                                 float* grad_off, GradAcc& acc) {
+    PathStats st;
+    Segment sg;
+    sg.begin<false>(S, o, d, 0.0, t1, rng, st);
+    float Tr = 1.0f;
+    for (;;) {
+        const int ev = sg.step<false>(S, st);
+        if (ev == kCell) continue;
+        if (ev == kEnd) return;
+        if (++sg.steps > kStepCap) return;
+        const float3 x = sg.pos();
+        const PointQ q = eval_point(S, x);
+        const float sig = sigma_t_of(q, df);
+        add_dlog_sigma_t(S, x, q, df, -coef * sig / (sg.maj - sig), grad_off, acc);
+        Tr *= 1.0f - sig / sg.maj;
+        if (!roulette(Tr, rng)) return;
+        sg.redraw(rng);
+    }
+}
+
+template <int NLIGHT>
+struct VertexNee {
+    float E[NLIGHT];
+    float3 wh[NLIGHT];
+};
+
+// Replay of path (pixel, sample) with radiance L_total; wpix = dloss/dI_pixel / samples.
+__device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, float L_total, float wpix,
+                            float* grad_off, GradAcc& acc) {
+    PathStats st;
+    Rng rng;
+    rng.init(S.key0, S.key1, pixel, sample, 0u, kStreamCam);
+    const float ux = rng.uniform(), uy = rng.uniform();
+    D3 o, d;
+    camera_ray(S, pixel, ux, uy, o, d);
+    float beta = 1.0f, Lrem = L_total;
+    int b = 0;
+    for (;;) {
+        double t0, t1;
+        if (!clip_box(S, o, d, t0, t1)) break;
+        rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamTrack);
+        const float3 df = to_f3(d);
+        Segment sg;
+        sg.begin<false>(S, o, d, t0, t1, rng, st);
+        bool hit = false;
+        for (;;) {
+            const int ev = sg.step<false>(S, st);
+            if (ev == kCell) continue;
+            if (ev == kEnd) break;
+            if (++sg.steps > kStepCap) break;
+            const float u2 = rng.uniform();
+            const float3 x = sg.pos();
+            const PointQ q = eval_point(S, x);
+            const float sig = sigma_t_of(q, df);
+            if (u2 * sg.maj < sig) {
+                hit = true;
+                break;
+            }
+            if (Lrem != 0.0f) add_dlog_sigma_t(S, x, q, df, -wpix * Lrem * sig / (sg.maj - sig), grad_off, acc);
+            sg.redraw(rng);
+        }
+        if (!hit) break;
+        ++b;
+        if (b > S.max_depth) break;
+        const D3 x = o + sg.t * d;
+        const float3 xf = to_f3(x);
+        const PointQ q = eval_point(S, xf);
+        VertexNee<2> nv;
+        float Etot = 0.0f;
+#pragma unroll 1
+        for (int li = 0; li < 2; ++li) {
+            nv.E[li] = 0.0f;
+            D3 wl;
+            double tend;
+            float Le;
+            if (!light_sample(S, li, x, wl, tend, Le)) continue;
+            const float3 wlf = to_f3(wl);
+            const float p = phase_eval(q, df, wlf);
+            Rng rn;
+            rn.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
+            const float Tr = ratio_track<false>(S, x, wl, wlf, tend, rn, st);
+            nv.E[li] = nee_contribution(mul_rn(beta, p), Tr, Le);
+            Etot = add_rn(Etot, nv.E[li]);
+            if (nv.E[li] != 0.0f) {
+                Rng rn2;
+                rn2.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
+                ratio_track_grad(S, x, wl, wlf, tend, rn2, wpix * nv.E[li], grad_off, acc);
+                const float3 h = wlf - df;
+                const float hn = sqrtf(dot(h, h));
+                float3 dG;
+                float ds;
+                if (hn >= 1e-7f && dlog_ndf(q.G, q.s, (1.0f / hn) * h, dG, ds)) {
+                    const float c = wpix * nv.E[li];
+                    scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc);
+                }
+            }
+        }
+        // density and albedo: every contribution from this vertex on
+        {
+            float dmu, dsig;
+            dlog_rho(q.mu, q.sigma, dmu, dsig);
+            const float c = wpix * Lrem;
+            scatter_grad(S, xf, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, grad_off, acc);
+            if (!S.albedo_per_prim && S.albedo > 0.0f) acc.alb += c / S.albedo;
+        }
+        // phase sampling (same draws as the forward pass)
+        rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamPhase);
+        D3 wi;
+        float wgt, pdf;
+        float3 wm;
+        const bool ok = sample_scatter(S, q, d, df, rng, wi, wgt, wm, pdf);
+        const float Lafter = Lrem - Etot;
+        if (ok && Lafter != 0.0f) {
+            float3 dG;
+            float ds;
+            if (dlog_ndf(q.G, q.s, wm, dG, ds)) {
+                const float c = wpix * Lafter;
+                scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc);
+            }
+        }
+        if (!ok) break;
+        Lrem = Lafter;
+        beta = mul_rn(beta, wgt);
+        o = x;
+        d = wi;
+    }
+}
+
+#ifndef GPSS_ADJ_MIN_WAVES
+#define GPSS_ADJ_MIN_WAVES 4
+#endif
+
+__global__ __launch_bounds__(256, GPSS_ADJ_MIN_WAVES) void adjoint_kernel(SceneDev S, const float* __restrict__ dloss,
+                                                                         float* __restrict__ grad_off,
+                                                                         float* __restrict__ grad_scalars, uint32_t s0,
+                                                                         uint32_t ns, uint64_t npaths) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    GradAcc acc{0.0f, 0.0f, 0.0f};
+    if (p < npaths) {
+        const uint32_t pixel = (uint32_t)(p / ns), sample = s0 + (uint32_t)(p % ns);
+        const float wpix = dloss[pixel] / (float)ns;
+        if (wpix != 0.0f) {
+            PathStats st;
+            st.clear();
+            const float L = trace_path<false>(S, pixel, sample, st);
+            replay_path(S, pixel, sample, L, wpix, grad_off, acc);
+        }
+    }
+    float v[3] = {acc.var, acc.len, acc.alb};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (v[0] != 0.0f) atomicAdd(&grad_scalars[0], v[0]);
+        if (v[1] != 0.0f) atomicAdd(&grad_scalars[1], v[1]);
+        if (v[2] != 0.0f) atomicAdd(&grad_scalars[2], v[2]);
+    }
+}
+
+__global__ void zero_kernel(float* __restrict__ a, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0f;
+}
+
+int launch_adjoint(gpss_scene* s, const float* dloss, float* grad_off, float* grad_scalars, uint32_t s0,
+                   uint32_t ns, hipStream_t stream) {
+    const uint64_t noff = (uint64_t)s->desc.off_res[0] * s->desc.off_res[1] * s->desc.off_res[2];
+    if (grad_off && s->d_offset)
+        hipLaunchKernelGGL(zero_kernel, dim3((uint32_t)((noff + 255) / 256)), dim3(256), 0, stream, grad_off, noff);
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, stream, grad_scalars, (uint64_t)3);
+    const uint64_t npaths = s->n_pixels() * ns;
+    const uint64_t blocks = (npaths + 255) / 256;
+    if (blocks > 0x7FFFFFFFull) return set_error(GPSS_ERR_INVALID_ARG, "too many paths in one launch");
+    hipLaunchKernelGGL(adjoint_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, s->dev, dloss,
+                       s->d_offset ? grad_off : nullptr, grad_scalars, s0, ns, npaths);
+    return check_hip(hipGetLastError(), "adjoint_kernel launch");
+}
+
+}  // namespace gpss

@@ -343,6 +343,13 @@ int gpss_scene_set_kernel(gpss_scene_t scene, int32_t kernel) {
 
 int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n) {
     if (!scene || !out) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
+    if (scene->maj_h_stale) {
+        int rc = check_hip(hipMemcpy(scene->maj_h.data(), scene->d_maj, scene->maj_h.size() * sizeof(float),
+                                     hipMemcpyDeviceToHost),
+                           "hipMemcpy majorants");
+        if (rc) return rc;
+        scene->maj_h_stale = false;
+    }
     if (n < scene->maj_h.size()) return set_error(GPSS_ERR_INVALID_ARG, "output holds %llu < %zu floats",
                                                   (unsigned long long)n, scene->maj_h.size());
     std::memcpy(out, scene->maj_h.data(), scene->maj_h.size() * sizeof(float));
@@ -367,6 +374,43 @@ int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1, 
     rc = gpss::launch_render_paths(scene, scene->d_scratch, nullptr, s0, ns, st);
     if (rc) return rc;
     return gpss::launch_reduce(scene, scene->d_scratch, image_dev, ns, st);
+}
+
+int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, float variance, float lengthscale,
+                          float albedo, gpss_stream_t stream) {
+    if (!scene) return set_error(GPSS_ERR_INVALID_ARG, "scene is NULL");
+    if (mean_offset_dev && !scene->d_offset)
+        return set_error(GPSS_ERR_INVALID_ARG, "scene has no mean-offset grid");
+    if (!(variance > 0.0f) || !std::isfinite(variance)) return set_error(GPSS_ERR_INVALID_ARG, "variance must be > 0");
+    if (!(lengthscale > 0.0f) || !std::isfinite(lengthscale))
+        return set_error(GPSS_ERR_INVALID_ARG, "lengthscale must be > 0");
+    if (!(albedo >= 0.0f && albedo <= 1.0f)) return set_error(GPSS_ERR_INVALID_ARG, "albedo not in [0,1]");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (mean_offset_dev) {
+        const size_t n = (size_t)scene->desc.off_res[0] * scene->desc.off_res[1] * scene->desc.off_res[2];
+        int rc = check_hip(hipMemcpyAsync(scene->d_offset, mean_offset_dev, n * sizeof(float),
+                                          hipMemcpyDeviceToDevice, st),
+                           "hipMemcpyAsync(offset)");
+        if (rc) return rc;
+    }
+    scene->desc.variance = variance;
+    scene->desc.lengthscale = lengthscale;
+    scene->desc.albedo = albedo;
+    scene->dev.variance = variance;
+    scene->dev.lengthscale = lengthscale;
+    scene->dev.albedo = albedo;
+    scene->maj_h_stale = true;
+    return gpss::launch_majorants(scene, st);
+}
+
+int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float* grad_offset_dev,
+                        float* grad_scalars_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream) {
+    if (!scene || !dloss_dimage_dev || !grad_scalars_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
+    if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
+    if (scene->d_offset && !grad_offset_dev)
+        return set_error(GPSS_ERR_INVALID_ARG, "scene has a mean-offset grid: grad_offset_dev is required");
+    return gpss::launch_adjoint(scene, dloss_dimage_dev, grad_offset_dev, grad_scalars_dev, s0, s1 - s0,
+                                reinterpret_cast<hipStream_t>(stream));
 }
 
 int gpss_eval_medium(gpss_scene_t scene, const float* points_dev, const float* dirs_dev, float* out_dev,

@@ -30,6 +30,7 @@ struct gpss_scene {
     gpss_scene_desc desc{};            // host pointers cleared after create
     gpss::SceneDev dev{};              // device view (pointers into the buffers below)
     std::vector<float> prims_h, offset_h, var_h, maj_h;
+    bool maj_h_stale = false;          // device majorants rebuilt since maj_h was copied
     float* d_prims = nullptr;
     float* d_offset = nullptr;
     float* d_var = nullptr;
@@ -62,6 +63,8 @@ int wf_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint
 int mega_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
 int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* out, int kmax,
                        hipStream_t stream);
+int launch_adjoint(gpss_scene* s, const float* dloss, float* grad_off, float* grad_scalars, uint32_t s0,
+                   uint32_t ns, hipStream_t stream);
 int launch_eval(gpss_scene* s, const float* pts, const float* dirs, float* out, uint64_t n,
                 hipStream_t stream);
 

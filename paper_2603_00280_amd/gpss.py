@@ -26,7 +26,7 @@ COUNTER_NAMES = ["track_steps", "real", "nee_steps", "violations", "capped", "es
 
 EXPORTED = ["gpss_scene_create", "gpss_scene_destroy", "gpss_scene_get_majorants", "gpss_render",
             "gpss_render_paths", "gpss_eval_medium", "gpss_debug_trace", "gpss_scene_set_kernel",
-            "gpss_last_error"]
+            "gpss_render_adjoint", "gpss_scene_set_params", "gpss_last_error"]
 GPSS_KERNEL_AUTO, GPSS_KERNEL_MEGA, GPSS_KERNEL_WAVEFRONT = 0, 1, 2
 KERNELS = {"auto": GPSS_KERNEL_AUTO, "mega": GPSS_KERNEL_MEGA, "wavefront": GPSS_KERNEL_WAVEFRONT}
 REC_FIELDS = 16
@@ -76,6 +76,8 @@ def lib():
         L.gpss_eval_medium.argtypes = [vp, vp, vp, vp, C.c_uint64, vp]
         L.gpss_debug_trace.argtypes = [vp, vp, C.c_uint32, vp, C.c_uint32, vp]
         L.gpss_scene_set_kernel.argtypes = [vp, C.c_int32]
+        L.gpss_render_adjoint.argtypes = [vp, vp, vp, vp, C.c_uint32, C.c_uint32, vp]
+        L.gpss_scene_set_params.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, vp]
         L.gpss_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name != "gpss_last_error":
@@ -181,6 +183,18 @@ def gpss_eval_medium(handle: int, pts_ptr: int, dirs_ptr: int, out_ptr: int, n: 
     _check(lib().gpss_eval_medium(handle, pts_ptr, dirs_ptr, out_ptr, n, _stream_ptr(stream)))
 
 
+def gpss_render_adjoint(handle: int, dloss_ptr: int, grad_off_ptr: Optional[int], grad_sc_ptr: int,
+                        s0: int, s1: int, stream=None) -> None:
+    _check(lib().gpss_render_adjoint(handle, dloss_ptr, grad_off_ptr, grad_sc_ptr, s0, s1,
+                                     _stream_ptr(stream)))
+
+
+def gpss_scene_set_params(handle: int, offset_ptr: Optional[int], variance: float, lengthscale: float,
+                          albedo: float, stream=None) -> None:
+    _check(lib().gpss_scene_set_params(handle, offset_ptr, variance, lengthscale, albedo,
+                                       _stream_ptr(stream)))
+
+
 def gpss_scene_set_kernel(handle: int, kernel: int) -> None:
     _check(lib().gpss_scene_set_kernel(handle, kernel))
 
@@ -261,6 +275,36 @@ class GpssScene:
         gpss_debug_trace(self.handle, ids.data_ptr(), n, out.data_ptr(), kmax, stream)
         o = out.cpu().numpy()
         return o[:, :-1].reshape(n, kmax, REC_FIELDS), o[:, -1]
+
+    def render_adjoint(self, dloss, s0: int = 0, s1: Optional[int] = None, stream=None):
+        """(grad of the offset grid (nz, ny, nx) or None, grad of (variance, lengthscale, albedo))."""
+        import torch
+        s1 = self.scene.spp if s1 is None else s1
+        dl = dloss.to(device="cuda", dtype=torch.float32).contiguous()
+        assert dl.numel() == self.scene.n_pixels
+        g_off = None
+        if self.scene.offset_grid is not None:
+            g_off = torch.empty(self.scene.offset_grid.shape, dtype=torch.float32, device="cuda")
+        g_sc = torch.empty(3, dtype=torch.float32, device="cuda")
+        gpss_render_adjoint(self.handle, dl.data_ptr(), g_off.data_ptr() if g_off is not None else None,
+                            g_sc.data_ptr(), s0, s1, stream)
+        return g_off, g_sc
+
+    def set_params(self, offset=None, variance=None, lengthscale=None, albedo=None, stream=None):
+        """Update the differentiable parameters (offset: device tensor of the grid's shape)."""
+        import torch
+        s = self.scene
+        variance = float(s.variance if variance is None else variance)
+        lengthscale = float(s.lengthscale if lengthscale is None else lengthscale)
+        albedo = float(s.albedo if albedo is None else albedo)
+        optr = None
+        if offset is not None:
+            off = offset.detach().to(device="cuda", dtype=torch.float32).contiguous()
+            assert tuple(off.shape) == tuple(s.offset_grid.shape)
+            optr = off.data_ptr()
+            self._offset_keep = off
+        gpss_scene_set_params(self.handle, optr, variance, lengthscale, albedo, stream)
+        self.scene = s.replace(variance=variance, lengthscale=lengthscale, albedo=albedo)
 
     def eval_medium(self, points, dirs, stream=None):
         import torch

@@ -1,0 +1,154 @@
+"""Path-replay adjoint on the GPU against the oracle's dual-number gradient of the same
+frozen-sampling estimator, and parameter updates through the C-ABI."""
+import numpy as np
+import pytest
+
+from gpss_inputs import scenes as sc
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_00280_amd import gpss
+    return gpss
+
+
+def _small(target, w=48, spp=4, depth=8):
+    return sc.offset_sphere_scene(target, width=w, height=w, spp=spp, max_depth=depth)
+
+
+def _dloss(theta0, target):
+    """d/dI of mean((I - T)^2), with I and T rendered by the oracle."""
+    I = orc.OracleScene(theta0).render()["mean"]
+    T = orc.OracleScene(target).render()["mean"]
+    return 2.0 * (I - T) / I.size
+
+
+@pytest.mark.parametrize("perturbed", [False, True])
+def test_adjoint_matches_oracle_dual_gradient(G, perturbed):
+    s0 = _small(False)
+    if perturbed:   # theta0 with non-zero offsets, so that every gradient term is exercised
+        s0.offset_grid = np.random.default_rng(9).normal(0, 0.01, s0.offset_grid.shape).astype(np.float32)
+    tgt = _small(True)
+    dl = _dloss(s0, tgt)
+    ids = [-1, -2, -3] + [int(i) for i in sc.grad_param_indices(s0)]
+    print(f"[adjoint] perturbed={perturbed} {s0.width}x{s0.height} spp {s0.spp} params {len(ids)}", flush=True)
+    g_orc, _ = orc.OracleScene(s0).render_grad(dl, ids)
+    g = G.GpssScene(s0)
+    g_off, g_sc = g.render_adjoint(torch.as_tensor(dl, dtype=torch.float32))
+    torch.cuda.synchronize()
+    g_off = g_off.cpu().numpy().ravel()
+    g_sc = g_sc.cpu().numpy()
+    g_gpu = np.array([g_sc[0], g_sc[1], g_sc[2]] + [g_off[i] for i in ids[3:]], np.float64)
+    scale = np.abs(g_orc).max()
+    err = np.abs(g_gpu - g_orc)
+    for name, a, b in zip(["var", "len", "alb"] + [f"n{i}" for i in ids[3:]], g_gpu, g_orc):
+        print(f"   {name:>8s} gpu {a:+.6e} oracle {b:+.6e}", flush=True)
+    print(f"   max |diff| / max |g| = {err.max() / scale:.3e}", flush=True)
+    _check_groups(g_gpu, g_orc)
+
+
+def _check_groups(g_gpu, g_orc):
+    """Scalars and grid nodes separately: each within 1e-3 of its group's largest entry."""
+    assert np.isfinite(g_gpu).all()
+    for sl in (slice(0, 3), slice(3, None)):
+        a, b = g_gpu[sl], g_orc[sl]
+        scale = np.abs(b).max()
+        assert scale > 0
+        assert np.abs(a - b).max() <= 1e-3 * scale, (a, b)
+
+
+def test_adjoint_full_size_sampled_pixels(G):
+    """The offset-sphere workload at full size (256^2, 16 spp, depth 16): loss weight on 400
+    random pixels, so the oracle traces only those; all 32 parameters compared."""
+    s0 = sc.offset_sphere_scene(False)
+    rng = np.random.default_rng(21)
+    dl = np.zeros((s0.height, s0.width))
+    ys, xs = np.meshgrid(np.arange(64, 192), np.arange(64, 192), indexing="ij")
+    pick = rng.choice(ys.size, 400, replace=False)
+    dl[ys.ravel()[pick], xs.ravel()[pick]] = rng.normal(size=400) / s0.n_pixels
+    ids = [-1, -2, -3] + [int(i) for i in sc.grad_param_indices(s0)]
+    print(f"[adjoint] full size {s0.width}x{s0.height} spp {s0.spp} depth {s0.max_depth}", flush=True)
+    g_orc, _ = orc.OracleScene(s0).render_grad(dl, ids, want_image=False)
+    g_off, g_sc = G.GpssScene(s0).render_adjoint(torch.as_tensor(dl, dtype=torch.float32))
+    g_off = g_off.cpu().numpy().ravel()
+    g_sc = g_sc.cpu().numpy()
+    g_gpu = np.array(list(g_sc) + [g_off[i] for i in ids[3:]], np.float64)
+    print("   scalars gpu", g_gpu[:3], "oracle", g_orc[:3], flush=True)
+    print("   nodes: nonzero", int((g_orc[3:] != 0).sum()), "max rel",
+          float(np.max(np.abs(g_gpu[3:] - g_orc[3:])) / np.abs(g_orc[3:]).max()), flush=True)
+    _check_groups(g_gpu, g_orc)
+
+
+def test_set_params_equals_fresh_scene(G):
+    s0 = _small(False, w=32)
+    tgt = _small(True, w=32)
+    g = G.GpssScene(s0)
+    off = torch.as_tensor(tgt.offset_grid, device="cuda")
+    g.set_params(off, tgt.variance, tgt.lengthscale, tgt.albedo)
+    a = g.render().cpu().numpy()
+    fresh = G.GpssScene(tgt)
+    b = fresh.render().cpu().numpy()
+    assert np.array_equal(a, b)
+    assert np.array_equal(g.majorants(), fresh.majorants())
+
+
+def test_adjoint_without_offset_grid(G):
+    s = sc.sphere_scene(0.1, width=32, height=32, spp=4, max_depth=8)
+    dl = np.random.default_rng(1).normal(size=(32, 32)) / 1024
+    ids = [-1, -2, -3]
+    g_orc, _ = orc.OracleScene(s).render_grad(dl, ids)
+    g_off, g_sc = G.GpssScene(s).render_adjoint(torch.as_tensor(dl, dtype=torch.float32))
+    assert g_off is None
+    g_sc = g_sc.cpu().numpy().astype(np.float64)
+    print("   gpu", g_sc, "oracle", g_orc, flush=True)
+    assert np.allclose(g_sc, g_orc, rtol=2e-3, atol=2e-3 * np.abs(g_orc).max())
+
+
+def test_torch_autograd_function(G):
+    from paper_2603_00280_amd import autograd as ag
+    s0 = _small(False, w=32)
+    tgt = _small(True, w=32)
+    T = G.GpssScene(tgt).render()
+    scene = G.GpssScene(s0)
+    off = torch.zeros(s0.offset_grid.shape, device="cuda", requires_grad=True)
+    var = torch.tensor(float(np.float32(s0.variance)), requires_grad=True)
+    ls = torch.tensor(float(np.float32(s0.lengthscale)), requires_grad=True)
+    alb = torch.tensor(float(np.float32(s0.albedo)), requires_grad=True)
+    img = ag.render(scene, off, var, ls, alb)
+    loss = ((img - T) ** 2).mean()
+    loss.backward()
+    dl = (2.0 * (img.detach() - T) / img.numel())
+    g_off, g_sc = scene.render_adjoint(dl)
+    assert var.grad.device.type == "cpu" and off.grad.device.type == "cuda"
+    assert torch.allclose(off.grad, g_off, rtol=1e-5, atol=1e-9)
+    got = torch.stack([var.grad, ls.grad, alb.grad]).float()
+    assert torch.allclose(got, g_sc.cpu(), rtol=1e-5, atol=1e-9)
+
+
+def test_gradient_descent_reduces_loss(G):
+    """A few Adam steps on (variance, lengthscale, albedo) toward the target's values."""
+    from paper_2603_00280_amd import autograd as ag
+    s0 = sc.sphere_scene(0.12, width=48, height=48, spp=8, max_depth=8, variance=0.003, albedo=0.7)
+    tgt = sc.sphere_scene(0.1, width=48, height=48, spp=8, max_depth=8, variance=0.0025, albedo=0.8)
+    T = G.GpssScene(tgt).render()
+    scene = G.GpssScene(s0)
+    # optimise the logarithms of the three parameters (they differ by orders of magnitude)
+    p = torch.log(torch.tensor([0.003, 0.12, 0.7], dtype=torch.float64)).requires_grad_(True)
+    opt = torch.optim.Adam([p], lr=0.03)
+    losses = []
+    for _ in range(8):
+        opt.zero_grad()
+        q = torch.exp(p)
+        img = ag.render(scene, None, q[0], q[1], q[2].clamp(max=1.0))
+        loss = ((img - T) ** 2).mean()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss.detach()))
+    print("   losses", [f"{l:.3e}" for l in losses], flush=True)
+    assert losses[-1] < losses[0]
