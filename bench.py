@@ -66,18 +66,86 @@ def cpu_baseline(scenes, spp: int):
             "cpu": platform.processor() or platform.machine()}
 
 
+def adjoint_measurement(torch, gpss):
+    """Path-replay adjoint of the L2 image loss on the offset-sphere workload (256^2, 16 spp,
+    depth 16, 64^3 mean-offset grid) at theta0 against the target image; a path counts once
+    although it is traced and replayed."""
+    from gpss_inputs import scenes as sc
+    s0, st = sc.offset_sphere_scene(False), sc.offset_sphere_scene(True)
+    target = gpss.GpssScene(st).render()
+    g = gpss.GpssScene(s0)
+    img = g.render()
+    dl = (2.0 * (img - target) / img.numel()).contiguous()
+    g.render_adjoint(dl)      # warm-up
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, fn in (("forward", lambda: g.render(out=img)), ("adjoint", lambda: g.render_adjoint(dl))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1)
+    return {"workload": "offset sphere: 64^3 mean-offset grid, 256x256, 16 spp, max depth 16, "
+                        "L2 loss against the seeded target",
+            "adjoint_mpaths_s": s0.n_paths / (res["adjoint"] / 1e3) / 1e6,
+            "forward_mpaths_s": s0.n_paths / (res["forward"] / 1e3) / 1e6,
+            "adjoint_ms": res["adjoint"], "forward_ms": res["forward"],
+            "loss": float(((img - target) ** 2).mean())}
+
+
+def batch_measurement(torch, gpss, tune: bool):
+    """64 sphere scenes of uneven resolution, spp and lengthscale: one persistent
+    hipGraph-captured launch against 64 sequential plain launches (same images)."""
+    from gpss_inputs import scenes as sc
+    scenes = sc.batch_scenes()
+    gs = [gpss.GpssScene(s) for s in scenes]
+    outs = [torch.empty(g.shape, dtype=torch.float32, device="cuda") for g in gs]
+    plain = [torch.empty(g.shape, dtype=torch.float32, device="cuda") for g in gs]
+    npaths = sum(s.n_paths for s in scenes)
+    tuned = None
+    if tune:
+        tuned = gpss.gpss_batch_autotune([g.handle for g in gs], [o.data_ptr() for o in outs])
+    gpss.render_batch(gs, outs)             # plan + graph capture
+    for g, o in zip(gs, plain):
+        g.render(out=o)                      # wavefront buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gpss.render_batch(gs, outs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for g, o in zip(gs, plain):
+        g.render(out=o)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = all(bool(torch.equal(a, b)) for a, b in zip(outs, plain))
+    return {"workload": "64 sphere scenes, resolution {64..512}^2, spp {4,16,64}, lengthscale "
+                        "log-uniform [0.005, 0.5], max depth 32", "paths": npaths,
+            "batch_mpaths_s": npaths / t_batch / 1e6, "plain_sequential_mpaths_s": npaths / t_plain / 1e6,
+            "batch_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3, "images_identical": same,
+            "tuning": tuned}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-spp", type=int, default=16, help="spp of the oracle CPU sample")
+    ap.add_argument("--cpu-spp", type=int, default=48, help="spp of the oracle CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default="auto", choices=["auto", "mega", "wavefront"],
                     help="tracer form timed for the headline value")
     ap.add_argument("--compare", action="store_true",
                     help="also time one step of the other tracer form")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint measurement on the offset-sphere workload")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-render measurement on the 64-scene workload")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the batch autotuner first (its choice is cached on disk)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -166,6 +234,12 @@ def main():
         torch.cuda.synchronize()
         result["compare"] = {"tracer": other,
                              "mpaths_s": sum(s.n_paths for s in scenes) / (time.perf_counter() - t0) / 1e6}
+    if not args.no_adjoint:
+        print("[bench] adjoint", file=sys.stderr, flush=True)
+        result["adjoint"] = adjoint_measurement(torch, gpss)
+    if not args.no_batch:
+        print("[bench] batch", file=sys.stderr, flush=True)
+        result["batch"] = batch_measurement(torch, gpss, args.tune)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the CPU", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(scenes, args.cpu_spp)

@@ -134,6 +134,23 @@ int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_d
 int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float* grad_offset_dev,
                         float* grad_scalars_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream);
 
+/* Render n scenes of uneven size and sample count in one persistent launch, each over its
+ * full [0, spp) into images_dev[i] (host array of device pointers, width*height floats
+ * each).  Images are identical to gpss_render's.  The work table (tiles of one scene's
+ * paths) and a hipGraph of [cursor reset, persistent kernel, reduction] are built on the
+ * first call for a given scene list and replayed afterwards; tile size and persistent grid
+ * come from the tuning cache written by gpss_batch_autotune (file $GPSS_TUNE_CACHE, else
+ * ~/.cache/gpss_batch_tuning.txt), else 1024 paths and 16 waves per CU.  The call returns
+ * after the batch has completed on `stream`.  All scenes must live on one device. */
+int gpss_render_batch(const gpss_scene_t* scenes, uint32_t n, float* const* images_dev,
+                      gpss_stream_t stream);
+
+/* Time every (tile size, waves per CU) candidate on this batch, keep the fastest for later
+ * gpss_render_batch calls and append it to the tuning cache.  Outputs (nullable): the
+ * chosen tile size, waves per CU and the batch time in ms. */
+int gpss_batch_autotune(const gpss_scene_t* scenes, uint32_t n, float* const* images_dev,
+                        gpss_stream_t stream, uint32_t* tile, uint32_t* waves_per_cu, float* ms);
+
 /* Replace the differentiable parameters: mean-offset grid (device, nullable = unchanged),
  * kernel variance (> 0), lengthscale (> 0), albedo (in [0, 1]); rebuilds the majorant grid.
  * Asynchronous on `stream`. */

@@ -329,6 +329,7 @@ int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out) {
 
 int gpss_scene_destroy(gpss_scene_t scene) {
     if (!scene) return set_error(GPSS_ERR_INVALID_ARG, "scene is NULL");
+    gpss::forget_scene_plans(scene);
     free_scene(scene);
     return GPSS_OK;
 }
@@ -411,6 +412,24 @@ int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float
         return set_error(GPSS_ERR_INVALID_ARG, "scene has a mean-offset grid: grad_offset_dev is required");
     return gpss::launch_adjoint(scene, dloss_dimage_dev, grad_offset_dev, grad_scalars_dev, s0, s1 - s0,
                                 reinterpret_cast<hipStream_t>(stream));
+}
+
+int gpss_render_batch(const gpss_scene_t* scenes, uint32_t n, float* const* images_dev, gpss_stream_t stream) {
+    try {
+        return gpss::render_batch(scenes, n, images_dev, reinterpret_cast<hipStream_t>(stream));
+    } catch (...) {
+        return set_error(GPSS_ERR_OOM, "unexpected host exception in gpss_render_batch");
+    }
+}
+
+int gpss_batch_autotune(const gpss_scene_t* scenes, uint32_t n, float* const* images_dev, gpss_stream_t stream,
+                        uint32_t* tile, uint32_t* waves_per_cu, float* ms) {
+    try {
+        return gpss::autotune_batch(scenes, n, images_dev, reinterpret_cast<hipStream_t>(stream), tile,
+                                    waves_per_cu, ms);
+    } catch (...) {
+        return set_error(GPSS_ERR_OOM, "unexpected host exception in gpss_batch_autotune");
+    }
 }
 
 int gpss_eval_medium(gpss_scene_t scene, const float* points_dev, const float* dirs_dev, float* out_dev,

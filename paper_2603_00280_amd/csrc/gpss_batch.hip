@@ -1,0 +1,372 @@
+// Batched rendering of many scenes in one persistent launch.
+//
+// A batch plan holds, in device memory, one record per scene (its scene record and the
+// offset of its paths in a shared per-path buffer) and a table of tiles, each a contiguous
+// range of one scene's paths (path p = pixel * spp + sample).  A persistent kernel's waves
+// take tiles from a global cursor (one atomic per tile) and trace the tile's paths one per
+// lane; a second kernel forms every scene's image as the per-pixel mean over its samples,
+// in sample order.  [reset cursor -> persistent kernel -> reduction] is captured once into
+// a hipGraph per plan and replayed on every call.  Path radiances equal those of
+// gpss_render (same per-path routine and random numbers).
+#include <sys/stat.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+
+#include "gpss_internal.hpp"
+#include "gpss_trace.hpp"
+
+namespace gpss {
+
+struct BatchScene {
+    SceneDev S;
+    uint64_t path_base;    // first slot of this scene in the per-path buffer
+    uint64_t pix_base;     // first pixel of this scene in the batch's pixel numbering
+    uint32_t spp;
+    uint32_t npix;
+};
+
+struct Tile {
+    uint32_t scene;
+    uint32_t count;        // paths in the tile
+    uint64_t p0;           // first path (within the scene)
+};
+
+__global__ void batch_reset_kernel(uint32_t* cursor) {
+    if (threadIdx.x == 0) *cursor = 0u;
+}
+
+#ifndef GPSS_BATCH_MIN_WAVES
+#define GPSS_BATCH_MIN_WAVES 4
+#endif
+
+__global__ __launch_bounds__(256, GPSS_BATCH_MIN_WAVES) void batch_kernel(const BatchScene* __restrict__ scenes,
+                                                                         const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                                         uint32_t* cursor, float* __restrict__ paths) {
+    const uint32_t lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(cursor, 1u);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+        if (t >= ntiles) break;
+        const Tile tl = tiles[t];
+        const BatchScene& B = scenes[tl.scene];
+        for (uint32_t k = lane; k < tl.count; k += 64) {
+            const uint64_t p = tl.p0 + k;
+            const uint32_t pixel = (uint32_t)(p / B.spp), sample = (uint32_t)(p % B.spp);
+            PathStats st;
+            paths[B.path_base + p] = trace_path<false>(B.S, pixel, sample, st);
+        }
+    }
+}
+
+// One thread per pixel of the batch: image[pixel] = mean of its samples, in sample order.
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchScene* __restrict__ scenes, uint32_t nscenes,
+                                                           float* const* __restrict__ images,
+                                                           const float* __restrict__ paths, uint64_t total_pix) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_pix) return;
+    uint32_t lo = 0, hi = nscenes - 1;   // last scene whose pix_base <= g
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (scenes[mid].pix_base <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchScene& B = scenes[lo];
+    const uint64_t pix = g - B.pix_base;
+    const float* src = paths + B.path_base + pix * B.spp;
+    float acc = 0.0f;
+    for (uint32_t k = 0; k < B.spp; ++k) acc += src[k];
+    images[lo][pix] = acc / (float)B.spp;
+}
+
+// ---------------------------------------------------------------------------
+// Plans, graphs and tuning.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    std::vector<gpss_scene*> scenes;
+    uint32_t tile = 0, grid = 0;
+    BatchScene* d_scenes = nullptr;
+    BatchScene* h_scenes = nullptr;     // pinned staging of the scene records
+    Tile* d_tiles = nullptr;
+    uint32_t ntiles = 0;
+    uint32_t* d_cursor = nullptr;
+    float** d_images = nullptr;
+    float** h_images = nullptr;         // pinned staging of the image pointers
+    float* d_paths = nullptr;
+    uint64_t total_paths = 0, total_pix = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+std::mutex g_mu;
+std::vector<BatchPlan*> g_plans;
+
+void free_plan(BatchPlan* P) {
+    if (!P) return;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    (void)hipFree(P->d_scenes);
+    (void)hipHostFree(P->h_scenes);
+    (void)hipFree(P->d_tiles);
+    (void)hipFree(P->d_cursor);
+    (void)hipFree(P->d_images);
+    (void)hipHostFree(P->h_images);
+    (void)hipFree(P->d_paths);
+    delete P;
+}
+
+// Batch signature for the tuning cache: device and the work of every scene.
+std::string signature(gpss_scene* const* scenes, uint32_t n, int cus) {
+    std::ostringstream o;
+    o << "cus" << cus;
+    for (uint32_t i = 0; i < n; ++i) {
+        const gpss_scene_desc& D = scenes[i]->desc;
+        o << ";" << D.mean_kind << "," << D.n_prims << "," << D.width << "x" << D.height << "," << D.spp << ","
+          << D.max_depth << "," << D.lengthscale << "," << D.variance << "," << D.majorant_res[0];
+    }
+    return o.str();
+}
+
+std::string cache_path() {
+    if (const char* p = std::getenv("GPSS_TUNE_CACHE")) return p;
+    const char* home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/gpss_batch_tuning.txt";
+}
+
+bool cache_lookup(const std::string& sig, uint32_t& tile, uint32_t& wpc) {
+    std::ifstream f(cache_path());
+    std::string line;
+    size_t h = std::hash<std::string>{}(sig);
+    while (std::getline(f, line)) {
+        std::istringstream l(line);
+        size_t key;
+        uint32_t t, w;
+        if (l >> key >> t >> w && key == h) {
+            tile = t;
+            wpc = w;
+        }
+    }
+    return tile != 0;
+}
+
+void cache_store(const std::string& sig, uint32_t tile, uint32_t wpc) {
+    const std::string path = cache_path();
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos) {
+        const std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)   // create the directory, parents first
+            if (i == dir.size() || dir[i] == '/') (void)::mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    std::ofstream f(path, std::ios::app);
+    f << std::hash<std::string>{}(sig) << " " << tile << " " << wpc << "\n";
+}
+}  // namespace
+
+int get_cus(int device, int& cus) {
+    return check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device),
+                     "hipDeviceGetAttribute");
+}
+
+static int build_plan(gpss_scene* const* scenes, uint32_t n, uint32_t tile, uint32_t waves_per_cu, BatchPlan** out) {
+    BatchPlan* P = new (std::nothrow) BatchPlan();
+    if (!P) return set_error(GPSS_ERR_OOM, "host allocation");
+    P->scenes.assign(scenes, scenes + n);
+    int cus = 0;
+    int rc = get_cus(scenes[0]->device, cus);
+    P->tile = tile;
+    P->grid = (uint32_t)std::max(1, cus) * waves_per_cu / 4u;
+    std::vector<Tile> tiles;
+    uint64_t pbase = 0, xbase = 0;
+    if (!rc) rc = check_hip(hipHostMalloc(reinterpret_cast<void**>(&P->h_scenes), n * sizeof(BatchScene)),
+                            "hipHostMalloc");
+    for (uint32_t i = 0; i < n && !rc; ++i) {
+        const gpss_scene* s = scenes[i];
+        BatchScene& B = P->h_scenes[i];
+        B.S = s->dev;
+        B.spp = s->desc.spp;
+        B.npix = (uint32_t)s->n_pixels();
+        B.path_base = pbase;
+        B.pix_base = xbase;
+        const uint64_t np = s->n_pixels() * s->desc.spp;
+        for (uint64_t p0 = 0; p0 < np; p0 += tile)
+            tiles.push_back(Tile{i, (uint32_t)std::min<uint64_t>(tile, np - p0), p0});
+        pbase += np;
+        xbase += s->n_pixels();
+    }
+    P->total_paths = pbase;
+    P->total_pix = xbase;
+    P->ntiles = (uint32_t)tiles.size();
+    if (!rc) rc = check_hip(hipMalloc(&P->d_scenes, n * sizeof(BatchScene)), "hipMalloc");
+    if (!rc) rc = check_hip(hipMalloc(&P->d_tiles, tiles.size() * sizeof(Tile)), "hipMalloc");
+    if (!rc)
+        rc = check_hip(hipMemcpy(P->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice),
+                       "hipMemcpy tiles");
+    if (!rc) rc = check_hip(hipMalloc(&P->d_cursor, 64), "hipMalloc");
+    if (!rc) rc = check_hip(hipMalloc(&P->d_images, n * sizeof(float*)), "hipMalloc");
+    if (!rc) rc = check_hip(hipHostMalloc(reinterpret_cast<void**>(&P->h_images), n * sizeof(float*)),
+                            "hipHostMalloc");
+    if (!rc) rc = check_hip(hipMalloc(&P->d_paths, std::max<uint64_t>(1, pbase) * sizeof(float)), "hipMalloc(paths)");
+    if (rc) {
+        free_plan(P);
+        return rc;
+    }
+    *out = P;
+    return GPSS_OK;
+}
+
+static int capture_graph(BatchPlan* P, hipStream_t stream) {
+    hipStream_t cs;
+    int rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    if (rc) return rc;
+    rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (!rc) {
+        hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, P->d_cursor);
+        hipLaunchKernelGGL(batch_kernel, dim3(P->grid), dim3(256), 0, cs, P->d_scenes, P->d_tiles, P->ntiles,
+                           P->d_cursor, P->d_paths);
+        hipLaunchKernelGGL(batch_reduce_kernel, dim3((uint32_t)((P->total_pix + 255) / 256)), dim3(256), 0, cs,
+                           P->d_scenes, (uint32_t)P->scenes.size(), P->d_images, P->d_paths, P->total_pix);
+        hipGraph_t g = nullptr;
+        rc = check_hip(hipStreamEndCapture(cs, &g), "hipStreamEndCapture");
+        if (!rc) {
+            P->graph = g;
+            rc = check_hip(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    (void)stream;
+    return rc;
+}
+
+// Stage the scene records and image pointers, then launch the plan's graph on `stream`.
+static int run_plan(BatchPlan* P, float* const* images, hipStream_t stream) {
+    const uint32_t n = (uint32_t)P->scenes.size();
+    for (uint32_t i = 0; i < n; ++i) {
+        P->h_scenes[i].S = P->scenes[i]->dev;
+        P->h_images[i] = images[i];
+    }
+    int rc = check_hip(hipMemcpyAsync(P->d_scenes, P->h_scenes, n * sizeof(BatchScene), hipMemcpyHostToDevice, stream),
+                       "hipMemcpyAsync(batch scenes)");
+    if (!rc)
+        rc = check_hip(hipMemcpyAsync(P->d_images, P->h_images, n * sizeof(float*), hipMemcpyHostToDevice, stream),
+                       "hipMemcpyAsync(batch images)");
+    if (!rc && !P->exec) rc = capture_graph(P, stream);
+    if (!rc) rc = check_hip(hipGraphLaunch(P->exec, stream), "hipGraphLaunch");
+    // the pinned staging buffers are reused by the next call on this plan: wait for the copies
+    if (!rc) rc = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    return rc;
+}
+
+static BatchPlan* find_plan(gpss_scene* const* scenes, uint32_t n) {
+    for (BatchPlan* P : g_plans)
+        if (P->scenes.size() == n && std::equal(P->scenes.begin(), P->scenes.end(), scenes)) return P;
+    return nullptr;
+}
+
+void forget_scene_plans(gpss_scene* s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::find((*it)->scenes.begin(), (*it)->scenes.end(), s) != (*it)->scenes.end()) {
+            free_plan(*it);
+            it = g_plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+static int validate_batch(gpss_scene* const* scenes, uint32_t n, float* const* images) {
+    if (!scenes || !images || n == 0) return set_error(GPSS_ERR_INVALID_ARG, "empty or NULL batch");
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!scenes[i] || !images[i]) return set_error(GPSS_ERR_INVALID_ARG, "NULL scene or image %u", i);
+        if (scenes[i]->device != scenes[0]->device)
+            return set_error(GPSS_ERR_INVALID_ARG, "scenes of one batch must share a device");
+    }
+    return GPSS_OK;
+}
+
+int render_batch(gpss_scene* const* scenes, uint32_t n, float* const* images, hipStream_t stream) {
+    int rc = validate_batch(scenes, n, images);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    BatchPlan* P = find_plan(scenes, n);
+    if (!P) {
+        int cus = 0;
+        rc = get_cus(scenes[0]->device, cus);
+        if (rc) return rc;
+        uint32_t tile = 0, wpc = 16;
+        if (!cache_lookup(signature(scenes, n, cus), tile, wpc)) {
+            tile = 1024;
+            wpc = 16;
+        }
+        rc = build_plan(scenes, n, tile, wpc, &P);
+        if (rc) return rc;
+        g_plans.push_back(P);
+    }
+    return run_plan(P, images, stream);
+}
+
+// Time every candidate (tile size x persistent waves per CU) on the batch itself, keep the
+// fastest as the batch's plan and append it to the on-disk cache.
+int autotune_batch(gpss_scene* const* scenes, uint32_t n, float* const* images, hipStream_t stream,
+                   uint32_t* best_tile, uint32_t* best_wpc, float* best_ms) {
+    int rc = validate_batch(scenes, n, images);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cus = 0;
+    rc = get_cus(scenes[0]->device, cus);
+    if (rc) return rc;
+    const uint32_t tiles[] = {256, 1024, 4096};
+    const uint32_t wpcs[] = {8, 16, 24};
+    float bms = 1e30f;
+    BatchPlan* best = nullptr;
+    hipEvent_t e0, e1;
+    rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
+    if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+    for (uint32_t t : tiles) {
+        for (uint32_t w : wpcs) {
+            if (rc) break;
+            BatchPlan* P = nullptr;
+            rc = build_plan(scenes, n, t, w, &P);
+            if (rc) break;
+            rc = run_plan(P, images, stream);   // capture + warm-up
+            if (!rc) rc = check_hip(hipEventRecord(e0, stream), "hipEventRecord");
+            if (!rc) rc = run_plan(P, images, stream);
+            if (!rc) rc = check_hip(hipEventRecord(e1, stream), "hipEventRecord");
+            if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (!rc && ms < bms) {
+                bms = ms;
+                std::swap(best, P);
+            }
+            free_plan(P);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        free_plan(best);
+        return rc;
+    }
+    BatchPlan* old = find_plan(scenes, n);
+    if (old) {
+        g_plans.erase(std::find(g_plans.begin(), g_plans.end(), old));
+        free_plan(old);
+    }
+    g_plans.push_back(best);
+    cache_store(signature(scenes, n, cus), best->tile, best->grid * 4u / (uint32_t)std::max(1, cus));
+    if (best_tile) *best_tile = best->tile;
+    if (best_wpc) *best_wpc = best->grid * 4u / (uint32_t)std::max(1, cus);
+    if (best_ms) *best_ms = bms;
+    return GPSS_OK;
+}
+
+}  // namespace gpss

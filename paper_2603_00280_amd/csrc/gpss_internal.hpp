@@ -65,6 +65,10 @@ int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* ou
                        hipStream_t stream);
 int launch_adjoint(gpss_scene* s, const float* dloss, float* grad_off, float* grad_scalars, uint32_t s0,
                    uint32_t ns, hipStream_t stream);
+int render_batch(gpss_scene* const* scenes, uint32_t n, float* const* images, hipStream_t stream);
+int autotune_batch(gpss_scene* const* scenes, uint32_t n, float* const* images, hipStream_t stream,
+                   uint32_t* best_tile, uint32_t* best_wpc, float* best_ms);
+void forget_scene_plans(gpss_scene* s);
 int launch_eval(gpss_scene* s, const float* pts, const float* dirs, float* out, uint64_t n,
                 hipStream_t stream);
 

@@ -26,7 +26,8 @@ COUNTER_NAMES = ["track_steps", "real", "nee_steps", "violations", "capped", "es
 
 EXPORTED = ["gpss_scene_create", "gpss_scene_destroy", "gpss_scene_get_majorants", "gpss_render",
             "gpss_render_paths", "gpss_eval_medium", "gpss_debug_trace", "gpss_scene_set_kernel",
-            "gpss_render_adjoint", "gpss_scene_set_params", "gpss_last_error"]
+            "gpss_render_adjoint", "gpss_scene_set_params", "gpss_render_batch", "gpss_batch_autotune",
+            "gpss_last_error"]
 GPSS_KERNEL_AUTO, GPSS_KERNEL_MEGA, GPSS_KERNEL_WAVEFRONT = 0, 1, 2
 KERNELS = {"auto": GPSS_KERNEL_AUTO, "mega": GPSS_KERNEL_MEGA, "wavefront": GPSS_KERNEL_WAVEFRONT}
 REC_FIELDS = 16
@@ -78,6 +79,10 @@ def lib():
         L.gpss_scene_set_kernel.argtypes = [vp, C.c_int32]
         L.gpss_render_adjoint.argtypes = [vp, vp, vp, vp, C.c_uint32, C.c_uint32, vp]
         L.gpss_scene_set_params.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, vp]
+        L.gpss_render_batch.argtypes = [C.POINTER(vp), C.c_uint32, C.POINTER(vp), vp]
+        L.gpss_batch_autotune.argtypes = [C.POINTER(vp), C.c_uint32, C.POINTER(vp), vp,
+                                          C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                          C.POINTER(C.c_float)]
         L.gpss_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name != "gpss_last_error":
@@ -193,6 +198,31 @@ def gpss_scene_set_params(handle: int, offset_ptr: Optional[int], variance: floa
                           albedo: float, stream=None) -> None:
     _check(lib().gpss_scene_set_params(handle, offset_ptr, variance, lengthscale, albedo,
                                        _stream_ptr(stream)))
+
+
+def gpss_render_batch(handles, image_ptrs, stream=None) -> None:
+    n = len(handles)
+    hs = (C.c_void_p * n)(*handles)
+    ims = (C.c_void_p * n)(*image_ptrs)
+    _check(lib().gpss_render_batch(hs, n, ims, _stream_ptr(stream)))
+
+
+def gpss_batch_autotune(handles, image_ptrs, stream=None):
+    n = len(handles)
+    hs = (C.c_void_p * n)(*handles)
+    ims = (C.c_void_p * n)(*image_ptrs)
+    t, w, ms = C.c_uint32(), C.c_uint32(), C.c_float()
+    _check(lib().gpss_batch_autotune(hs, n, ims, _stream_ptr(stream), C.byref(t), C.byref(w), C.byref(ms)))
+    return {"tile": t.value, "waves_per_cu": w.value, "ms": ms.value}
+
+
+def render_batch(scenes, outs=None, stream=None):
+    """Render GpssScene objects in one persistent launch; returns their images."""
+    import torch
+    if outs is None:
+        outs = [torch.empty(g.shape, dtype=torch.float32, device="cuda") for g in scenes]
+    gpss_render_batch([g.handle for g in scenes], [o.data_ptr() for o in outs], stream)
+    return outs
 
 
 def gpss_scene_set_kernel(handle: int, kernel: int) -> None:
