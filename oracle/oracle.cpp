@@ -941,6 +941,37 @@ static int render_impl(const oracle_scene* s_dec, const oracle_scene* s_w, bool 
     return 0;
 }
 
+int oracle_render_pixels(const oracle_scene* s, const int64_t* pixels, int64_t n, int32_t s0, int32_t s1,
+                         double* mean, double* var, int64_t* counters, int32_t nthreads) {
+    if (!s || !pixels || !mean || n < 0 || s1 <= s0 || s0 < 0) return -1;
+    const int64_t npix = (int64_t)s->W * s->H;
+    for (int64_t i = 0; i < n; ++i)
+        if (pixels[i] < 0 || pixels[i] >= npix) return -1;
+    const int ns = s1 - s0;
+    Counters total;
+    const Params<double> P = plain_params(s);
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+    {
+        Counters C;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < n; ++i) {
+            double sum = 0.0, sq = 0.0, tb = 0.0;
+            for (int sidx = s0; sidx < s1; ++sidx) {
+                const double L = trace_path<double>(P, P, false, (uint32_t)pixels[i], (uint32_t)sidx, C, tb);
+                sum += L;
+                sq += L * L;
+            }
+            mean[i] = sum / ns;
+            if (var) var[i] = ns > 1 ? std::max(0.0, (sq - sum * sum / ns) / (ns - 1)) : 0.0;
+        }
+#pragma omp critical
+        total.add(C);
+    }
+    if (counters) for (int i = 0; i < ORC_C_COUNT; ++i) counters[i] = total.c[i];
+    return 0;
+}
+
 int oracle_render(const oracle_scene* s, int32_t s0, int32_t s1, double* mean, double* var,
                   double* paths, double* trunc_beta, int64_t* counters, int32_t nthreads) {
     return render_impl(s, s, false, s0, s1, mean, var, paths, trunc_beta, counters, nthreads);

@@ -89,6 +89,10 @@ int oracle_majorants(const oracle_scene* s, float* out, int64_t n);
 int oracle_render(const oracle_scene* s, int32_t s0, int32_t s1, double* mean, double* var,
                   double* paths, double* trunc_beta, int64_t* counters, int32_t nthreads);
 
+/* Forward render of listed pixels only (flat indices): mean/var of n entries. */
+int oracle_render_pixels(const oracle_scene* s, const int64_t* pixels, int64_t n, int32_t s0,
+                         int32_t s1, double* mean, double* var, int64_t* counters, int32_t nthreads);
+
 /* Frozen-sampling render: every sampling decision is taken with scene s_dec, every
  * weight is evaluated with scene s_w (same geometry, different parameters). With
  * s_w == s_dec it equals oracle_render. */

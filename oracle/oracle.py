@@ -56,6 +56,8 @@ def lib():
         L.oracle_majorants.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64]
         L.oracle_render.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp, dp, dp, dp,
                                     C.POINTER(C.c_int64), C.c_int32]
+        L.oracle_render_pixels.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int64, C.c_int32,
+                                           C.c_int32, dp, dp, C.POINTER(C.c_int64), C.c_int32]
         L.oracle_render_frozen.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, dp,
                                            C.POINTER(C.c_int64), C.c_int32]
         L.oracle_render_grad.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp, C.c_int32,
@@ -194,6 +196,17 @@ class OracleScene:
         if want_paths:
             out["paths"] = paths.reshape(s.height, s.width, s1 - s0)
         return out
+
+    def render_pixels(self, pixels, s0: int = 0, s1: Optional[int] = None, nthreads: int = 0):
+        """Mean and variance of the listed pixels (flat indices) over samples [s0, s1)."""
+        s = self.scene
+        s1 = s.spp if s1 is None else s1
+        px = np.ascontiguousarray(np.asarray(pixels, np.int64))
+        mean, var = np.zeros(px.size), np.zeros(px.size)
+        rc = lib().oracle_render_pixels(self.handle, px.ctypes.data_as(C.POINTER(C.c_int64)), px.size,
+                                        s0, s1, _dp(mean), _dp(var), None, nthreads)
+        assert rc == 0
+        return {"mean": mean, "var": var}
 
     def render_frozen(self, weights: "OracleScene", s0: int = 0, s1: Optional[int] = None,
                       nthreads: int = 0) -> np.ndarray:

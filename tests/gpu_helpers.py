@@ -67,3 +67,32 @@ def isclose_rel(a, b, rel):
 
 
 __all__ = ["compare_images", "assert_parity", "compare_paths", "fmt", "math"]
+
+
+def allowed_flips(n: int) -> int:
+    """Flipped pixels allowed among n sampled pixels: the 99th percentile of
+    Binomial(n, FLIP_FRACTION), i.e. what a 0.1 % flip rate produces by chance."""
+    from scipy import stats
+    return int(stats.binom.ppf(0.99, n, FLIP_FRACTION))
+
+
+def compare_sampled(gpu_vals, ref: dict, spp: int, label: str = ""):
+    """Sampled-pixel comparison: gpu_vals and ref['mean'/'var'] are 1-D over the samples."""
+    o = np.asarray(ref["mean"], np.float64)
+    g = np.asarray(gpu_vals, np.float64)
+    floor = 1e-6 * max(float(np.abs(o).max()), 1e-30)
+    rel = np.abs(g - o) / np.maximum(np.abs(o), floor)
+    bad = rel > REL_TOL
+    se = np.sqrt(np.maximum(ref["var"], 0.0) / spp)
+    within = np.abs(g - o) <= FLIP_SIGMAS * se + floor
+    return {"label": label, "n_pixels": int(o.size), "n_flipped": int(bad.sum()),
+            "allowed": allowed_flips(o.size),
+            "max_rel_unflipped": float(rel[~bad].max()) if (~bad).any() else 0.0,
+            "flipped_outside_3sigma": int((bad & ~within).sum()), "image_mean": float(o.mean())}
+
+
+def assert_sampled_parity(stats: dict):
+    msg = str(stats)
+    assert stats["n_flipped"] <= stats["allowed"], msg
+    assert stats["flipped_outside_3sigma"] == 0, msg
+    assert stats["max_rel_unflipped"] <= REL_TOL, msg

@@ -438,3 +438,13 @@ def _unrounded(scene):
     orc.lib().oracle_scene_destroy(o.handle)
     o.handle = h
     return o
+
+
+def test_pixel_list_render_equals_full_render():
+    s = sc.sphere_scene(0.1, width=24, height=20, spp=3, max_depth=6)
+    o = orc.OracleScene(s)
+    full = o.render()
+    px = np.array([0, 7, 133, 479, 250])
+    r = o.render_pixels(px)
+    assert np.array_equal(r["mean"], full["mean"].ravel()[px])
+    assert np.allclose(r["var"], full["var"].ravel()[px], rtol=1e-12, atol=0)
