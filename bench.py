@@ -36,6 +36,10 @@ WORKLOADS = {
 }
 
 
+TRACERS = {"auto": "persistent scheduled waves", "persistent": "persistent scheduled waves",
+           "wavefront": "wavefront", "mega": "one thread per path"}
+
+
 def make_scenes(name):
     from gpss_inputs import scenes as sc
     if name == "sphere":
@@ -136,7 +140,7 @@ def main():
     ap.add_argument("--workload", default="sphere", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-spp", type=int, default=48, help="spp of the oracle CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "mega", "wavefront"],
+    ap.add_argument("--kernel", default="auto", choices=["auto", "persistent", "mega", "wavefront"],
                     help="tracer form timed for the headline value")
     ap.add_argument("--compare", action="store_true",
                     help="also time one step of the other tracer form")
@@ -216,7 +220,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + WORKLOADS[args.workload],
                    "paths_per_step": sum(s.n_paths for s in scenes),
-                   "tracer": "one thread per path" if args.kernel == "mega" else "wavefront"},
+                   "tracer": TRACERS[args.kernel]},
         "roofline": {"bound": "alu", "achieved": flop_rate / 1e12, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flop_rate / 1e12 / FP32_PEAK_TFLOPS, "traffic": None,
                      "avg_launch_ms": avg_launch_ms,
@@ -224,16 +228,20 @@ def main():
         "per_scene_mpaths_s": [s.n_paths / (ms / 1e3) / 1e6 for s, ms in zip(scenes, per_scene_ms)],
     }
     if args.compare:
-        other = "mega" if args.kernel != "mega" else "wavefront"
-        for g in gs:
-            g.set_kernel(other)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for g, im in zip(gs, imgs):
-            g.render(out=im)
-        torch.cuda.synchronize()
-        result["compare"] = {"tracer": other,
-                             "mpaths_s": sum(s.n_paths for s in scenes) / (time.perf_counter() - t0) / 1e6}
+        result["compare"] = {}
+        for other in ("persistent", "wavefront", "mega"):
+            if TRACERS[other] == TRACERS[args.kernel]:
+                continue
+            for g in gs:
+                g.set_kernel(other)
+            for g, im in zip(gs, imgs):   # warm-up (wavefront buffers are allocated here)
+                g.render(out=im)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for g, im in zip(gs, imgs):
+                g.render(out=im)
+            torch.cuda.synchronize()
+            result["compare"][TRACERS[other]] = sum(s.n_paths for s in scenes) / (time.perf_counter() - t0) / 1e6
     if not args.no_adjoint:
         print("[bench] adjoint", file=sys.stderr, flush=True)
         result["adjoint"] = adjoint_measurement(torch, gpss)

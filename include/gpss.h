@@ -93,10 +93,13 @@ typedef struct {
 int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out);
 int gpss_scene_destroy(gpss_scene_t scene);
 
-/* Implementation used by gpss_render / gpss_render_paths.  Both give bit-identical path
- * radiances.  AUTO (default) = WAVEFRONT: per-bounce track / scatter / light-connection
- * kernels over queues of structure-of-arrays path state; MEGA: one thread per path. */
-enum { GPSS_KERNEL_AUTO = 0, GPSS_KERNEL_MEGA = 1, GPSS_KERNEL_WAVEFRONT = 2 };
+/* Implementation used by gpss_render / gpss_render_paths.  All give bit-identical path
+ * radiances.  AUTO (default) = PERSISTENT: persistent waves that take paths in chunks and
+ * schedule each path's operations (cell steps, medium evaluations, phase sampling, segment
+ * starts) so that every operation runs for many lanes of a wave at once; WAVEFRONT:
+ * per-bounce track / scatter / light-connection kernels over queues of structure-of-arrays
+ * path state; MEGA: one thread per path. */
+enum { GPSS_KERNEL_AUTO = 0, GPSS_KERNEL_MEGA = 1, GPSS_KERNEL_WAVEFRONT = 2, GPSS_KERNEL_PERSISTENT = 3 };
 int gpss_scene_set_kernel(gpss_scene_t scene, int32_t kernel);
 
 /* Copy the majorant grid (majorant_res[0]*[1]*[2] floats, x fastest) to host memory `out`

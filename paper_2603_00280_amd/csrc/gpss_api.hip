@@ -76,10 +76,34 @@ int ensure_wavefront(gpss_scene* s, uint64_t npaths) {
     s->wf_cap = npaths;
     if (!s->wf_grid) {
         int cus = 0;
-        rc = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device),
-                       "hipDeviceGetAttribute");
+        rc = device_cus(s->device, &cus);
         if (rc) return rc;
-        s->wf_grid = (uint32_t)(cus > 0 ? cus : 1) * 4u;
+        s->wf_grid = (uint32_t)cus * 4u;
+    }
+    return GPSS_OK;
+}
+
+int device_cus(int device, int* cus) {
+    int n = 0;
+    int rc = check_hip(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device),
+                       "hipDeviceGetAttribute");
+    if (rc) return rc;
+    *cus = n > 0 ? n : 1;
+    return GPSS_OK;
+}
+
+// Path counter and grid size of the persistent scheduled kernel: one 256-thread workgroup
+// per compute unit for each wave per SIMD that the kernel's register budget allows.
+int ensure_sched(gpss_scene* s) {
+    if (!s->d_head) {
+        int rc = check_hip(hipMalloc(&s->d_head, 64), "hipMalloc(path counter)");
+        if (rc) return rc;
+    }
+    if (!s->sched_grid) {
+        int cus = 0;
+        int rc = device_cus(s->device, &cus);
+        if (rc) return rc;
+        s->sched_grid = (uint32_t)cus * (uint32_t)sched_waves_per_simd();
     }
     return GPSS_OK;
 }
@@ -193,6 +217,7 @@ void free_scene(gpss_scene* s) {
     (void)hipFree(s->d_maj);
     (void)hipFree(s->d_scratch);
     (void)hipFree(s->wf_mem);
+    (void)hipFree(s->d_head);
     delete s;
 }
 
@@ -336,7 +361,8 @@ int gpss_scene_destroy(gpss_scene_t scene) {
 
 int gpss_scene_set_kernel(gpss_scene_t scene, int32_t kernel) {
     if (!scene) return set_error(GPSS_ERR_INVALID_ARG, "scene is NULL");
-    if (kernel != GPSS_KERNEL_AUTO && kernel != GPSS_KERNEL_MEGA && kernel != GPSS_KERNEL_WAVEFRONT)
+    if (kernel != GPSS_KERNEL_AUTO && kernel != GPSS_KERNEL_MEGA && kernel != GPSS_KERNEL_WAVEFRONT &&
+        kernel != GPSS_KERNEL_PERSISTENT)
         return set_error(GPSS_ERR_INVALID_ARG, "unknown kernel %d", kernel);
     scene->kernel = kernel;
     return GPSS_OK;

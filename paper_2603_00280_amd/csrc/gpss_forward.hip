@@ -236,7 +236,8 @@ int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* ou
 int launch_render_paths(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns,
                         hipStream_t stream) {
     if (s->kernel == GPSS_KERNEL_MEGA) return mega_render(s, paths, counters, s0, ns, stream);
-    return wf_render(s, paths, counters, s0, ns, stream);
+    if (s->kernel == GPSS_KERNEL_WAVEFRONT) return wf_render(s, paths, counters, s0, ns, stream);
+    return sched_render(s, paths, counters, s0, ns, stream);
 }
 
 // Per-pixel mean over the sample range, summed in sample order (deterministic).

@@ -44,6 +44,8 @@ struct gpss_scene {
     void* wf_mem = nullptr;
     uint64_t wf_cap = 0;               // paths the wavefront buffers hold
     uint32_t wf_grid = 0;              // persistent workgroups per wavefront launch
+    uint32_t* d_head = nullptr;        // path counter of the persistent scheduled kernel
+    uint32_t sched_grid = 0;           // workgroups of the persistent scheduled kernel
     uint64_t n_pixels() const { return (uint64_t)desc.width * desc.height; }
 };
 
@@ -61,6 +63,10 @@ int launch_reduce(gpss_scene* s, const float* paths, float* image, uint32_t ns, 
 int ensure_wavefront(gpss_scene* s, uint64_t npaths);
 int wf_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
 int mega_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
+int ensure_sched(gpss_scene* s);
+int sched_waves_per_simd();
+int sched_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
+int device_cus(int device, int* cus);
 int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* out, int kmax,
                        hipStream_t stream);
 int launch_adjoint(gpss_scene* s, const float* dloss, float* grad_off, float* grad_scalars, uint32_t s0,

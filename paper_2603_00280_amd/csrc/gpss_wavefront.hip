@@ -15,24 +15,11 @@
 // one-thread-per-path kernel, so both give bit-identical path radiances.
 #include "gpss_internal.hpp"
 #include "gpss_trace.hpp"
+#include "gpss_waves.hpp"
 
 namespace gpss {
 
 constexpr uint32_t kDead = 0x80000000u;   // path ended at its last vertex (degenerate phase sample)
-constexpr uint32_t kChunk = 64;
-
-__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
-
-// Append `item` for lanes with `want` to queue q (counter *cnt): one atomic per wave.
-__device__ __forceinline__ void wave_push(bool want, uint32_t item, uint32_t* __restrict__ q, uint32_t* cnt) {
-    const uint64_t m = __ballot(want);
-    if (m == 0) return;
-    const int leader = __builtin_ctzll(m);
-    uint32_t base = 0;
-    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, 64);
-    if (want) q[base + (uint32_t)__popcll(m & lanemask_lt())] = item;
-}
 
 __device__ __forceinline__ void pixel_sample(const WfState& W, uint32_t p, uint32_t& pixel, uint32_t& sample) {
     pixel = p / W.ns;
@@ -83,45 +70,6 @@ __global__ void wf_next_kernel(WfState W) {
         W.cnt[kQNeeHead] = 0;
     }
 }
-
-// ---------------------------------------------------------------------------
-// Persistent-wave chunked queue reader.
-// ---------------------------------------------------------------------------
-struct ChunkReader {
-    uint32_t pos, end, n;
-    bool exhausted;
-    __device__ __forceinline__ void init(uint32_t n_items) {
-        pos = end = 0;
-        n = n_items;
-        exhausted = false;
-    }
-    // Give each lane with `idle` the index of a queue item (true) while items remain.
-    __device__ __forceinline__ bool take(bool idle, uint32_t* head, uint32_t& idx) {
-        uint64_t m = __ballot(idle);
-        bool got = false;
-        while (m && !exhausted) {
-            if (pos >= end) {
-                uint32_t base = 0;
-                if ((threadIdx.x & 63) == 0) base = atomicAdd(head, kChunk);
-                base = __shfl(base, 0, 64);
-                if (base >= n) { exhausted = true; break; }
-                pos = base;
-                end = min(base + kChunk, n);
-            }
-            const uint32_t avail = end - pos;
-            const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
-            const bool mine = idle && !got && ((m >> (threadIdx.x & 63)) & 1ull) && rank < avail;
-            if (mine) {
-                idx = pos + rank;
-                got = true;
-            }
-            const uint32_t used = min((uint32_t)__popcll(m), avail);
-            pos += used;
-            m = __ballot(idle && !got);
-        }
-        return got;
-    }
-};
 
 template <bool STATS>
 __device__ __forceinline__ void flush_stats_wf(const PathStats& st, unsigned long long* counters) {

@@ -28,8 +28,9 @@ EXPORTED = ["gpss_scene_create", "gpss_scene_destroy", "gpss_scene_get_majorants
             "gpss_render_paths", "gpss_eval_medium", "gpss_debug_trace", "gpss_scene_set_kernel",
             "gpss_render_adjoint", "gpss_scene_set_params", "gpss_render_batch", "gpss_batch_autotune",
             "gpss_last_error"]
-GPSS_KERNEL_AUTO, GPSS_KERNEL_MEGA, GPSS_KERNEL_WAVEFRONT = 0, 1, 2
-KERNELS = {"auto": GPSS_KERNEL_AUTO, "mega": GPSS_KERNEL_MEGA, "wavefront": GPSS_KERNEL_WAVEFRONT}
+GPSS_KERNEL_AUTO, GPSS_KERNEL_MEGA, GPSS_KERNEL_WAVEFRONT, GPSS_KERNEL_PERSISTENT = 0, 1, 2, 3
+KERNELS = {"auto": GPSS_KERNEL_AUTO, "mega": GPSS_KERNEL_MEGA, "wavefront": GPSS_KERNEL_WAVEFRONT,
+           "persistent": GPSS_KERNEL_PERSISTENT}
 REC_FIELDS = 16
 
 

@@ -1,5 +1,6 @@
-"""The wavefront tracer against the one-thread-per-path kernel: identical arithmetic per
-path, so path radiances must agree bit for bit, and event counts must be equal."""
+"""The wavefront and the persistent scheduled tracers against the one-thread-per-path
+kernel: identical arithmetic per path, so path radiances must agree bit for bit, and event
+counts must be equal."""
 import numpy as np
 import pytest
 
@@ -29,13 +30,14 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("kernel", ["wavefront", "persistent"])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_wavefront_matches_megakernel_bitwise(G, name):
+def test_kernel_matches_megakernel_bitwise(G, name, kernel):
     s = CASES[name]()
-    print(f"[wavefront] {name} {s.width}x{s.height} spp {s.spp} depth {s.max_depth}", flush=True)
+    print(f"[{kernel}] {name} {s.width}x{s.height} spp {s.spp} depth {s.max_depth}", flush=True)
     g = G.GpssScene(s, kernel="mega")
     pm, cm = g.render_paths(counters=True)
-    g.set_kernel("wavefront")
+    g.set_kernel(kernel)
     pw, cw = g.render_paths(counters=True)
     pm, pw = pm.cpu().numpy(), pw.cpu().numpy()
     diff = np.flatnonzero(pm.view(np.uint32) != pw.view(np.uint32))
@@ -48,15 +50,26 @@ def test_wavefront_matches_megakernel_bitwise(G, name):
     assert np.array_equal(im_w, im_m)
 
 
-def test_wavefront_sample_ranges_and_reuse(G):
+@pytest.mark.parametrize("kernel", ["wavefront", "persistent"])
+def test_sample_ranges_and_reuse(G, kernel):
     s = sc.sphere_scene(0.1, width=40, height=24, spp=12, max_depth=8)
-    g = G.GpssScene(s, kernel="wavefront")
+    g = G.GpssScene(s, kernel=kernel)
     full = g.render_paths(0, 12).cpu().numpy()
     a = g.render_paths(0, 5).cpu().numpy()
     b = g.render_paths(5, 12).cpu().numpy()
     assert np.array_equal(np.concatenate([a, b], axis=2), full)
     # a larger launch after a smaller one, then a smaller one again (buffer reuse)
-    big = G.GpssScene(s.replace(width=64, height=64), kernel="wavefront")
+    big = G.GpssScene(s.replace(width=64, height=64), kernel=kernel)
     big.render_paths(0, 12)
     again = g.render_paths(0, 12).cpu().numpy()
     assert np.array_equal(again, full)
+
+
+def test_auto_is_persistent_and_single_path_launches(G):
+    """The default kernel is the persistent one; launches smaller than one wave's chunk
+    (a single path, a 1x1 image) and larger than the resident grid both complete."""
+    s = sc.sphere_scene(0.02, width=1, height=1, spp=1, max_depth=6)
+    g = G.GpssScene(s)
+    p1 = g.render_paths().cpu().numpy()
+    g.set_kernel("mega")
+    assert np.array_equal(p1, g.render_paths().cpu().numpy())
