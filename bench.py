@@ -113,7 +113,7 @@ def batch_measurement(torch, gpss, tune: bool):
         tuned = gpss.gpss_batch_autotune([g.handle for g in gs], [o.data_ptr() for o in outs])
     gpss.render_batch(gs, outs)             # plan + graph capture
     for g, o in zip(gs, plain):
-        g.render(out=o)                      # wavefront buffers
+        g.render(out=o)                      # warm-up of the single-scene path
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gpss.render_batch(gs, outs)

@@ -143,7 +143,7 @@ int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float
  * paths) and a hipGraph of [cursor reset, persistent kernel, reduction] are built on the
  * first call for a given scene list and replayed afterwards; tile size and persistent grid
  * come from the tuning cache written by gpss_batch_autotune (file $GPSS_TUNE_CACHE, else
- * ~/.cache/gpss_batch_tuning.txt), else 1024 paths and 16 waves per CU.  The call returns
+ * ~/.cache/gpss_batch_tuning.txt), else 4096 paths and 12 waves per CU.  The call returns
  * after the batch has completed on `stream`.  All scenes must live on one device. */
 int gpss_render_batch(const gpss_scene_t* scenes, uint32_t n, float* const* images_dev,
                       gpss_stream_t stream);

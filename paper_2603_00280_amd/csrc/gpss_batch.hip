@@ -3,8 +3,8 @@
 // A batch plan holds, in device memory, one record per scene (its scene record and the
 // offset of its paths in a shared per-path buffer) and a table of tiles, each a contiguous
 // range of one scene's paths (path p = pixel * spp + sample).  A persistent kernel's waves
-// take tiles from a global cursor (one atomic per tile) and trace the tile's paths one per
-// lane; a second kernel forms every scene's image as the per-pixel mean over its samples,
+// take tiles from a global cursor (one atomic per tile) and trace each tile's paths with the
+// scheduled loop of the persistent tracer; a second kernel forms every scene's image as the per-pixel mean over its samples,
 // in sample order.  [reset cursor -> persistent kernel -> reduction] is captured once into
 // a hipGraph per plan and replayed on every call.  Path radiances equal those of
 // gpss_render (same per-path routine and random numbers).
@@ -20,7 +20,7 @@
 #include <string>
 
 #include "gpss_internal.hpp"
-#include "gpss_trace.hpp"
+#include "gpss_sched.hpp"
 
 namespace gpss {
 
@@ -42,14 +42,35 @@ __global__ void batch_reset_kernel(uint32_t* cursor) {
     if (threadIdx.x == 0) *cursor = 0u;
 }
 
-#ifndef GPSS_BATCH_MIN_WAVES
-#define GPSS_BATCH_MIN_WAVES 4
-#endif
+// Paths [p0, p0 + count) of one scene's tile, handed to idle lanes in order (the wave owns
+// the tile, so no atomics): pixel p / spp, sample p % spp, slot base + p.
+struct TileSource {
+    uint64_t next, end, base;
+    uint32_t spp;
+    __device__ __forceinline__ bool exhausted() const { return next >= end; }
+    __device__ __forceinline__ bool take(bool idle, uint32_t& slot, uint32_t& pixel, uint32_t& sample) {
+        const uint64_t m = __ballot(idle);
+        const uint64_t avail = end - next;
+        const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
+        const bool got = idle && rank < avail;
+        const uint64_t p = next + rank;
+        next += min((uint64_t)__popcll(m), avail);
+        if (!got) return false;
+        slot = (uint32_t)(base + p);
+        pixel = (uint32_t)(p / spp);
+        sample = (uint32_t)(p % spp);
+        return true;
+    }
+};
 
-__global__ __launch_bounds__(256, GPSS_BATCH_MIN_WAVES) void batch_kernel(const BatchScene* __restrict__ scenes,
+// Persistent waves take tiles from a global cursor (one atomic per tile) and trace each
+// tile's paths with the scheduled loop; the scene record is wave-uniform.
+__global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const BatchScene* __restrict__ scenes,
                                                                          const Tile* __restrict__ tiles, uint32_t ntiles,
                                                                          uint32_t* cursor, float* __restrict__ paths) {
     const uint32_t lane = threadIdx.x & 63;
+    PathStats st;
+    st.clear();
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(cursor, 1u);
@@ -57,12 +78,12 @@ __global__ __launch_bounds__(256, GPSS_BATCH_MIN_WAVES) void batch_kernel(const 
         if (t >= ntiles) break;
         const Tile tl = tiles[t];
         const BatchScene& B = scenes[tl.scene];
-        for (uint32_t k = lane; k < tl.count; k += 64) {
-            const uint64_t p = tl.p0 + k;
-            const uint32_t pixel = (uint32_t)(p / B.spp), sample = (uint32_t)(p % B.spp);
-            PathStats st;
-            paths[B.path_base + p] = trace_path<false>(B.S, pixel, sample, st);
-        }
+        TileSource src;
+        src.next = tl.p0;
+        src.end = tl.p0 + tl.count;
+        src.base = B.path_base;
+        src.spp = B.spp;
+        run_scheduled<false>(B.S, src, paths, st);
     }
 }
 
@@ -126,7 +147,7 @@ void free_plan(BatchPlan* P) {
 // Batch signature for the tuning cache: device and the work of every scene.
 std::string signature(gpss_scene* const* scenes, uint32_t n, int cus) {
     std::ostringstream o;
-    o << "cus" << cus;
+    o << "sched;cus" << cus;
     for (uint32_t i = 0; i < n; ++i) {
         const gpss_scene_desc& D = scenes[i]->desc;
         o << ";" << D.mean_kind << "," << D.n_prims << "," << D.width << "x" << D.height << "," << D.spp << ","
@@ -182,7 +203,7 @@ static int build_plan(gpss_scene* const* scenes, uint32_t n, uint32_t tile, uint
     int cus = 0;
     int rc = get_cus(scenes[0]->device, cus);
     P->tile = tile;
-    P->grid = (uint32_t)std::max(1, cus) * waves_per_cu / 4u;
+    P->grid = std::max(1u, (uint32_t)std::max(1, cus) * waves_per_cu / 4u);
     std::vector<Tile> tiles;
     uint64_t pbase = 0, xbase = 0;
     if (!rc) rc = check_hip(hipHostMalloc(reinterpret_cast<void**>(&P->h_scenes), n * sizeof(BatchScene)),
@@ -301,10 +322,10 @@ int render_batch(gpss_scene* const* scenes, uint32_t n, float* const* images, hi
         int cus = 0;
         rc = get_cus(scenes[0]->device, cus);
         if (rc) return rc;
-        uint32_t tile = 0, wpc = 16;
+        uint32_t tile = 0, wpc = 4u * GPSS_SCHED_MIN_WAVES;
         if (!cache_lookup(signature(scenes, n, cus), tile, wpc)) {
-            tile = 1024;
-            wpc = 16;
+            tile = 4096;
+            wpc = 4u * GPSS_SCHED_MIN_WAVES;
         }
         rc = build_plan(scenes, n, tile, wpc, &P);
         if (rc) return rc;
@@ -323,8 +344,8 @@ int autotune_batch(gpss_scene* const* scenes, uint32_t n, float* const* images, 
     int cus = 0;
     rc = get_cus(scenes[0]->device, cus);
     if (rc) return rc;
-    const uint32_t tiles[] = {256, 1024, 4096};
-    const uint32_t wpcs[] = {8, 16, 24};
+    const uint32_t tiles[] = {1024, 4096, 16384};
+    const uint32_t wpcs[] = {4u * (GPSS_SCHED_MIN_WAVES - 1), 4u * GPSS_SCHED_MIN_WAVES};
     float bms = 1e30f;
     BatchPlan* best = nullptr;
     hipEvent_t e0, e1;

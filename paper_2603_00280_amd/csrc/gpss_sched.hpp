@@ -1,0 +1,263 @@
+// Scheduled path tracing loop of the persistent kernels (single render and batch).
+//
+// One lane carries one path at a time through a small state machine; idle lanes take new
+// paths from a path source.  A path's work splits into operations of very different cost:
+//   walk    - one majorant-cell step of the current segment (cheap, most frequent);
+//   eval    - medium evaluation at a tentative collision (density, projected area) and its
+//             outcome: accept/reject for delta tracking, the transmittance factor and
+//             Russian roulette for ratio tracking;
+//   scatter - at a real collision: light-connection set-up and phase-function sampling;
+//   begin   - start of a segment (box clip, cell walker, first free-flight draw), either
+//             the next track segment or a shadow ray toward one light.
+// Each iteration the wave counts its lanes per pending operation (ballots) and runs ONE
+// operation for all lanes waiting on it.  Expensive operations wait until enough lanes
+// are ready, so that they run with most lanes active; while they wait, the other lanes
+// keep walking.  Every decision is wave-uniform, so the only divergence left is inside an
+// operation.
+//
+// Per path the operations run in the same order, with the same random-number streams and
+// the same floating-point roundings as the one-thread-per-path routine trace_path; the
+// path radiances are bit-identical to it.
+#pragma once
+
+#include "gpss_trace.hpp"
+#include "gpss_waves.hpp"
+
+namespace gpss {
+
+enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBegin = 4 };
+
+// Minimum number of waiting lanes (of 64) before an operation runs while other lanes could
+// still walk, and the number of cell steps per walk operation.
+#ifndef GPSS_SCHED_EVAL_MIN
+#define GPSS_SCHED_EVAL_MIN 16
+#endif
+#ifndef GPSS_SCHED_SCATTER_MIN
+#define GPSS_SCHED_SCATTER_MIN 16
+#endif
+#ifndef GPSS_SCHED_BEGIN_MIN
+#define GPSS_SCHED_BEGIN_MIN 16
+#endif
+#ifndef GPSS_SCHED_REFILL_MIN
+#define GPSS_SCHED_REFILL_MIN 8
+#endif
+#ifndef GPSS_SCHED_WALK_STEPS
+#define GPSS_SCHED_WALK_STEPS 4
+#endif
+#ifndef GPSS_SCHED_MIN_WAVES
+#define GPSS_SCHED_MIN_WAVES 3
+#endif
+
+// Trace every path of `src` (a wave-collective path source: take(idle, slot, pixel, sample)
+// hands idle lanes new paths, exhausted() is wave-uniform) and write each path's radiance to
+// paths[slot].  Must be called by whole waves; returns when the source is exhausted and
+// every lane's path has ended.
+template <bool STATS, class Source>
+__device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, float* __restrict__ paths,
+                                              PathStats& st) {
+    int op = kOpIdle;
+    uint32_t p = 0, pixel = 0, sample = 0;
+    int b = 0;                 // real collisions so far
+    int mode = 0;              // current segment: 0 track, 1 + li shadow ray toward light li
+    bool has0 = false, has1 = false, dead = false;
+    float beta = 0.0f, L = 0.0f, Tr = 1.0f;
+    float bp0 = 0.0f, bp1 = 0.0f, le0 = 0.0f, le1 = 0.0f;
+    D3 wnext = d3(0.0, 0.0, 0.0);   // direction of the next track segment
+    float3 df = f3(0.0f, 0.0f, 0.0f);
+    Segment sg;
+    sg.o = d3(0.0, 0.0, 0.0);
+    Rng rng;
+
+    for (;;) {
+        const uint64_t mIdle = __ballot(op == kOpIdle);
+        const uint64_t mWalk = __ballot(op == kOpWalk);
+        const uint64_t mEval = __ballot(op == kOpEval);
+        const uint64_t mScat = __ballot(op == kOpScatter);
+        const uint64_t mBegin = __ballot(op == kOpBegin);
+        const int nIdle = __popcll(mIdle), nWalk = __popcll(mWalk), nEval = __popcll(mEval),
+                  nScat = __popcll(mScat), nBegin = __popcll(mBegin);
+        const int nBusy = nWalk + nEval + nScat + nBegin;
+
+        // ---- refill idle lanes with new paths (camera rays) ----
+        if (nIdle > 0 && !src.exhausted() && (nIdle >= GPSS_SCHED_REFILL_MIN || nBusy == 0)) {
+            if (src.take(op == kOpIdle, p, pixel, sample)) {
+                Rng rc;
+                rc.init(S.key0, S.key1, pixel, sample, 0u, kStreamCam);
+                const float ux = rc.uniform(), uy = rc.uniform();
+                D3 o, d;
+                camera_ray(S, pixel, ux, uy, o, d);
+                sg.o = o;
+                wnext = d;
+                beta = 1.0f;
+                L = 0.0f;
+                b = 0;
+                mode = 0;
+                dead = false;
+                op = kOpBegin;
+            }
+            continue;
+        }
+        if (nBusy == 0) break;  // every lane idle and no paths left
+
+        // ---- phase sampling and light-connection set-up at real collisions ----
+        if (nScat > 0 && (nScat >= GPSS_SCHED_SCATTER_MIN || nWalk + nEval + nBegin == 0)) {
+            if (op == kOpScatter) {
+                ++b;
+                const D3 x = sg.o + sg.t * sg.d;
+                const D3 d = sg.d;
+                const PointQ q = eval_point(S, to_f3(x));
+                has0 = has1 = false;
+#pragma unroll
+                for (int li = 0; li < 2; ++li) {
+                    D3 wl;
+                    double tend;
+                    float Le;
+                    if (!light_sample(S, li, x, wl, tend, Le)) continue;
+                    if (STATS) st.nee++;
+                    const float ph = phase_eval(q, df, to_f3(wl));
+                    if (li == 0) { has0 = true; bp0 = mul_rn(beta, ph); le0 = Le; }
+                    else { has1 = true; bp1 = mul_rn(beta, ph); le1 = Le; }
+                }
+                rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamPhase);
+                D3 wi;
+                float wgt, pdf;
+                float3 wm;
+                if (STATS) st.phase++;
+                if (sample_scatter(S, q, d, df, rng, wi, wgt, wm, pdf)) {
+                    beta = mul_rn(beta, wgt);
+                    wnext = wi;
+                } else {
+                    dead = true;   // the path ends after this vertex's light connections
+                }
+                sg.o = x;
+                mode = has0 ? 1 : (has1 ? 2 : 0);
+                if (mode == 0 && dead) {
+                    paths[p] = L;
+                    op = kOpIdle;
+                } else {
+                    op = kOpBegin;
+                }
+            }
+            continue;
+        }
+
+        // ---- segment starts: next track segment or shadow ray ----
+        if (nBegin > 0 && (nBegin >= GPSS_SCHED_BEGIN_MIN || nWalk + nEval == 0)) {
+            if (op == kOpBegin) {
+                if (mode == 0) {
+                    const D3 o = sg.o, d = wnext;
+                    double t0, t1;
+                    if (!clip_box(S, o, d, t0, t1)) {
+                        L = add_rn(L, mul_rn(beta, S.env));
+                        if (STATS) st.escaped++;
+                        paths[p] = L;
+                        op = kOpIdle;
+                    } else {
+                        rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamTrack);
+                        df = to_f3(d);
+                        sg.begin<STATS>(S, o, d, t0, t1, rng, st);
+                        op = kOpWalk;
+                    }
+                } else {
+                    const int li = mode - 1;
+                    const D3 x = sg.o;
+                    D3 wl;
+                    double tend;
+                    float Le;
+                    light_sample(S, li, x, wl, tend, Le);
+                    rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
+                    df = to_f3(wl);
+                    sg.begin<STATS>(S, x, wl, 0.0, tend, rng, st);
+                    Tr = 1.0f;
+                    op = kOpWalk;
+                }
+            }
+            continue;
+        }
+
+        // ---- medium evaluation at tentative collisions ----
+        bool nee_done = false;
+        if (nEval > 0 && (nEval >= GPSS_SCHED_EVAL_MIN || nWalk == 0)) {
+            if (op == kOpEval) {
+                if (STATS) {
+                    if (mode == 0) st.track_steps++;
+                    else st.nee_steps++;
+                }
+                const bool capped = ++sg.steps > kStepCap;
+                float u2 = 0.0f;
+                if (!capped && mode == 0) u2 = rng.uniform();
+                const PointQ q = eval_point(S, sg.pos());
+                const float sig = sigma_t_of(q, df);
+                if (capped) {
+                    if (STATS) st.capped++;
+                    if (mode == 0) {
+                        paths[p] = L;
+                        op = kOpIdle;
+                    } else {
+                        Tr = 0.0f;
+                        nee_done = true;
+                    }
+                } else {
+                    if (STATS && sig > sg.maj) st.violations++;
+                    if (mode == 0) {
+                        if (u2 * sg.maj < sig) {
+                            if (STATS) st.real++;
+                            if (b + 1 > S.max_depth) {
+                                if (STATS) st.truncated++;
+                                paths[p] = L;
+                                op = kOpIdle;
+                            } else {
+                                op = kOpScatter;
+                            }
+                        } else {
+                            sg.redraw(rng);
+                            op = kOpWalk;
+                        }
+                    } else {
+                        Tr *= 1.0f - sig / sg.maj;
+                        if (!roulette(Tr, rng)) {
+                            Tr = 0.0f;
+                            nee_done = true;
+                        } else {
+                            sg.redraw(rng);
+                            op = kOpWalk;
+                        }
+                    }
+                }
+            }
+        } else if (op == kOpWalk) {
+            // ---- cell walk: up to GPSS_SCHED_WALK_STEPS events per lane ----
+#pragma unroll 1
+            for (int k = 0; k < GPSS_SCHED_WALK_STEPS; ++k) {
+                const int ev = sg.step<STATS>(S, st);
+                if (ev == kCell) continue;
+                if (ev == kTentative) {
+                    op = kOpEval;
+                } else if (mode == 0) {   // track segment left the medium
+                    L = add_rn(L, mul_rn(beta, S.env));
+                    if (STATS) st.escaped++;
+                    paths[p] = L;
+                    op = kOpIdle;
+                } else {
+                    nee_done = true;
+                }
+                break;
+            }
+        }
+        if (nee_done) {
+            // shadow ray finished: add its contribution, then the next light or the next
+            // track segment (or the end of a path whose phase sample was degenerate)
+            const bool first = mode == 1;
+            L = add_rn(L, nee_contribution(first ? bp0 : bp1, Tr, first ? le0 : le1));
+            mode = (first && has1) ? 2 : 0;
+            if (mode == 0 && dead) {
+                paths[p] = L;
+                op = kOpIdle;
+            } else {
+                op = kOpBegin;
+            }
+        }
+    }
+}
+
+}  // namespace gpss

@@ -60,7 +60,7 @@ def test_batch_autotune_and_cache(G, tmp_path):
         outs = [torch.empty(g.shape, device="cuda") for g in gs]
         best = G.gpss_batch_autotune([g.handle for g in gs], [o.data_ptr() for o in outs])
         print("   tuned", best, flush=True)
-        assert best["tile"] in (256, 1024, 4096) and best["waves_per_cu"] in (8, 16, 24)
+        assert best["tile"] in (1024, 4096, 16384) and best["waves_per_cu"] in (8, 12)
         assert (tmp_path / "tune.txt").exists()
         imgs = G.render_batch(gs)
         for a, b in zip(imgs, ref):
