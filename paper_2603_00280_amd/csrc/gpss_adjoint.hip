@@ -133,6 +133,7 @@ __device__ void ratio_track_grad(const SceneDev& S, D3 o, D3 d, float3 df, doubl
         const int ev = sg.step<false>(S, st);
         if (ev == kCell) continue;
         if (ev == kEnd) return;
+        sg.advance();
         if (++sg.steps > kStepCap) return;
         const float3 x = sg.pos();
         const PointQ q = eval_point(S, x);
@@ -173,6 +174,7 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
             const int ev = sg.step<false>(S, st);
             if (ev == kCell) continue;
             if (ev == kEnd) break;
+            sg.advance();
             if (++sg.steps > kStepCap) break;
             const float u2 = rng.uniform();
             const float3 x = sg.pos();

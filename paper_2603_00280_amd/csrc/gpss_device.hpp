@@ -460,18 +460,27 @@ __device__ __forceinline__ bool clip_box(const SceneDev& S, D3 o, D3 d, double& 
 // Majorant-grid walker (3D DDA).  Boundary distances are computed once per segment with
 // one reciprocal per axis and then advanced by the per-axis cell width in distance.
 struct Walker {
-    int ix, iy, iz;
     double tx, ty, tz;      // distance to the next boundary on each axis
     double dtx, dty, dtz;   // distance between successive boundaries on each axis
-    int sx, sy, sz;
+    int idx;                // flat index of the current cell (x fastest)
+    int nx, ny, nz;         // cells left in the grid along each axis in the direction of travel
+    int stx, sty, stz;      // flat-index step of a crossing along each axis
     __device__ __forceinline__ void init(const SceneDev& S, D3 o, D3 d, double t) {
         const D3 p = o + t * d;
-        ix = min(max((int)floor((p.x - S.lo_d[0]) * S.inv_cw_d[0]), 0), S.M[0] - 1);
-        iy = min(max((int)floor((p.y - S.lo_d[1]) * S.inv_cw_d[1]), 0), S.M[1] - 1);
-        iz = min(max((int)floor((p.z - S.lo_d[2]) * S.inv_cw_d[2]), 0), S.M[2] - 1);
+        const int ix = min(max((int)floor((p.x - S.lo_d[0]) * S.inv_cw_d[0]), 0), S.M[0] - 1);
+        const int iy = min(max((int)floor((p.y - S.lo_d[1]) * S.inv_cw_d[1]), 0), S.M[1] - 1);
+        const int iz = min(max((int)floor((p.z - S.lo_d[2]) * S.inv_cw_d[2]), 0), S.M[2] - 1);
+        int sx, sy, sz;
         axis(S.lo_d[0], S.cw_d[0], o.x, d.x, ix, tx, dtx, sx);
         axis(S.lo_d[1], S.cw_d[1], o.y, d.y, iy, ty, dty, sy);
         axis(S.lo_d[2], S.cw_d[2], o.z, d.z, iz, tz, dtz, sz);
+        idx = (iz * S.M[1] + iy) * S.M[0] + ix;
+        nx = sx > 0 ? S.M[0] - 1 - ix : (sx < 0 ? ix : 0);
+        ny = sy > 0 ? S.M[1] - 1 - iy : (sy < 0 ? iy : 0);
+        nz = sz > 0 ? S.M[2] - 1 - iz : (sz < 0 ? iz : 0);
+        stx = sx;
+        sty = sy * S.M[0];
+        stz = sz * S.M[0] * S.M[1];
     }
     __device__ __forceinline__ static void axis(double lo, double cw, double o, double d, int i, double& tn,
                                                 double& dt, int& s) {
@@ -491,23 +500,30 @@ struct Walker {
             s = 0;
         }
     }
-    __device__ __forceinline__ float majorant(const SceneDev& S) const {
-        return S.maj[(iz * S.M[1] + iy) * S.M[0] + ix];
-    }
-    // distance along the ray to the exit of the current cell and the axis crossed
+    __device__ __forceinline__ float majorant(const SceneDev& S) const { return S.maj[idx]; }
+    // distance along the ray to the exit of the current cell and the axis crossed (ties go
+    // to the lower axis)
     __device__ __forceinline__ double exit(int& ax) const {
-        ax = 0;
-        double best = tx;
-        if (ty < best) { best = ty; ax = 1; }
-        if (tz < best) { best = tz; ax = 2; }
-        return best;
+        const bool y = ty < tx;
+        const double bxy = y ? ty : tx;
+        const bool z = tz < bxy;
+        ax = z ? 2 : (y ? 1 : 0);
+        return z ? tz : bxy;
     }
-    __device__ __forceinline__ bool step(const SceneDev& S, int ax) {
-        if (ax == 0) { ix += sx; tx += dtx; return ix >= 0 && ix < S.M[0]; }
-        if (ax == 1) { iy += sy; ty += dty; return iy >= 0 && iy < S.M[1]; }
-        iz += sz;
-        tz += dtz;
-        return iz >= 0 && iz < S.M[2];
+    // cross into the next cell along ax; false if that leaves the grid (written with
+    // lane masks rather than selects of members, so that the walker stays in registers)
+    __device__ __forceinline__ bool step(int ax) {
+        const int m0 = -(int)(ax == 0), m1 = -(int)(ax == 1), m2 = -(int)(ax == 2);
+        const int left = (nx & m0) | (ny & m1) | (nz & m2);
+        if (left <= 0) return false;
+        nx += m0;
+        ny += m1;
+        nz += m2;
+        idx += (stx & m0) | (sty & m1) | (stz & m2);
+        tx += m0 ? dtx : 0.0;
+        ty += m1 ? dty : 0.0;
+        tz += m2 ? dtz : 0.0;
+        return true;
     }
 };
 

@@ -179,6 +179,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
         bool nee_done = false;
         if (nEval > 0 && (nEval >= GPSS_SCHED_EVAL_MIN || nWalk == 0)) {
             if (op == kOpEval) {
+                sg.advance();
                 if (STATS) {
                     if (mode == 0) st.track_steps++;
                     else st.nee_steps++;

@@ -34,9 +34,10 @@ struct Segment {
     __device__ __forceinline__ void redraw(Rng& rng) { tau = -(double)logf(1.0f - rng.uniform()); }
     __device__ __forceinline__ float3 pos() const { return to_f3(o + t * d); }
     // One event of the walk: reach the next tentative collision in the current cell
-    // (kTentative; t and maj updated), cross into the next cell (kCell), or reach the end of
-    // the segment (kEnd).  Callers loop over events, so that lanes of a wave crossing cells
-    // and lanes evaluating collisions progress in the same iterations.
+    // (kTentative; maj set, t left at the start of the cell's remaining part until advance()
+    // moves it to the collision), cross into the next cell (kCell), or reach the end of the
+    // segment (kEnd).  Callers loop over events, so that lanes of a wave crossing cells and
+    // lanes evaluating collisions progress in the same iterations.
     template <bool STATS>
     __device__ __forceinline__ int step(const SceneDev& S, PathStats& st) {
         int ax;
@@ -45,17 +46,18 @@ struct Segment {
         const float m = w.majorant(S);
         const double seg = fmax(0.0, tc - t);
         if (m > 0.0f && tau < (double)m * seg) {
-            t += tau / (double)m;
             maj = m;
             return kTentative;
         }
         if (m > 0.0f) tau -= (double)m * seg;
         t = tc;
         if (tn >= t1) return kEnd;
-        if (!w.step(S, ax)) return kEnd;
+        if (!w.step(ax)) return kEnd;
         if (STATS) st.cells++;
         return kCell;
     }
+    // Move t to the tentative collision found by step().
+    __device__ __forceinline__ void advance() { t += tau / (double)maj; }
 };
 
 // Delta tracking over [t0, t1]: the tentative collision is real iff u2 * majorant < sigma_t.
@@ -68,6 +70,7 @@ __device__ __forceinline__ int delta_track(const SceneDev& S, D3 o, D3 d, float3
         const int ev = sg.step<STATS>(S, st);
         if (ev == kCell) continue;
         if (ev == kEnd) return kEscape;
+        sg.advance();
         if (STATS) st.track_steps++;
         if (++sg.steps > kStepCap) {
             if (STATS) st.capped++;
@@ -107,6 +110,7 @@ __device__ __forceinline__ float ratio_track(const SceneDev& S, D3 o, D3 d, floa
         const int ev = sg.step<STATS>(S, st);
         if (ev == kCell) continue;
         if (ev == kEnd) return Tr;
+        sg.advance();
         if (STATS) st.nee_steps++;
         if (++sg.steps > kStepCap) {
             if (STATS) st.capped++;

@@ -157,6 +157,7 @@ __global__ __launch_bounds__(256, GPSS_WF_TRACK_MIN_WAVES) void wf_track_kernel(
             if (ev == kEnd) {
                 res = kEscape;
             } else {
+                sg.advance();
                 if (STATS) st.track_steps++;
                 if (++sg.steps > kStepCap) {
                     if (STATS) st.capped++;
@@ -306,6 +307,7 @@ __global__ __launch_bounds__(256, GPSS_WF_NEE_MIN_WAVES) void wf_nee_kernel(Scen
             if (ev == kEnd) {
                 done = true;
             } else {
+                sg.advance();
                 if (STATS) st.nee_steps++;
                 if (++sg.steps > kStepCap) {
                     if (STATS) st.capped++;
