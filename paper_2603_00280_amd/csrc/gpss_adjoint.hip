@@ -198,15 +198,15 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
 #pragma unroll 1
         for (int li = 0; li < 2; ++li) {
             nv.E[li] = 0.0f;
-            D3 wl;
+            D3 wl, inv;
             double tend;
             float Le;
-            if (!light_sample(S, li, x, wl, tend, Le)) continue;
+            if (!light_sample(S, li, x, wl, tend, Le, inv)) continue;
             const float3 wlf = to_f3(wl);
             const float p = phase_eval(q, df, wlf);
             Rng rn;
             rn.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
-            const float Tr = ratio_track<false>(S, x, wl, wlf, tend, rn, st);
+            const float Tr = ratio_track<false>(S, x, wl, inv, wlf, tend, rn, st);
             nv.E[li] = nee_contribution(mul_rn(beta, p), Tr, Le);
             Etot = add_rn(Etot, nv.E[li]);
             if (nv.E[li] != 0.0f) {

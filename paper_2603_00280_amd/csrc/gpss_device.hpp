@@ -113,14 +113,15 @@ __device__ __forceinline__ void onb(float3 n, float3& t, float3& b) {
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds, each two 32x32 -> 64-bit products,
-// key bumped by the Weyl constants between rounds.
-// ---------------------------------------------------------------------------
+// key bumped by the Weyl constants between rounds.  Each product is one 64-bit multiply
+// (both halves from one v_mad_u64_u32).
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k.y,
+                       (uint32_t)p0);
         k.x += 0x9E3779B9u;
         k.y += 0xBB67AE85u;
     }
@@ -284,19 +285,24 @@ __device__ __forceinline__ float rho_of(float mu, float sigma) {
 }
 
 // Projected area sigma(d) = E[max(0, -d.g)], g ~ N(G, s^2 I): with m = d.G, z = m / s,
-//   s phi(z) - m Phi(-z);  for z > 0 written as s phi(z) (1 - z sqrt(pi/2) erfcx(z/sqrt2)).
-// Equals the paper's Lambda(w) cos(theta) for G of unit length; scales with |G| otherwise.
+//   s phi(z) - m Phi(-z) = max(-m, 0) + s phi(z) (1 - |z| sqrt(pi/2) erfcx(|z|/sqrt2)),
+// one scaled complementary error function for either sign of z (Phi of a non-positive
+// argument written as sqrt(pi/2) phi erfcx).  Equals the paper's Lambda(w) cos(theta) for G
+// of unit length; scales with |G| otherwise.
 __device__ __forceinline__ float sigma_proj(float3 G, float s, float3 d) {
     const float m = dot(d, G);
     const float z = m / s;
+    const float az = fabsf(z);
     const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
-    if (z <= 0.0f) return s * ph - m * (1.0f - 0.5f * erfcf(-z * kInvSqrt2));
-    return s * ph * (1.0f - z * kSqrtHalfPi * erfcxf(z * kInvSqrt2));
+    return fmaxf(-m, 0.0f) + s * ph * (1.0f - az * kSqrtHalfPi * erfcxf(az * kInvSqrt2));
 }
 
 // Generalized NDF (Sec. 4.2.2) for g ~ N(G, s^2 I): int_0^inf P(t wm) t^3 dt in closed form,
 //   D = s (2 pi)^(-3/2) [ (k^2 + 2) e^{-|G|^2/(2 s^2)} + sqrt(2 pi) k (k^2 + 3) e^{-q/2} Phi(k) ],
-// k = G.wm / s, q = |G x wm|^2 / s^2; for k < 0, e^{-q/2} Phi(k) = e^{-|G|^2/(2s^2)} erfcx(-k/sqrt2)/2.
+// k = G.wm / s, q = |G x wm|^2 / s^2 (so |G|^2/s^2 = k^2 + q).  With e^{-q/2} Phi(k) written
+// through erfcx(|k|/sqrt2) for either sign of k:
+//   D = s (2 pi)^(-3/2) [ e^{-|G|^2/(2s^2)} ((k^2+2) - sqrt(pi/2) |k| (k^2+3) erfcx(|k|/sqrt2))
+//                         + [k > 0] sqrt(2 pi) k (k^2+3) e^{-q/2} ].
 __device__ __forceinline__ float ndf(float3 G, float s, float3 wm) {
     const float is = 1.0f / s;
     const float k = dot(G, wm) * is;
@@ -305,13 +311,10 @@ __device__ __forceinline__ float ndf(float3 G, float s, float3 wm) {
     const float g2 = dot(G, G) * is * is;
     const float eG = expf(-0.5f * g2);
     const float pre = s * kInv2PiPow1p5;
-    const float k2 = k * k;
-    if (k >= 0.0f) {
-        const float E = expf(-0.5f * q) * (1.0f - 0.5f * erfcf(k * kInvSqrt2));
-        return pre * ((k2 + 2.0f) * eG + kSqrt2Pi * k * (k2 + 3.0f) * E);
-    }
-    const float b = (k2 + 2.0f) + kSqrtHalfPi * k * (k2 + 3.0f) * erfcxf(-k * kInvSqrt2);
-    return pre * eG * fmaxf(b, 0.0f);
+    const float k2 = k * k, ak = fabsf(k);
+    const float b = (k2 + 2.0f) - kSqrtHalfPi * ak * (k2 + 3.0f) * erfcxf(ak * kInvSqrt2);
+    const float up = k > 0.0f ? kSqrt2Pi * k * (k2 + 3.0f) * expf(-0.5f * q) : 0.0f;
+    return pre * fmaxf(eG * b + up, 0.0f);
 }
 
 __device__ __forceinline__ float sigma_t_of(const PointQ& q, float3 d) {
@@ -439,22 +442,29 @@ __device__ __forceinline__ float3 sample_half_vector(const Proposal& p, float3 v
 // ---------------------------------------------------------------------------
 // Ray / box clipping and majorant-grid walking.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool clip_box(const SceneDev& S, D3 o, D3 d, double& t0, double& t1) {
+// Ray-box clip: [t0, t1] of o + t d inside the scene box (slab test with one reciprocal per
+// axis, returned in inv for the cell walker of the same ray).
+__device__ __forceinline__ bool clip_box(const SceneDev& S, D3 o, D3 d, double& t0, double& t1, D3& inv) {
+    inv = d3(1.0 / d.x, 1.0 / d.y, 1.0 / d.z);
     t0 = 0.0;
     t1 = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double oa = comp(o, a), da = comp(d, a);
+        const double oa = comp(o, a), da = comp(d, a), ia = comp(inv, a);
         if (da == 0.0) {
             if (oa < S.lo_d[a] || oa > S.hi_d[a]) return false;
             continue;
         }
-        double ta = (S.lo_d[a] - oa) / da, tb = (S.hi_d[a] - oa) / da;
+        double ta = (S.lo_d[a] - oa) * ia, tb = (S.hi_d[a] - oa) * ia;
         if (ta > tb) { const double tmp = ta; ta = tb; tb = tmp; }
         t0 = fmax(t0, ta);
         t1 = fmin(t1, tb);
     }
     return t0 < t1;
+}
+__device__ __forceinline__ bool clip_box(const SceneDev& S, D3 o, D3 d, double& t0, double& t1) {
+    D3 inv;
+    return clip_box(S, o, d, t0, t1, inv);
 }
 
 // Majorant-grid walker (3D DDA).  Boundary distances are computed once per segment with
@@ -465,15 +475,16 @@ struct Walker {
     int idx;                // flat index of the current cell (x fastest)
     int nx, ny, nz;         // cells left in the grid along each axis in the direction of travel
     int stx, sty, stz;      // flat-index step of a crossing along each axis
-    __device__ __forceinline__ void init(const SceneDev& S, D3 o, D3 d, double t) {
+    // walker of ray o + t d from distance t; inv = per-axis reciprocals of d
+    __device__ __forceinline__ void init(const SceneDev& S, D3 o, D3 d, D3 inv, double t) {
         const D3 p = o + t * d;
         const int ix = min(max((int)floor((p.x - S.lo_d[0]) * S.inv_cw_d[0]), 0), S.M[0] - 1);
         const int iy = min(max((int)floor((p.y - S.lo_d[1]) * S.inv_cw_d[1]), 0), S.M[1] - 1);
         const int iz = min(max((int)floor((p.z - S.lo_d[2]) * S.inv_cw_d[2]), 0), S.M[2] - 1);
         int sx, sy, sz;
-        axis(S.lo_d[0], S.cw_d[0], o.x, d.x, ix, tx, dtx, sx);
-        axis(S.lo_d[1], S.cw_d[1], o.y, d.y, iy, ty, dty, sy);
-        axis(S.lo_d[2], S.cw_d[2], o.z, d.z, iz, tz, dtz, sz);
+        axis(S.lo_d[0], S.cw_d[0], o.x, d.x, inv.x, ix, tx, dtx, sx);
+        axis(S.lo_d[1], S.cw_d[1], o.y, d.y, inv.y, iy, ty, dty, sy);
+        axis(S.lo_d[2], S.cw_d[2], o.z, d.z, inv.z, iz, tz, dtz, sz);
         idx = (iz * S.M[1] + iy) * S.M[0] + ix;
         nx = sx > 0 ? S.M[0] - 1 - ix : (sx < 0 ? ix : 0);
         ny = sy > 0 ? S.M[1] - 1 - iy : (sy < 0 ? iy : 0);
@@ -482,15 +493,13 @@ struct Walker {
         sty = sy * S.M[0];
         stz = sz * S.M[0] * S.M[1];
     }
-    __device__ __forceinline__ static void axis(double lo, double cw, double o, double d, int i, double& tn,
-                                                double& dt, int& s) {
+    __device__ __forceinline__ static void axis(double lo, double cw, double o, double d, double inv, int i,
+                                                double& tn, double& dt, int& s) {
         if (d > 0.0) {
-            const double inv = 1.0 / d;
             tn = (lo + (double)(i + 1) * cw - o) * inv;
             dt = cw * inv;
             s = 1;
         } else if (d < 0.0) {
-            const double inv = 1.0 / d;
             tn = (lo + (double)i * cw - o) * inv;
             dt = -cw * inv;
             s = -1;

@@ -42,7 +42,7 @@ enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBe
 #define GPSS_SCHED_REFILL_MIN 8
 #endif
 #ifndef GPSS_SCHED_WALK_STEPS
-#define GPSS_SCHED_WALK_STEPS 4
+#define GPSS_SCHED_WALK_STEPS 6
 #endif
 #ifndef GPSS_SCHED_MIN_WAVES
 #define GPSS_SCHED_MIN_WAVES 3
@@ -147,7 +147,8 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 if (mode == 0) {
                     const D3 o = sg.o, d = wnext;
                     double t0, t1;
-                    if (!clip_box(S, o, d, t0, t1)) {
+                    D3 inv;
+                    if (!clip_box(S, o, d, t0, t1, inv)) {
                         L = add_rn(L, mul_rn(beta, S.env));
                         if (STATS) st.escaped++;
                         paths[p] = L;
@@ -155,19 +156,19 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     } else {
                         rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamTrack);
                         df = to_f3(d);
-                        sg.begin<STATS>(S, o, d, t0, t1, rng, st);
+                        sg.begin<STATS>(S, o, d, inv, t0, t1, rng, st);
                         op = kOpWalk;
                     }
                 } else {
                     const int li = mode - 1;
                     const D3 x = sg.o;
-                    D3 wl;
+                    D3 wl, inv;
                     double tend;
                     float Le;
-                    light_sample(S, li, x, wl, tend, Le);
+                    light_sample(S, li, x, wl, tend, Le, inv);
                     rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
                     df = to_f3(wl);
-                    sg.begin<STATS>(S, x, wl, 0.0, tend, rng, st);
+                    sg.begin<STATS>(S, x, wl, inv, 0.0, tend, rng, st);
                     Tr = 1.0f;
                     op = kOpWalk;
                 }

@@ -20,16 +20,21 @@ struct Segment {
     float maj;      // majorant of the cell holding the current tentative collision
     int steps;      // tentative collisions so far
     template <bool STATS>
-    __device__ __forceinline__ void begin(const SceneDev& S, D3 o_, D3 d_, double t0, double t1_, Rng& rng,
-                                          PathStats& st) {
+    __device__ __forceinline__ void begin(const SceneDev& S, D3 o_, D3 d_, D3 inv, double t0, double t1_,
+                                          Rng& rng, PathStats& st) {
         o = o_;
         d = d_;
         t = t0;
         t1 = t1_;
-        w.init(S, o, d, t0);
+        w.init(S, o, d, inv, t0);
         tau = -(double)logf(1.0f - rng.uniform());
         steps = 0;
         if (STATS) st.cells++;
+    }
+    template <bool STATS>
+    __device__ __forceinline__ void begin(const SceneDev& S, D3 o_, D3 d_, double t0, double t1_, Rng& rng,
+                                          PathStats& st) {
+        begin<STATS>(S, o_, d_, d3(1.0 / d_.x, 1.0 / d_.y, 1.0 / d_.z), t0, t1_, rng, st);
     }
     __device__ __forceinline__ void redraw(Rng& rng) { tau = -(double)logf(1.0f - rng.uniform()); }
     __device__ __forceinline__ float3 pos() const { return to_f3(o + t * d); }
@@ -62,10 +67,10 @@ struct Segment {
 
 // Delta tracking over [t0, t1]: the tentative collision is real iff u2 * majorant < sigma_t.
 template <bool STATS>
-__device__ __forceinline__ int delta_track(const SceneDev& S, D3 o, D3 d, float3 df, double t0, double t1,
-                                           Rng& rng, double& t_hit, PathStats& st) {
+__device__ __forceinline__ int delta_track(const SceneDev& S, D3 o, D3 d, D3 inv, float3 df, double t0,
+                                           double t1, Rng& rng, double& t_hit, PathStats& st) {
     Segment sg;
-    sg.begin<STATS>(S, o, d, t0, t1, rng, st);
+    sg.begin<STATS>(S, o, d, inv, t0, t1, rng, st);
     for (;;) {
         const int ev = sg.step<STATS>(S, st);
         if (ev == kCell) continue;
@@ -101,10 +106,10 @@ __device__ __forceinline__ bool roulette(float& Tr, Rng& rng) {
 // Ratio tracking transmittance over [0, t1]: product of (1 - sigma_t / majorant) at
 // tentative collisions (one uniform each for the free flight), with Russian roulette.
 template <bool STATS>
-__device__ __forceinline__ float ratio_track(const SceneDev& S, D3 o, D3 d, float3 df, double t1, Rng& rng,
-                                             PathStats& st) {
+__device__ __forceinline__ float ratio_track(const SceneDev& S, D3 o, D3 d, D3 inv, float3 df, double t1,
+                                             Rng& rng, PathStats& st) {
     Segment sg;
-    sg.begin<STATS>(S, o, d, 0.0, t1, rng, st);
+    sg.begin<STATS>(S, o, d, inv, 0.0, t1, rng, st);
     float Tr = 1.0f;
     for (;;) {
         const int ev = sg.step<STATS>(S, st);
@@ -145,13 +150,15 @@ __device__ __forceinline__ void camera_ray(const SceneDev& S, uint32_t pixel, fl
 }
 
 // Light direction, segment length inside the medium and arriving radiance for light li
-// (0 directional, 1 point) seen from x; false if the light is absent.
-__device__ __forceinline__ bool light_sample(const SceneDev& S, int li, D3 x, D3& wl, double& tend, float& Le) {
+// (0 directional, 1 point) seen from x; false if the light is absent.  inv receives the
+// per-axis reciprocals of the direction.
+__device__ __forceinline__ bool light_sample(const SceneDev& S, int li, D3 x, D3& wl, double& tend, float& Le,
+                                             D3& inv) {
     double a0, a1;
     if (li == 0) {
         if (!(S.dl[3] > 0.0f)) return false;
         wl = d3(S.dl[0], S.dl[1], S.dl[2]);
-        if (!clip_box(S, x, wl, a0, a1)) a1 = 0.0;
+        if (!clip_box(S, x, wl, a0, a1, inv)) a1 = 0.0;
         tend = a1;
         Le = S.dl[3];
         return true;
@@ -161,10 +168,14 @@ __device__ __forceinline__ bool light_sample(const SceneDev& S, int li, D3 x, D3
     const double r2 = dot(dv, dv);
     const double r = sqrt(r2);
     wl = (1.0 / r) * dv;
-    if (!clip_box(S, x, wl, a0, a1)) a1 = 0.0;
+    if (!clip_box(S, x, wl, a0, a1, inv)) a1 = 0.0;
     tend = fmin(a1, r);
     Le = (float)((double)S.pl[3] / r2);
     return true;
+}
+__device__ __forceinline__ bool light_sample(const SceneDev& S, int li, D3 x, D3& wl, double& tend, float& Le) {
+    D3 inv;
+    return light_sample(S, li, x, wl, tend, Le, inv);
 }
 
 // Phase-function sampling at a real collision (Sec. 4.2.2 proposal): draws (select, a, b)
@@ -210,7 +221,8 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
     int b = 0;
     for (;;) {
         double t0, t1;
-        if (!clip_box(S, o, d, t0, t1)) {
+        D3 inv;
+        if (!clip_box(S, o, d, t0, t1, inv)) {
             L = add_rn(L, mul_rn(beta, S.env));
             if (STATS) st.escaped++;
             break;
@@ -219,7 +231,7 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         double th = 0.0;
         const uint32_t steps_before = st.track_steps;
         const float3 df = to_f3(d);
-                const int res = delta_track<STATS || REC>(S, o, d, df, t0, t1, rng, th, st);
+                const int res = delta_track<STATS || REC>(S, o, d, inv, df, t0, t1, rng, th, st);
         float* r = (REC && b < kmax) ? rec + b * kRecFields : nullptr;
         if (res == kAbsorbed) break;
         if (res == kEscape) {
@@ -242,16 +254,16 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         // next-event estimation: directional light on stream kStreamNee0, point light on +1
 #pragma unroll 1
         for (int li = 0; li < 2; ++li) {
-            D3 wl;
+            D3 wl, inv;
             double tend;
             float Le;
-            if (!light_sample(S, li, x, wl, tend, Le)) continue;
+            if (!light_sample(S, li, x, wl, tend, Le, inv)) continue;
             if (STATS) st.nee++;
             const float3 wlf = to_f3(wl);
             const float p = phase_eval(q, df, wlf);
             Rng rn;
             rn.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
-                        const float Tr = ratio_track<STATS>(S, x, wl, wlf, tend, rn, st);
+                        const float Tr = ratio_track<STATS>(S, x, wl, inv, wlf, tend, rn, st);
             L = add_rn(L, nee_contribution(mul_rn(beta, p), Tr, Le));
             if (REC && r) { r[5 + 2 * li] = p; r[6 + 2 * li] = Tr; }
         }

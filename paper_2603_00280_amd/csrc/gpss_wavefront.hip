@@ -127,7 +127,8 @@ __global__ __launch_bounds__(256, GPSS_WF_TRACK_MIN_WAVES) void wf_track_kernel(
                 const D3 o = d3(W.ox[p], W.oy[p], W.oz[p]);
                 const D3 d = d3(W.dx[p], W.dy[p], W.dz[p]);
                 double t0, t1;
-                if (!clip_box(S, o, d, t0, t1)) {
+                D3 inv;
+                if (!clip_box(S, o, d, t0, t1, inv)) {
                     L = add_rn(L, mul_rn(beta, S.env));
                     if (STATS) st.escaped++;
                     W.out[p] = L;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256, GPSS_WF_TRACK_MIN_WAVES) void wf_track_kernel(
                     pixel_sample(W, p, pixel, sample);
                     rng.init(S.key0, S.key1, pixel, sample, b, kStreamTrack);
                     df = to_f3(d);
-                    sg.begin<STATS>(S, o, d, t0, t1, rng, st);
+                    sg.begin<STATS>(S, o, d, inv, t0, t1, rng, st);
                     active = true;
                 }
             }
@@ -284,13 +285,13 @@ __global__ __launch_bounds__(256, GPSS_WF_NEE_MIN_WAVES) void wf_nee_kernel(Scen
             uint32_t pixel, sample;
             pixel_sample(W, p, pixel, sample);
             const D3 x = d3(W.ox[p], W.oy[p], W.oz[p]);
-            D3 wl;
+            D3 wl, inv;
             double tend;
             float Le;
-            light_sample(S, (int)li, x, wl, tend, Le);
+            light_sample(S, (int)li, x, wl, tend, Le, inv);
             wf = to_f3(wl);
             rng.init(S.key0, S.key1, pixel, sample, b, kStreamNee0 + li);
-            sg.begin<STATS>(S, x, wl, 0.0, tend, rng, st);
+            sg.begin<STATS>(S, x, wl, inv, 0.0, tend, rng, st);
             Tr = 1.0f;
             active = true;
         }
