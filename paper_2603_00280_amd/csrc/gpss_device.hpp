@@ -134,17 +134,39 @@ struct Rng {
     uint4 ctr;
     uint4 buf;
     uint2 key;
-    int pos;
+    int pos;            // next draw: buf[pos]; -1: `carry`, then buf[0]
+    uint32_t carry;
     __device__ __forceinline__ void init(uint32_t k0, uint32_t k1, uint32_t pixel, uint32_t sample,
                                          uint32_t bounce, uint32_t stream) {
         key = make_uint2(k0, k1);
         ctr = make_uint4(pixel, sample, (bounce & 0xFFFFu) | (stream << 16), 0u);
         pos = 4;
     }
+    __device__ __forceinline__ void refill() {
+        buf = philox4x32_10(ctr, key);
+        ctr.w += 1u;
+    }
+    // Make the next two draws available without generating a block between them: a block
+    // that next() would generate later is generated here, the one unread draw of the current
+    // block kept ahead of it.  The sequence of draws is unchanged; callers use this to
+    // generate blocks at one place per operation.
+    __device__ __forceinline__ void ensure2() {
+        if (pos == 3) {
+            carry = buf.w;
+            refill();
+            pos = -1;
+        } else if (pos == 4) {
+            refill();
+            pos = 0;
+        }
+    }
     __device__ __forceinline__ uint32_t next() {
+        if (pos < 0) {
+            pos = 0;
+            return carry;
+        }
         if (pos == 4) {
-            buf = philox4x32_10(ctr, key);
-            ctr.w += 1u;
+            refill();
             pos = 0;
         }
         const uint32_t r = pos == 0 ? buf.x : (pos == 1 ? buf.y : (pos == 2 ? buf.z : buf.w));

@@ -181,6 +181,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
         if (nEval > 0 && (nEval >= GPSS_SCHED_EVAL_MIN || nWalk == 0)) {
             if (op == kOpEval) {
                 sg.advance();
+                rng.ensure2();   // this operation's draws (collision test or roulette, next flight)
                 if (STATS) {
                     if (mode == 0) st.track_steps++;
                     else st.nee_steps++;
