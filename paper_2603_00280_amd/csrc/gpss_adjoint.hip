@@ -11,9 +11,10 @@
 //   light connection      albedo D(w_h) / (4 sigma(d)) * prod (1 - sigma_t / m) * Le
 // (sigma(d) of a real collision cancels against the phase weight and the light
 // connection).  d C_k = C_k sum over its factors of d log(factor), so a factor contributes
-// d log(factor) times the radiance of all contributions that contain it.  Each thread
-// traces its path once to get the radiance L, then replays the same random streams while
-// carrying the remaining radiance L_rem = L - (contributions already passed), and adds
+// d log(factor) times the radiance of all contributions that contain it.  Each path's
+// radiance L comes from a forward pass of the scheduled tracer; one thread per path then
+// replays the same random streams while carrying the remaining radiance
+// L_rem = L - (contributions already passed), and adds
 //   nulls before vertex k:   -sigma_t / (m - sigma_t) d log sigma_t        x L_rem
 //   vertex k:                d log rho + d log albedo                      x L_rem
 //                            d log D(w_h, light)                           x C_k,light
@@ -258,7 +259,10 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
 #define GPSS_ADJ_MIN_WAVES 4
 #endif
 
+// Replay of every path (pixel p / ns, sample s0 + p % ns) whose radiance paths[p] the
+// forward tracer has just computed.
 __global__ __launch_bounds__(256, GPSS_ADJ_MIN_WAVES) void adjoint_kernel(SceneDev S, const float* __restrict__ dloss,
+                                                                         const float* __restrict__ paths,
                                                                          float* __restrict__ grad_off,
                                                                          float* __restrict__ grad_scalars, uint32_t s0,
                                                                          uint32_t ns, uint64_t npaths) {
@@ -267,12 +271,7 @@ __global__ __launch_bounds__(256, GPSS_ADJ_MIN_WAVES) void adjoint_kernel(SceneD
     if (p < npaths) {
         const uint32_t pixel = (uint32_t)(p / ns), sample = s0 + (uint32_t)(p % ns);
         const float wpix = dloss[pixel] / (float)ns;
-        if (wpix != 0.0f) {
-            PathStats st;
-            st.clear();
-            const float L = trace_path<false>(S, pixel, sample, st);
-            replay_path(S, pixel, sample, L, wpix, grad_off, acc);
-        }
+        if (wpix != 0.0f) replay_path(S, pixel, sample, paths[p], wpix, grad_off, acc);
     }
     float v[3] = {acc.var, acc.len, acc.alb};
 #pragma unroll
@@ -301,7 +300,11 @@ int launch_adjoint(gpss_scene* s, const float* dloss, float* grad_off, float* gr
     const uint64_t npaths = s->n_pixels() * ns;
     const uint64_t blocks = (npaths + 255) / 256;
     if (blocks > 0x7FFFFFFFull) return set_error(GPSS_ERR_INVALID_ARG, "too many paths in one launch");
-    hipLaunchKernelGGL(adjoint_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, s->dev, dloss,
+    // primal pass: every path's radiance from the persistent scheduled tracer
+    int rc = ensure_scratch(s, npaths);
+    if (!rc) rc = sched_render(s, s->d_scratch, nullptr, s0, ns, stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(adjoint_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, s->dev, dloss, s->d_scratch,
                        s->d_offset ? grad_off : nullptr, grad_scalars, s0, ns, npaths);
     return check_hip(hipGetLastError(), "adjoint_kernel launch");
 }
