@@ -36,6 +36,95 @@ WORKLOADS = {
 }
 
 
+# HBM traffic of the render kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by
+# the same counters on a plain copy (see --summarize-traffic); valid only while the kernel
+# sources hash to the recorded value.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sched_render_kernel_sphere_traffic.md")
+KERNEL_SOURCES = ["gpss_sched.hpp", "gpss_persistent.hip", "gpss_trace.hpp", "gpss_device.hpp", "gpss_waves.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_00280_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """Bytes of HBM traffic per render launch recorded for the current kernel, else None."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("    ") and ":" in ln:
+            k, v = ln.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return json.loads(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, commands):
+    """Write TRAFFIC_FILE from four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the
+    bench render and of the plain-copy calibration), each a directory of counter CSVs."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter, kernel):
+        vals = []
+        for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter and kernel in r["Kernel_Name"]:
+                    vals.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        return [v for _, v in sorted(vals)]
+
+    kern = "sched_render_kernel<false>"
+    fetch = per_dispatch(fetch_dir, "FETCH_SIZE", kern)
+    write = per_dispatch(write_dir, "WRITE_SIZE", kern)
+    cf = per_dispatch(copy_fetch_dir, "FETCH_SIZE", "copy")
+    cw = per_dispatch(copy_write_dir, "WRITE_SIZE", "copy")
+    f_fac = copy_bytes / 1024.0 / cf[-1]
+    w_fac = copy_bytes / 1024.0 / cw[-1]
+    traffic = [1024.0 * (a * f_fac + b * w_fac) for a, b in zip(fetch, write)]
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("# HBM traffic of sched_render_kernel on the sphere sweep\n\n")
+        f.write("Counters per dispatch of the forward render kernel (launches of the sphere sweep in\n"
+                "bench order: warm-up and timed renders of the four lengthscales), in KiB, from\n"
+                "separate rocprofv3 runs:\n\n")
+        for c in commands:
+            f.write(f"    {c}\n")
+        f.write("\nA plain device copy of known size calibrates each counter (known bytes / counter\n"
+                "bytes); traffic = FETCH_SIZE x fetch factor + WRITE_SIZE x write factor.\n\n")
+        f.write(f"    source_sha256: {kernel_source_hash()}\n")
+        f.write(f"    fetch_kib_per_launch: {json.dumps(fetch)}\n")
+        f.write(f"    write_kib_per_launch: {json.dumps(write)}\n")
+        f.write(f"    copy_bytes: {copy_bytes}\n")
+        f.write(f"    copy_fetch_kib: {cf[-1]}\n")
+        f.write(f"    copy_write_kib: {cw[-1]}\n")
+        f.write(f"    fetch_factor: {f_fac:.4f}\n")
+        f.write(f"    write_factor: {w_fac:.4f}\n")
+        f.write(f"    traffic_bytes_per_launch: {json.dumps([round(t) for t in traffic])}\n")
+    print(open(TRAFFIC_FILE).read())
+
+
+def copy_calibration(nbytes: int):
+    """One plain device-to-device copy of nbytes (the calibration kernel of the traffic runs)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}), flush=True)
+
+
 TRACERS = {"auto": "persistent scheduled waves", "persistent": "persistent scheduled waves",
            "wavefront": "wavefront", "mega": "one thread per path"}
 
@@ -52,19 +141,21 @@ def make_scenes(name):
 
 
 def cpu_baseline(scenes, spp: int):
-    """FP64 oracle on a bounded sample: every pixel of every scene at `spp` samples."""
+    """FP64 oracle on a bounded sample: every pixel of every scene at `spp` samples, with
+    one OpenMP thread per core available to this process (capped by OMP_NUM_THREADS)."""
     from oracle.oracle import OracleScene
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count() or 1
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
     n = 0
     t0 = time.perf_counter()
     for s in scenes:
-        OracleScene(s).render(0, spp)
+        OracleScene(s).render(0, spp, nthreads=cores)
         n += s.n_pixels * spp
     dt = time.perf_counter() - t0
-    try:
-        import psutil
-        cores = len(psutil.Process().cpu_affinity())
-    except Exception:
-        cores = os.cpu_count()
     return {"value": n / dt / 1e6, "unit": "Mpaths/s", "cores": cores, "kind": "oracle",
             "sample": f"all pixels of each scene at {spp} spp ({n} paths, {dt:.1f} s)",
             "cpu": platform.processor() or platform.machine()}
@@ -150,7 +241,19 @@ def main():
                     help="skip the batched-render measurement on the 64-scene workload")
     ap.add_argument("--tune", action="store_true",
                     help="run the batch autotuner first (its choice is cached on disk)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device copy of BYTES (traffic calibration) and exit")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the traffic profile from four rocprofv3 --pmc output directories and exit")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--commands", nargs="*", default=[], help="commands recorded in the traffic profile")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, args.copy_bytes, args.commands)
+        return
+    if args.calibrate_copy:
+        copy_calibration(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(the renderer shards by sample range across GPUs only by design, not in this build)",
@@ -204,6 +307,11 @@ def main():
     per_scene_ms = [sum(launch_ms[i::len(scenes)]) / args.steps for i in range(len(scenes))]
     # roofline of the render kernel: algorithmic FLOPs of each launch / its duration
     flop_rate = sum(w[0] for w in work) / (sum(per_scene_ms) / 1e3)
+    traffic = None
+    if args.workload == "sphere" and args.kernel in ("auto", "persistent"):
+        rec = recorded_traffic()
+        if rec:
+            traffic = sum(rec) / len(rec)
     avg_launch_ms = sum(launch_ms) / len(launch_ms)
     result = {
         "metric": METRIC,
@@ -222,7 +330,7 @@ def main():
                    "paths_per_step": sum(s.n_paths for s in scenes),
                    "tracer": TRACERS[args.kernel]},
         "roofline": {"bound": "alu", "achieved": flop_rate / 1e12, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": flop_rate / 1e12 / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": flop_rate / 1e12 / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "avg_launch_ms": avg_launch_ms,
                      "flops_per_launch": [w[0] for w in work]},
         "per_scene_mpaths_s": [s.n_paths / (ms / 1e3) / 1e6 for s, ms in zip(scenes, per_scene_ms)],

@@ -52,21 +52,35 @@ enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBe
 // hands idle lanes new paths, exhausted() is wave-uniform) and write each path's radiance to
 // paths[slot].  Must be called by whole waves; returns when the source is exhausted and
 // every lane's path has ended.
+// Threads per workgroup of the kernels that run the scheduled loop (per-lane LDS columns).
+constexpr int kSchedBlock = 256;
+
 template <bool STATS, class Source>
 __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, float* __restrict__ paths,
                                               PathStats& st) {
+    // Cold per-lane state (touched once per segment or vertex) lives in LDS, one column per
+    // lane, so that registers hold what the cell walk and the medium evaluation use.
+    __shared__ uint32_t cs_u[3][kSchedBlock];   // output slot, pixel, sample
+    __shared__ float cs_f[6][kSchedBlock];      // beta, L, beta*phase and Le per light
+    __shared__ double cs_d[3][kSchedBlock];     // direction of the next track segment
+    const int lt = threadIdx.x;
+    enum { kSlot = 0, kPixel = 1, kSample = 2 };
+    enum { kBeta = 0, kL = 1, kBp0 = 2, kBp1 = 3, kLe0 = 4, kLe1 = 5 };
+    enum { kHas0 = 1, kHas1 = 2, kDead = 4 };
+
     int op = kOpIdle;
-    uint32_t p = 0, pixel = 0, sample = 0;
     int b = 0;                 // real collisions so far
     int mode = 0;              // current segment: 0 track, 1 + li shadow ray toward light li
-    bool has0 = false, has1 = false, dead = false;
-    float beta = 0.0f, L = 0.0f, Tr = 1.0f;
-    float bp0 = 0.0f, bp1 = 0.0f, le0 = 0.0f, le1 = 0.0f;
-    D3 wnext = d3(0.0, 0.0, 0.0);   // direction of the next track segment
+    int flags = 0;             // kHas0 | kHas1 (lights connected at this vertex) | kDead
+    float Tr = 1.0f;
     float3 df = f3(0.0f, 0.0f, 0.0f);
     Segment sg;
     sg.o = d3(0.0, 0.0, 0.0);
     Rng rng;
+    auto finish = [&](float L) {   // the path's radiance to its output slot; the lane falls idle
+        paths[cs_u[kSlot][lt]] = L;
+        op = kOpIdle;
+    };
 
     for (;;) {
         const uint64_t mIdle = __ballot(op == kOpIdle);
@@ -80,19 +94,25 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
 
         // ---- refill idle lanes with new paths (camera rays) ----
         if (nIdle > 0 && !src.exhausted() && (nIdle >= GPSS_SCHED_REFILL_MIN || nBusy == 0)) {
-            if (src.take(op == kOpIdle, p, pixel, sample)) {
+            uint32_t slot = 0, pixel = 0, sample = 0;
+            if (src.take(op == kOpIdle, slot, pixel, sample)) {
                 Rng rc;
                 rc.init(S.key0, S.key1, pixel, sample, 0u, kStreamCam);
                 const float ux = rc.uniform(), uy = rc.uniform();
                 D3 o, d;
                 camera_ray(S, pixel, ux, uy, o, d);
+                cs_u[kSlot][lt] = slot;
+                cs_u[kPixel][lt] = pixel;
+                cs_u[kSample][lt] = sample;
+                cs_d[0][lt] = d.x;
+                cs_d[1][lt] = d.y;
+                cs_d[2][lt] = d.z;
+                cs_f[kBeta][lt] = 1.0f;
+                cs_f[kL][lt] = 0.0f;
                 sg.o = o;
-                wnext = d;
-                beta = 1.0f;
-                L = 0.0f;
                 b = 0;
                 mode = 0;
-                dead = false;
+                flags = 0;
                 op = kOpBegin;
             }
             continue;
@@ -106,7 +126,8 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 const D3 x = sg.o + sg.t * sg.d;
                 const D3 d = sg.d;
                 const PointQ q = eval_point(S, to_f3(x));
-                has0 = has1 = false;
+                float beta = cs_f[kBeta][lt];
+                flags = 0;
 #pragma unroll
                 for (int li = 0; li < 2; ++li) {
                     D3 wl;
@@ -115,28 +136,27 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     if (!light_sample(S, li, x, wl, tend, Le)) continue;
                     if (STATS) st.nee++;
                     const float ph = phase_eval(q, df, to_f3(wl));
-                    if (li == 0) { has0 = true; bp0 = mul_rn(beta, ph); le0 = Le; }
-                    else { has1 = true; bp1 = mul_rn(beta, ph); le1 = Le; }
+                    flags |= li == 0 ? kHas0 : kHas1;
+                    cs_f[kBp0 + li][lt] = mul_rn(beta, ph);
+                    cs_f[kLe0 + li][lt] = Le;
                 }
-                rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamPhase);
+                rng.init(S.key0, S.key1, cs_u[kPixel][lt], cs_u[kSample][lt], (uint32_t)b, kStreamPhase);
                 D3 wi;
                 float wgt, pdf;
                 float3 wm;
                 if (STATS) st.phase++;
                 if (sample_scatter(S, q, d, df, rng, wi, wgt, wm, pdf)) {
-                    beta = mul_rn(beta, wgt);
-                    wnext = wi;
+                    cs_f[kBeta][lt] = mul_rn(beta, wgt);
+                    cs_d[0][lt] = wi.x;
+                    cs_d[1][lt] = wi.y;
+                    cs_d[2][lt] = wi.z;
                 } else {
-                    dead = true;   // the path ends after this vertex's light connections
+                    flags |= kDead;   // the path ends after this vertex's light connections
                 }
                 sg.o = x;
-                mode = has0 ? 1 : (has1 ? 2 : 0);
-                if (mode == 0 && dead) {
-                    paths[p] = L;
-                    op = kOpIdle;
-                } else {
-                    op = kOpBegin;
-                }
+                mode = (flags & kHas0) ? 1 : ((flags & kHas1) ? 2 : 0);
+                if (mode == 0 && (flags & kDead)) finish(cs_f[kL][lt]);
+                else op = kOpBegin;
             }
             continue;
         }
@@ -144,15 +164,14 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
         // ---- segment starts: next track segment or shadow ray ----
         if (nBegin > 0 && (nBegin >= GPSS_SCHED_BEGIN_MIN || nWalk + nEval == 0)) {
             if (op == kOpBegin) {
+                const uint32_t pixel = cs_u[kPixel][lt], sample = cs_u[kSample][lt];
                 if (mode == 0) {
-                    const D3 o = sg.o, d = wnext;
+                    const D3 o = sg.o, d = d3(cs_d[0][lt], cs_d[1][lt], cs_d[2][lt]);
                     double t0, t1;
                     D3 inv;
                     if (!clip_box(S, o, d, t0, t1, inv)) {
-                        L = add_rn(L, mul_rn(beta, S.env));
                         if (STATS) st.escaped++;
-                        paths[p] = L;
-                        op = kOpIdle;
+                        finish(add_rn(cs_f[kL][lt], mul_rn(cs_f[kBeta][lt], S.env)));
                     } else {
                         rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamTrack);
                         df = to_f3(d);
@@ -194,8 +213,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 if (capped) {
                     if (STATS) st.capped++;
                     if (mode == 0) {
-                        paths[p] = L;
-                        op = kOpIdle;
+                        finish(cs_f[kL][lt]);
                     } else {
                         Tr = 0.0f;
                         nee_done = true;
@@ -207,8 +225,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                             if (STATS) st.real++;
                             if (b + 1 > S.max_depth) {
                                 if (STATS) st.truncated++;
-                                paths[p] = L;
-                                op = kOpIdle;
+                                finish(cs_f[kL][lt]);
                             } else {
                                 op = kOpScatter;
                             }
@@ -237,10 +254,8 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 if (ev == kTentative) {
                     op = kOpEval;
                 } else if (mode == 0) {   // track segment left the medium
-                    L = add_rn(L, mul_rn(beta, S.env));
                     if (STATS) st.escaped++;
-                    paths[p] = L;
-                    op = kOpIdle;
+                    finish(add_rn(cs_f[kL][lt], mul_rn(cs_f[kBeta][lt], S.env)));
                 } else {
                     nee_done = true;
                 }
@@ -250,15 +265,12 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
         if (nee_done) {
             // shadow ray finished: add its contribution, then the next light or the next
             // track segment (or the end of a path whose phase sample was degenerate)
-            const bool first = mode == 1;
-            L = add_rn(L, nee_contribution(first ? bp0 : bp1, Tr, first ? le0 : le1));
-            mode = (first && has1) ? 2 : 0;
-            if (mode == 0 && dead) {
-                paths[p] = L;
-                op = kOpIdle;
-            } else {
-                op = kOpBegin;
-            }
+            const int li = mode - 1;
+            const float L = add_rn(cs_f[kL][lt], nee_contribution(cs_f[kBp0 + li][lt], Tr, cs_f[kLe0 + li][lt]));
+            cs_f[kL][lt] = L;
+            mode = (li == 0 && (flags & kHas1)) ? 2 : 0;
+            if (mode == 0 && (flags & kDead)) finish(L);
+            else op = kOpBegin;
         }
     }
 }
