@@ -73,7 +73,6 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
     int mode = 0;              // current segment: 0 track, 1 + li shadow ray toward light li
     int flags = 0;             // kHas0 | kHas1 (lights connected at this vertex) | kDead
     float Tr = 1.0f;
-    float3 df = f3(0.0f, 0.0f, 0.0f);
     Segment sg;
     sg.o = d3(0.0, 0.0, 0.0);
     Rng rng;
@@ -125,6 +124,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 ++b;
                 const D3 x = sg.o + sg.t * sg.d;
                 const D3 d = sg.d;
+                const float3 df = to_f3(d);
                 const PointQ q = eval_point(S, to_f3(x));
                 float beta = cs_f[kBeta][lt];
                 flags = 0;
@@ -174,7 +174,6 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                         finish(add_rn(cs_f[kL][lt], mul_rn(cs_f[kBeta][lt], S.env)));
                     } else {
                         rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamTrack);
-                        df = to_f3(d);
                         sg.begin<STATS>(S, o, d, inv, t0, t1, rng, st);
                         op = kOpWalk;
                     }
@@ -186,7 +185,6 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     float Le;
                     light_sample(S, li, x, wl, tend, Le, inv);
                     rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
-                    df = to_f3(wl);
                     sg.begin<STATS>(S, x, wl, inv, 0.0, tend, rng, st);
                     Tr = 1.0f;
                     op = kOpWalk;
@@ -200,6 +198,13 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
         if (nEval > 0 && (nEval >= GPSS_SCHED_EVAL_MIN || nWalk == 0)) {
             if (op == kOpEval) {
                 sg.advance();
+                // the generator's key and address words are recomputed here rather than kept
+                // live through the other operations: key, pixel, sample, bounce | stream
+                rng.key = make_uint2(S.key0, S.key1);
+                rng.ctr.x = cs_u[kPixel][lt];
+                rng.ctr.y = cs_u[kSample][lt];
+                const uint32_t stream = mode == 0 ? kStreamTrack : kStreamNee0 + (uint32_t)(mode - 1);
+                rng.ctr.z = ((uint32_t)b & 0xFFFFu) | (stream << 16);
                 rng.ensure2();   // this operation's draws (collision test or roulette, next flight)
                 if (STATS) {
                     if (mode == 0) st.track_steps++;
@@ -209,7 +214,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 float u2 = 0.0f;
                 if (!capped && mode == 0) u2 = rng.uniform();
                 const PointQ q = eval_point(S, sg.pos());
-                const float sig = sigma_t_of(q, df);
+                const float sig = sigma_t_of(q, to_f3(sg.d));   // single-precision travel direction
                 if (capped) {
                     if (STATS) st.capped++;
                     if (mode == 0) {
