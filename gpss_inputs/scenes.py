@@ -66,6 +66,7 @@ class Scene:
     max_depth: int = 8
     seed: int = 0
     scene_id: int = 0
+    lengthscale_n: float = 0.0             # lengthscale along the local mean-gradient direction (0: isotropic)
 
     @property
     def n_pixels(self) -> int:

@@ -39,6 +39,8 @@ struct oracle_scene {
     std::vector<Prim> prims;
     Grid offset, var;
     double variance, l, albedo;
+    double l_n;            // lengthscale along the local mean-gradient direction (= l: isotropic)
+    bool aniso;            // l_n != l
     bool albedo_per_prim;
     double lo[3], hi[3], ext[3];
     double R;
@@ -172,15 +174,18 @@ void trilinear(const Grid& G, const Scene& S, const double x[3], Tri& t) {
 
 // ---------------------------------------------------------------------------
 // GP statistics at a point (Sec. 3.1): f(x) ~ N(mu(x), sigma^2) and, independent of it
-// at the same point (Eq. joint_fg), g(x) ~ N(grad mu(x), (sigma/l)^2 I) for the
-// isotropic squared-exponential kernel.
+// at the same point (Eq. joint_fg), g(x) ~ N(grad mu(x), Sigma) with, for the
+// squared-exponential kernel with lengthscale l across and l_n along the local
+// mean-gradient direction n (Eq. se_kernel in that frame; n = z where grad mu = 0),
+//   Sigma = (sigma / l)^2 (I - n n^T) + (sigma / l_n)^2 n n^T.
 // ---------------------------------------------------------------------------
 template <class T>
 struct PointQ {
     T mu;
     T G[3];
     T sigma;
-    T s;       // per-axis gradient standard deviation sigma / l
+    T s;       // gradient standard deviation across n: sigma / l
+    T sn;      // gradient standard deviation along n: sigma / l_n
     T albedo;
 };
 
@@ -230,6 +235,7 @@ PointQ<T> eval_point(const Params<T>& P, const double x[3]) {
     }
     q.sigma = t_sqrt(variance);
     q.s = q.sigma / mk<T>(S.l, P.slot_l);
+    q.sn = S.aniso ? q.sigma / T(S.l_n) : q.s;
     if (S.albedo_per_prim && which >= 0) q.albedo = T(S.prims[which].albedo);
     else q.albedo = mk<T>(S.albedo, P.slot_alb);
     return q;
@@ -275,30 +281,40 @@ T ndf_general(const T& ax, const T& ay, const T& az, const T& c, const T& tx2, c
     return pre * (t1 + t2);
 }
 
-// Projected area for travel direction d at a point whose gradient is g ~ N(G, s^2 I):
-// the paper's Lambda(w) cos(theta) about the local geometric normal G/|G| with the
-// isotropic roughness alpha = sqrt(2) s / |G| (Eq. roughness), scaled by |G|, the length
-// of the mean gradient.
+// Projected area for travel direction d at a point whose gradient is g ~ N(G, Sigma):
+// the paper's Lambda(w) cos(theta) (Eq. generalized_lambda) about the local geometric
+// normal n = G/|G| with roughnesses alpha_x = alpha_y = sqrt(2) s / |G| and
+// alpha_z = sqrt(2) s_n / |G| (Eq. roughness), scaled by |G|, the length of the mean
+// gradient.  Where grad mu = 0: E[max(0, -d.g)] = s_d / sqrt(2 pi), s_d^2 = d^T Sigma d.
 template <class T>
 T sigma_proj(const PointQ<T>& q, const double d[3]) {
     const T g2 = q.G[0] * q.G[0] + q.G[1] * q.G[1] + q.G[2] * q.G[2];
-    if (val(g2) == 0.0) return q.s / kSqrt2Pi;  // E[max(0, -d.g)] for g ~ N(0, s^2 I)
+    if (val(g2) == 0.0) {
+        const T sd = t_sqrt(q.s * q.s * (1.0 - d[2] * d[2]) + q.sn * q.sn * (d[2] * d[2]));
+        return sd / kSqrt2Pi;
+    }
     const T gn = t_sqrt(g2);
     const T c = (q.G[0] * d[0] + q.G[1] * d[1] + q.G[2] * d[2]) / gn;
-    const T alpha = kSqrt2 * q.s / gn;
-    return gn * lambda_cos_general(alpha, alpha, alpha, c, 1.0 - c * c, T(0.0));
+    const T alpha = kSqrt2 * q.s / gn, alpha_n = kSqrt2 * q.sn / gn;
+    return gn * lambda_cos_general(alpha, alpha, alpha_n, c, 1.0 - c * c, T(0.0));
 }
 
-// Generalized NDF at normal wm for g ~ N(G, s^2 I): Eq. macro_ndf with
-// alpha_x = alpha_y = alpha_z = sqrt(2) s / |G| about G/|G|, scaled by |G|.
+// Generalized NDF at normal wm for g ~ N(G, Sigma): Eq. macro_ndf with
+// alpha_x = alpha_y = sqrt(2) s / |G|, alpha_z = sqrt(2) s_n / |G| about n = G/|G|, scaled
+// by |G|.  Where grad mu = 0 (the B = C = 0 limit, n = z):
+//   D = 2 / ((2 pi)^(3/2) s^2 s_n A^2),  A = (1 - c^2) / s^2 + c^2 / s_n^2,  c = wm_z.
 template <class T>
 T ndf(const PointQ<T>& q, const double wm[3]) {
     const T g2 = q.G[0] * q.G[0] + q.G[1] * q.G[1] + q.G[2] * q.G[2];
-    if (val(g2) == 0.0) return q.s / (kSqrt2 * kPi * kSqrtPi);  // isotropic limit
+    if (val(g2) == 0.0) {
+        const double c2 = wm[2] * wm[2];
+        const T A = (1.0 - c2) / (q.s * q.s) + c2 / (q.sn * q.sn);
+        return 2.0 / (2.0 * kPi * kSqrt2Pi * q.s * q.s * q.sn * A * A);
+    }
     const T gn = t_sqrt(g2);
     const T c = (q.G[0] * wm[0] + q.G[1] * wm[1] + q.G[2] * wm[2]) / gn;
-    const T alpha = kSqrt2 * q.s / gn;
-    return gn * ndf_general(alpha, alpha, alpha, c, 1.0 - c * c, T(0.0));
+    const T alpha = kSqrt2 * q.s / gn, alpha_n = kSqrt2 * q.sn / gn;
+    return gn * ndf_general(alpha, alpha, alpha_n, c, 1.0 - c * c, T(0.0));
 }
 
 // Beckmann NDF and Smith Lambda (the height-field limit used by the proposal).
@@ -510,7 +526,7 @@ void build_majorants(Scene& S) {
                 mu_min += off_min;
                 gmax += off_g;
                 const double smin_f = std::sqrt(vmin), smax_f = std::sqrt(vmax);
-                const double s_max = smax_f / S.l;
+                const double s_max = smax_f / std::min(S.l, S.l_n);
                 const double rho_max = r_ratio(mu_min / (mu_min > 0.0 ? smax_f : smin_f)) / smin_f;
                 const double z = gmax / s_max;
                 const double proj_max = gmax * Phi_d(z) + s_max * phi_d(z);
@@ -841,6 +857,7 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
     if (!D || !out) return -1;
     if (D->width <= 0 || D->height <= 0 || D->spp <= 0 || D->max_depth < 0) return -1;
     if (!(D->lengthscale > 0.0) || !(D->albedo >= 0.0 && D->albedo <= 1.0)) return -1;
+    if (!(D->lengthscale_n >= 0.0)) return -1;
     if (!D->var_grid && !(D->variance > 0.0)) return -1;
     for (int a = 0; a < 3; ++a) {
         if (!(D->bounds[3 + a] > D->bounds[a])) return -1;
@@ -870,6 +887,8 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
     load(S->var, D->var_grid, D->var_res);
     S->variance = D->variance;
     S->l = D->lengthscale;
+    S->l_n = D->lengthscale_n > 0.0 ? D->lengthscale_n : D->lengthscale;
+    S->aniso = S->l_n != S->l;
     S->albedo = D->albedo;
     S->albedo_per_prim = D->albedo_per_prim != 0;
     for (int a = 0; a < 3; ++a) {
@@ -1056,12 +1075,13 @@ double oracle_erfcx(double x) { return erfcx_d(x); }
 double oracle_erfinv(double y) { return erfinv_d(y); }
 double oracle_rho(double mu, double sigma) { return rho_of(mu, sigma); }
 
-static PointQ<double> point_from(const double G[3], double s, double albedo) {
+static PointQ<double> point_from(const double G[3], double s, double albedo, double sn = 0.0) {
     PointQ<double> q;
     q.mu = 0.0;
     for (int a = 0; a < 3; ++a) q.G[a] = G[a];
     q.sigma = 0.0;
     q.s = s;
+    q.sn = sn > 0.0 ? sn : s;
     q.albedo = albedo;
     return q;
 }
@@ -1070,6 +1090,12 @@ double oracle_sigma_proj(const double G[3], double s, const double d[3]) {
     return sigma_proj(point_from(G, s, 1.0), d);
 }
 double oracle_ndf(const double G[3], double s, const double wm[3]) { return ndf(point_from(G, s, 1.0), wm); }
+double oracle_sigma_proj_n(const double G[3], double s, double sn, const double d[3]) {
+    return sigma_proj(point_from(G, s, 1.0, sn), d);
+}
+double oracle_ndf_n(const double G[3], double s, double sn, const double wm[3]) {
+    return ndf(point_from(G, s, 1.0, sn), wm);
+}
 double oracle_beckmann_ndf(double alpha, double cos_m) {
     return beckmann_D(alpha, cos_m, std::max(0.0, 1.0 - cos_m * cos_m));
 }

@@ -57,6 +57,7 @@ typedef struct {
     int32_t width, height, spp, max_depth;
     uint64_t seed;
     uint32_t scene_id;
+    double lengthscale_n;       /* lengthscale along the local mean-gradient direction (0: = lengthscale) */
 } oracle_scene_desc;
 
 typedef struct oracle_scene oracle_scene;
@@ -125,6 +126,9 @@ double oracle_ndf(const double G[3], double s, const double wm[3]);
 double oracle_beckmann_ndf(double alpha, double cos_m);
 double oracle_beckmann_lambda(double a);
 /* Eqs. macro_ndf and generalized_lambda with separate roughnesses, local frame (z = normal) */
+/* sigma(d) and D(wm) for g ~ N(G, s^2 (I - n n^T) + sn^2 n n^T), n = G/|G| (z if G = 0) */
+double oracle_sigma_proj_n(const double G[3], double s, double sn, const double d[3]);
+double oracle_ndf_n(const double G[3], double s, double sn, const double wm[3]);
 double oracle_ndf_aniso(double ax, double ay, double az, const double wm[3]);
 double oracle_lambda_aniso(double ax, double ay, double az, const double w[3]);
 double oracle_phase_eval(const double G[3], double s, double albedo, const double d[3],

@@ -36,7 +36,7 @@ class _Desc(C.Structure):
         ("cam_kind", C.c_int32), ("eye", C.c_double * 3), ("target", C.c_double * 3),
         ("up", C.c_double * 3), ("fov_deg", C.c_double), ("window", C.c_double * 2),
         ("width", C.c_int32), ("height", C.c_int32), ("spp", C.c_int32), ("max_depth", C.c_int32),
-        ("seed", C.c_uint64), ("scene_id", C.c_uint32),
+        ("seed", C.c_uint64), ("scene_id", C.c_uint32), ("lengthscale_n", C.c_double),
     ]
 
 
@@ -71,6 +71,9 @@ def lib():
             getattr(L, name).restype = C.c_double
         for name in ("oracle_ndf_aniso", "oracle_lambda_aniso"):
             getattr(L, name).argtypes = [C.c_double, C.c_double, C.c_double, dp]
+            getattr(L, name).restype = C.c_double
+        for name in ("oracle_sigma_proj_n", "oracle_ndf_n"):
+            getattr(L, name).argtypes = [dp, C.c_double, C.c_double, dp]
             getattr(L, name).restype = C.c_double
         L.oracle_rho.argtypes = [C.c_double, C.c_double]
         L.oracle_rho.restype = C.c_double
@@ -150,6 +153,7 @@ class OracleScene:
         d.width, d.height, d.spp, d.max_depth = s.width, s.height, s.spp, s.max_depth
         d.seed = int(s.seed)
         d.scene_id = int(s.scene_id)
+        d.lengthscale_n = f32(s.lengthscale_n)
         self._desc = d
         h = C.c_void_p()
         rc = lib().oracle_scene_create(C.byref(d), C.byref(h))
@@ -296,6 +300,16 @@ def sigma_proj(G, s: float, d) -> float:
 
 def ndf(G, s: float, wm) -> float:
     return lib().oracle_ndf(_dp(_vec(G)), float(s), _dp(_vec(wm)))
+
+
+def sigma_proj_n(G, s: float, sn: float, d) -> float:
+    """Projected area with gradient std s across and sn along n = G/|G| (z if G = 0)."""
+    return lib().oracle_sigma_proj_n(_dp(_vec(G)), float(s), float(sn), _dp(_vec(d)))
+
+
+def ndf_n(G, s: float, sn: float, wm) -> float:
+    """Generalized NDF with gradient std s across and sn along n = G/|G| (z if G = 0)."""
+    return lib().oracle_ndf_n(_dp(_vec(G)), float(s), float(sn), _dp(_vec(wm)))
 
 
 def beckmann_ndf(alpha: float, cos_m: float) -> float:

@@ -92,12 +92,26 @@ int device_cus(int device, int* cus) {
     return GPSS_OK;
 }
 
-// Path counter and grid size of the persistent scheduled kernel: one 256-thread workgroup
-// per compute unit for each wave per SIMD that the kernel's register budget allows.
-int ensure_sched(gpss_scene* s) {
+// Path counter, device copy of the scene record and grid size of the persistent scheduled
+// kernel: one 256-thread workgroup per compute unit for each wave per SIMD that the kernel's
+// register budget allows.  The record (read through a pointer, which keeps the kernel's
+// scalar registers free) is re-uploaded after every change of `dev`, ordered after the
+// work already queued on `stream`.
+int ensure_sched(gpss_scene* s, hipStream_t stream) {
     if (!s->d_head) {
         int rc = check_hip(hipMalloc(&s->d_head, 64), "hipMalloc(path counter)");
         if (rc) return rc;
+    }
+    if (!s->d_dev) {
+        int rc = check_hip(hipMalloc(&s->d_dev, sizeof(SceneDev)), "hipMalloc(scene record)");
+        if (rc) return rc;
+    }
+    if (s->dev_uploaded != s->dev_version) {
+        int rc = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        if (!rc) rc = check_hip(hipMemcpy(s->d_dev, &s->dev, sizeof(SceneDev), hipMemcpyHostToDevice),
+                                "hipMemcpy(scene record)");
+        if (rc) return rc;
+        s->dev_uploaded = s->dev_version;
     }
     if (!s->sched_grid) {
         int cus = 0;
@@ -218,6 +232,7 @@ void free_scene(gpss_scene* s) {
     (void)hipFree(s->d_scratch);
     (void)hipFree(s->wf_mem);
     (void)hipFree(s->d_head);
+    (void)hipFree(s->d_dev);
     delete s;
 }
 
@@ -426,6 +441,7 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
     scene->dev.variance = variance;
     scene->dev.lengthscale = lengthscale;
     scene->dev.albedo = albedo;
+    scene->dev_version++;
     scene->maj_h_stale = true;
     return gpss::launch_majorants(scene, st);
 }

@@ -83,7 +83,9 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const 
         src.end = tl.p0 + tl.count;
         src.base = B.path_base;
         src.spp = B.spp;
-        run_scheduled<false>(B.S, src, paths, st);
+        const AdjointIo io{};
+        GradAcc acc{0.0f, 0.0f, 0.0f};
+        run_scheduled<false, false>(B.S, src, paths, st, io, acc);
     }
 }
 

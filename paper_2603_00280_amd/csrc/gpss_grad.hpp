@@ -1,0 +1,106 @@
+// Log-derivatives of the medium quantities with respect to the differentiable parameters
+// (mean offset grid, kernel variance, lengthscale, albedo) and their accumulation into the
+// gradient, shared by the path-replay adjoints (one thread per path and scheduled waves).
+#pragma once
+
+#include "gpss_device.hpp"
+
+namespace gpss {
+
+struct GradAcc {
+    float var, len, alb;   // d loss / d (variance, lengthscale, albedo), this thread's share
+};
+
+// d log rho = dmu * dmu_coef + dsigma * dsig_coef,  rho = phi(z)/(sigma Phi(z)), z = mu/sigma
+__device__ __forceinline__ void dlog_rho(float mu, float sigma, float& dmu, float& dsig) {
+    const float z = mu / sigma;
+    const float r = kSqrt2OverPi / erfcxf(-z * kInvSqrt2);   // phi(z) / Phi(z)
+    dmu = -(z + r) / sigma;
+    dsig = (z * z - 1.0f + z * r) / sigma;
+}
+
+// d log sigma_proj: sigma_proj = s phi(z) - m Phi(-z), m = d . G, z = m / s;
+// d/dm = -Phi(-z), d/ds = phi(z).  Written with the Mills ratio for z > 0.
+__device__ __forceinline__ void dlog_proj(float3 G, float s, float3 d, float3& dG, float& ds) {
+    const float m = dot(d, G);
+    const float z = m / s;
+    float a, b;
+    if (z <= 0.0f) {
+        const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
+        const float Phm = 1.0f - 0.5f * erfcf(-z * kInvSqrt2);
+        const float proj = s * ph - m * Phm;
+        a = Phm / proj;
+        b = ph / proj;
+    } else {
+        const float R = kSqrtHalfPi * erfcxf(z * kInvSqrt2);   // Phi(-z) / phi(z)
+        const float q = fmaxf(1.0f - z * R, 1e-30f);            // sigma_proj = s phi(z) q
+        a = R / (s * q);
+        b = 1.0f / (s * q);
+    }
+    dG = (-a) * d;
+    ds = b;
+}
+
+// d log D for g ~ N(G, s^2 I): with M_n = int_0^inf t^n exp(-(t - k)^2 / 2) dt, k = G.w / s,
+//   d log D / dG = (w s M4/M3 - G) / s^2,
+//   d log D / ds = (M5/M3 - 2 k M4/M3 + |G|^2/s^2 - 3) / s.
+// M_n by the recurrence M_n = k M_{n-1} + (n-1) M_{n-2}; scaled by exp(k^2/2) for k < 0.
+__device__ __forceinline__ bool dlog_ndf(float3 G, float s, float3 w, float3& dG, float& ds) {
+    const float is = 1.0f / s;
+    const float k = dot(G, w) * is;
+    float m0, m1;
+    if (k >= 0.0f) {
+        m0 = kSqrt2Pi * (1.0f - 0.5f * erfcf(k * kInvSqrt2));
+        m1 = expf(-0.5f * k * k) + k * m0;
+    } else {
+        m0 = kSqrtHalfPi * erfcxf(-k * kInvSqrt2);
+        m1 = 1.0f + k * m0;
+    }
+    const float m2 = k * m1 + m0;
+    const float m3 = k * m2 + 2.0f * m1;
+    const float m4 = k * m3 + 3.0f * m2;
+    const float m5 = k * m4 + 4.0f * m3;
+    if (!(m3 > 0.0f)) return false;
+    const float r4 = m4 / m3, r5 = m5 / m3;
+    dG = (is * is) * ((s * r4) * w - G);
+    ds = (r5 - 2.0f * k * r4 + dot(G, G) * is * is - 3.0f) * is;
+    return true;
+}
+
+// Add coefficients (of d mu, d grad mu, d sigma, d s at point x) to the parameter gradient.
+__device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const PointQ& q, float cmu, float3 cG,
+                                             float csig, float cs, float* __restrict__ grad_off, GradAcc& acc) {
+    if (S.offset && grad_off) {
+        const TriCell c = tri_cell(S.off_res, S.off_scale, S.lo, x);
+        const int sy = S.off_res[0], sz = S.off_res[0] * S.off_res[1];
+        const float fx = c.fx, fy = c.fy, fz = c.fz;
+        const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+        const float ax = cG.x * S.off_scale[0], ay = cG.y * S.off_scale[1], az = cG.z * S.off_scale[2];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            const int dx = n & 1, dy = (n >> 1) & 1, dz = n >> 2;
+            const float wx = dx ? fx : gx, wy = dy ? fy : gy, wz = dz ? fz : gz;
+            const float sxg = dx ? 1.0f : -1.0f, syg = dy ? 1.0f : -1.0f, szg = dz ? 1.0f : -1.0f;
+            const float v = cmu * (wx * wy * wz) + ax * (sxg * wy * wz) + ay * (syg * wx * wz) + az * (szg * wx * wy);
+            if (v != 0.0f) atomicAdd(&grad_off[c.base + dx + dy * sy + dz * sz], v);
+        }
+    }
+    if (!S.var_grid) {
+        // sigma = sqrt(variance), s = sigma / l
+        const float inv2sig = 0.5f / q.sigma;
+        acc.var += csig * inv2sig + cs * inv2sig / S.lengthscale;
+    }
+    acc.len -= cs * q.s / S.lengthscale;
+}
+
+// coefficient c on d log sigma_t(x, d) = d log rho + d log sigma_proj(d)
+__device__ __forceinline__ void add_dlog_sigma_t(const SceneDev& S, float3 x, const PointQ& q, float3 d, float c,
+                                                 float* grad_off, GradAcc& acc) {
+    float dmu, dsig, ds;
+    float3 dG;
+    dlog_rho(q.mu, q.sigma, dmu, dsig);
+    dlog_proj(q.G, q.s, d, dG, ds);
+    scatter_grad(S, x, q, c * dmu, c * dG, c * dsig, c * ds, grad_off, acc);
+}
+
+}  // namespace gpss

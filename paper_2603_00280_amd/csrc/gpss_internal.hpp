@@ -45,6 +45,9 @@ struct gpss_scene {
     uint64_t wf_cap = 0;               // paths the wavefront buffers hold
     uint32_t wf_grid = 0;              // persistent workgroups per wavefront launch
     uint32_t* d_head = nullptr;        // path counter of the persistent scheduled kernel
+    gpss::SceneDev* d_dev = nullptr;   // device copy of `dev` read by the persistent kernels
+    uint64_t dev_version = 1;          // bumped whenever `dev` changes
+    uint64_t dev_uploaded = 0;         // version held by d_dev
     uint32_t sched_grid = 0;           // workgroups of the persistent scheduled kernel
     uint64_t n_pixels() const { return (uint64_t)desc.width * desc.height; }
 };
@@ -63,7 +66,7 @@ int launch_reduce(gpss_scene* s, const float* paths, float* image, uint32_t ns, 
 int ensure_wavefront(gpss_scene* s, uint64_t npaths);
 int wf_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
 int mega_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
-int ensure_sched(gpss_scene* s);
+int ensure_sched(gpss_scene* s, hipStream_t stream);
 int sched_waves_per_simd();
 int sched_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
 int device_cus(int device, int* cus);

@@ -26,26 +26,11 @@ __global__ void sched_reset_kernel(uint32_t* head) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *head = 0u;
 }
 
-// Paths p in [0, npaths) of one launch: pixel p / ns, sample s0 + p % ns, slot p.
-struct LaunchSource {
-    ChunkReader rd;
-    uint32_t* head;
-    uint32_t s0, ns;
-    __device__ __forceinline__ bool exhausted() const { return rd.exhausted; }
-    __device__ __forceinline__ bool take(bool idle, uint32_t& slot, uint32_t& pixel, uint32_t& sample) {
-        uint32_t qi = 0;
-        if (!rd.take(idle, head, qi)) return false;
-        slot = qi;
-        pixel = qi / ns;
-        sample = s0 + qi % ns;
-        return true;
-    }
-};
-
 template <bool STATS>
 __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_render_kernel(
-    SceneDev S, float* __restrict__ paths, uint32_t* head, unsigned long long* counters, uint32_t s0,
-    uint32_t ns, uint32_t npaths) {
+    const SceneDev* __restrict__ Sp, float* __restrict__ paths, uint32_t* head, unsigned long long* counters,
+    uint32_t s0, uint32_t ns, uint32_t npaths) {
+    const SceneDev& S = *Sp;
     PathStats st;
     st.clear();
     LaunchSource src;
@@ -53,7 +38,9 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_render_kernel
     src.head = head;
     src.s0 = s0;
     src.ns = ns;
-    run_scheduled<STATS>(S, src, paths, st);
+    const AdjointIo io{};
+    GradAcc acc{0.0f, 0.0f, 0.0f};
+    run_scheduled<STATS, false>(S, src, paths, st, io, acc);
     flush_stats_sched<STATS>(st, counters);
 }
 
@@ -62,16 +49,16 @@ int sched_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, u
                  hipStream_t stream) {
     const uint64_t npaths = s->n_pixels() * ns;
     if (npaths > 0x7FFFFFFFull) return set_error(GPSS_ERR_INVALID_ARG, "persistent launch limited to 2^31 paths");
-    int rc = ensure_sched(s);
+    int rc = ensure_sched(s, stream);
     if (rc) return rc;
     hipLaunchKernelGGL(sched_reset_kernel, dim3(1), dim3(64), 0, stream, s->d_head);
     const dim3 blk(256);
     const dim3 grid(s->sched_grid);
     if (counters)
-        hipLaunchKernelGGL(sched_render_kernel<true>, grid, blk, 0, stream, s->dev, paths, s->d_head,
+        hipLaunchKernelGGL(sched_render_kernel<true>, grid, blk, 0, stream, s->d_dev, paths, s->d_head,
                            reinterpret_cast<unsigned long long*>(counters), s0, ns, (uint32_t)npaths);
     else
-        hipLaunchKernelGGL(sched_render_kernel<false>, grid, blk, 0, stream, s->dev, paths, s->d_head, nullptr,
+        hipLaunchKernelGGL(sched_render_kernel<false>, grid, blk, 0, stream, s->d_dev, paths, s->d_head, nullptr,
                            s0, ns, (uint32_t)npaths);
     return check_hip(hipGetLastError(), "sched_render_kernel launch");
 }

@@ -20,6 +20,7 @@
 // path radiances are bit-identical to it.
 #pragma once
 
+#include "gpss_grad.hpp"
 #include "gpss_trace.hpp"
 #include "gpss_waves.hpp"
 
@@ -48,36 +49,67 @@ enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBe
 #define GPSS_SCHED_MIN_WAVES 3
 #endif
 
-// Trace every path of `src` (a wave-collective path source: take(idle, slot, pixel, sample)
-// hands idle lanes new paths, exhausted() is wave-uniform) and write each path's radiance to
-// paths[slot].  Must be called by whole waves; returns when the source is exhausted and
-// every lane's path has ended.
 // Threads per workgroup of the kernels that run the scheduled loop (per-lane LDS columns).
 constexpr int kSchedBlock = 256;
 
-template <bool STATS, class Source>
+// Paths p in [0, npaths) of one launch: pixel p / ns, sample s0 + p % ns, slot p.
+struct LaunchSource {
+    ChunkReader rd;
+    uint32_t* head;
+    uint32_t s0, ns;
+    __device__ __forceinline__ bool exhausted() const { return rd.exhausted; }
+    __device__ __forceinline__ bool take(bool idle, uint32_t& slot, uint32_t& pixel, uint32_t& sample) {
+        uint32_t qi = 0;
+        if (!rd.take(idle, head, qi)) return false;
+        slot = qi;
+        pixel = qi / ns;
+        sample = s0 + qi % ns;
+        return true;
+    }
+};
+
+// Inputs and outputs of the path-replay adjoint form of the loop.
+struct AdjointIo {
+    const float* dloss;        // d loss / d pixel
+    const float* radiance;     // each path's radiance (forward pass), by output slot
+    float* grad_off;           // offset-grid gradient (nullable), accumulated atomically
+    float inv_ns;              // 1 / samples per pixel of the launch
+};
+
+// Trace every path of `src` (a wave-collective path source: take(idle, slot, pixel, sample)
+// hands idle lanes new paths, exhausted() is wave-uniform).  Forward form (ADJ false): write
+// each path's radiance to paths[slot].  Adjoint form: replay each path with weight
+// dloss[pixel] / ns against its forward radiance and accumulate the parameter gradient
+// (frozen-sampling estimator; the terms are those of the one-thread replay in
+// gpss_adjoint.hip) into io.grad_off and acc.  Must be called by whole waves; returns when
+// the source is exhausted and every lane's path has ended.
+template <bool STATS, bool ADJ, class Source>
 __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, float* __restrict__ paths,
-                                              PathStats& st) {
+                                              PathStats& st, const AdjointIo& io, GradAcc& acc) {
     // Cold per-lane state (touched once per segment or vertex) lives in LDS, one column per
     // lane, so that registers hold what the cell walk and the medium evaluation use.
+    constexpr int kNf = ADJ ? 15 : 6;
     __shared__ uint32_t cs_u[3][kSchedBlock];   // output slot, pixel, sample
-    __shared__ float cs_f[6][kSchedBlock];      // beta, L, beta*phase and Le per light
+    __shared__ float cs_f[kNf][kSchedBlock];    // beta, L, beta*phase and Le per light (+ adjoint terms)
     __shared__ double cs_d[3][kSchedBlock];     // direction of the next track segment
     const int lt = threadIdx.x;
     enum { kSlot = 0, kPixel = 1, kSample = 2 };
-    enum { kBeta = 0, kL = 1, kBp0 = 2, kBp1 = 3, kLe0 = 4, kLe1 = 5 };
-    enum { kHas0 = 1, kHas1 = 2, kDead = 4 };
+    // forward: kL = radiance so far; adjoint: kL = remaining radiance L_rem of the replay
+    enum { kBeta = 0, kL = 1, kBp0 = 2, kBp1 = 3, kLe0 = 4, kLe1 = 5,
+           kWpix = 6, kEtot = 7, kE = 8, kWm = 9, kDin = 12 };   // kWm, kDin: 3 columns each
+    enum { kHas0 = 1, kHas1 = 2, kDead = 4, kGradPass = 8, kVertex = 16 };
 
     int op = kOpIdle;
     int b = 0;                 // real collisions so far
     int mode = 0;              // current segment: 0 track, 1 + li shadow ray toward light li
-    int flags = 0;             // kHas0 | kHas1 (lights connected at this vertex) | kDead
+    int flags = 0;             // kHas0 | kHas1 (lights connected at this vertex) | kDead | ...
     float Tr = 1.0f;
+    float coef = 0.0f;         // adjoint: weight of the shadow ray being replayed for its gradient
     Segment sg;
     sg.o = d3(0.0, 0.0, 0.0);
     Rng rng;
     auto finish = [&](float L) {   // the path's radiance to its output slot; the lane falls idle
-        paths[cs_u[kSlot][lt]] = L;
+        if (!ADJ) paths[cs_u[kSlot][lt]] = L;
         op = kOpIdle;
     };
 
@@ -94,7 +126,13 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
         // ---- refill idle lanes with new paths (camera rays) ----
         if (nIdle > 0 && !src.exhausted() && (nIdle >= GPSS_SCHED_REFILL_MIN || nBusy == 0)) {
             uint32_t slot = 0, pixel = 0, sample = 0;
-            if (src.take(op == kOpIdle, slot, pixel, sample)) {
+            bool got = src.take(op == kOpIdle, slot, pixel, sample);
+            float wpix = 0.0f;
+            if (ADJ && got) {
+                wpix = io.dloss[pixel] * io.inv_ns;
+                got = wpix != 0.0f;   // paths of pixels without loss gradient are skipped
+            }
+            if (got) {
                 Rng rc;
                 rc.init(S.key0, S.key1, pixel, sample, 0u, kStreamCam);
                 const float ux = rc.uniform(), uy = rc.uniform();
@@ -107,7 +145,12 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 cs_d[1][lt] = d.y;
                 cs_d[2][lt] = d.z;
                 cs_f[kBeta][lt] = 1.0f;
-                cs_f[kL][lt] = 0.0f;
+                if (ADJ) {
+                    cs_f[kL][lt] = io.radiance[slot];
+                    cs_f[kWpix][lt] = wpix;
+                } else {
+                    cs_f[kL][lt] = 0.0f;
+                }
                 sg.o = o;
                 b = 0;
                 mode = 0;
@@ -125,8 +168,9 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 const D3 x = sg.o + sg.t * sg.d;
                 const D3 d = sg.d;
                 const float3 df = to_f3(d);
-                const PointQ q = eval_point(S, to_f3(x));
-                float beta = cs_f[kBeta][lt];
+                const float3 xf = to_f3(x);
+                const PointQ q = eval_point(S, xf);
+                const float beta = cs_f[kBeta][lt];
                 flags = 0;
 #pragma unroll
                 for (int li = 0; li < 2; ++li) {
@@ -140,6 +184,18 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     cs_f[kBp0 + li][lt] = mul_rn(beta, ph);
                     cs_f[kLe0 + li][lt] = Le;
                 }
+                if (ADJ) {
+                    // density and albedo: every contribution from this vertex on (L_rem)
+                    float dmu, dsig;
+                    dlog_rho(q.mu, q.sigma, dmu, dsig);
+                    const float c = cs_f[kWpix][lt] * cs_f[kL][lt];
+                    scatter_grad(S, xf, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, io.grad_off, acc);
+                    if (!S.albedo_per_prim && S.albedo > 0.0f) acc.alb += c / S.albedo;
+                    cs_f[kEtot][lt] = 0.0f;
+                    cs_f[kDin + 0][lt] = df.x;
+                    cs_f[kDin + 1][lt] = df.y;
+                    cs_f[kDin + 2][lt] = df.z;
+                }
                 rng.init(S.key0, S.key1, cs_u[kPixel][lt], cs_u[kSample][lt], (uint32_t)b, kStreamPhase);
                 D3 wi;
                 float wgt, pdf;
@@ -150,6 +206,12 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     cs_d[0][lt] = wi.x;
                     cs_d[1][lt] = wi.y;
                     cs_d[2][lt] = wi.z;
+                    if (ADJ) {
+                        cs_f[kWm + 0][lt] = wm.x;
+                        cs_f[kWm + 1][lt] = wm.y;
+                        cs_f[kWm + 2][lt] = wm.z;
+                        flags |= kVertex;   // phase-sample gradient once the connections are done
+                    }
                 } else {
                     flags |= kDead;   // the path ends after this vertex's light connections
                 }
@@ -166,6 +228,22 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
             if (op == kOpBegin) {
                 const uint32_t pixel = cs_u[kPixel][lt], sample = cs_u[kSample][lt];
                 if (mode == 0) {
+                    if (ADJ && (flags & kVertex)) {
+                        // phase sample of the vertex just left: contributions after its lights
+                        flags &= ~kVertex;
+                        const float Lafter = cs_f[kL][lt] - cs_f[kEtot][lt];
+                        if (Lafter != 0.0f) {
+                            const PointQ q = eval_point(S, to_f3(sg.o));
+                            const float3 wm = f3(cs_f[kWm][lt], cs_f[kWm + 1][lt], cs_f[kWm + 2][lt]);
+                            float3 dG;
+                            float ds;
+                            if (dlog_ndf(q.G, q.s, wm, dG, ds)) {
+                                const float c = cs_f[kWpix][lt] * Lafter;
+                                scatter_grad(S, to_f3(sg.o), q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc);
+                            }
+                        }
+                        cs_f[kL][lt] = Lafter;
+                    }
                     const D3 o = sg.o, d = d3(cs_d[0][lt], cs_d[1][lt], cs_d[2][lt]);
                     double t0, t1;
                     D3 inv;
@@ -213,8 +291,10 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 const bool capped = ++sg.steps > kStepCap;
                 float u2 = 0.0f;
                 if (!capped && mode == 0) u2 = rng.uniform();
-                const PointQ q = eval_point(S, sg.pos());
-                const float sig = sigma_t_of(q, to_f3(sg.d));   // single-precision travel direction
+                const float3 xf = sg.pos();
+                const float3 df = to_f3(sg.d);   // single-precision travel direction
+                const PointQ q = eval_point(S, xf);
+                const float sig = sigma_t_of(q, df);
                 if (capped) {
                     if (STATS) st.capped++;
                     if (mode == 0) {
@@ -235,10 +315,18 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                                 op = kOpScatter;
                             }
                         } else {
+                            if (ADJ) {   // null collision: every remaining contribution
+                                const float Lrem = cs_f[kL][lt];
+                                if (Lrem != 0.0f)
+                                    add_dlog_sigma_t(S, xf, q, df, -cs_f[kWpix][lt] * Lrem * sig / (sg.maj - sig),
+                                                     io.grad_off, acc);
+                            }
                             sg.redraw(rng);
                             op = kOpWalk;
                         }
                     } else {
+                        if (ADJ && (flags & kGradPass))   // shadow-ray factor of this connection
+                            add_dlog_sigma_t(S, xf, q, df, -coef * sig / (sg.maj - sig), io.grad_off, acc);
                         Tr *= 1.0f - sig / sg.maj;
                         if (!roulette(Tr, rng)) {
                             Tr = 0.0f;
@@ -271,11 +359,44 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
             // shadow ray finished: add its contribution, then the next light or the next
             // track segment (or the end of a path whose phase sample was degenerate)
             const int li = mode - 1;
-            const float L = add_rn(cs_f[kL][lt], nee_contribution(cs_f[kBp0 + li][lt], Tr, cs_f[kLe0 + li][lt]));
-            cs_f[kL][lt] = L;
-            mode = (li == 0 && (flags & kHas1)) ? 2 : 0;
-            if (mode == 0 && (flags & kDead)) finish(L);
-            else op = kOpBegin;
+            bool next = true;
+            if (!ADJ) {
+                const float L = add_rn(cs_f[kL][lt], nee_contribution(cs_f[kBp0 + li][lt], Tr, cs_f[kLe0 + li][lt]));
+                cs_f[kL][lt] = L;
+            } else if (!(flags & kGradPass)) {
+                // primal pass of the connection: its contribution E; a second pass over the same
+                // random stream differentiates it when E != 0
+                const float E = nee_contribution(cs_f[kBp0 + li][lt], Tr, cs_f[kLe0 + li][lt]);
+                cs_f[kEtot][lt] = add_rn(cs_f[kEtot][lt], E);
+                if (E != 0.0f) {
+                    cs_f[kE][lt] = E;
+                    coef = cs_f[kWpix][lt] * E;
+                    flags |= kGradPass;
+                    next = false;
+                    op = kOpBegin;
+                }
+            } else {
+                // gradient pass done: the NDF at the connection's half vector
+                flags &= ~kGradPass;
+                const float3 din = f3(cs_f[kDin][lt], cs_f[kDin + 1][lt], cs_f[kDin + 2][lt]);
+                const float3 h = to_f3(sg.d) - din;
+                const float hn = sqrtf(dot(h, h));
+                float3 dG;
+                float ds;
+                if (hn >= 1e-7f) {
+                    const float3 xf = to_f3(sg.o);
+                    const PointQ q = eval_point(S, xf);
+                    if (dlog_ndf(q.G, q.s, (1.0f / hn) * h, dG, ds)) {
+                        const float c = cs_f[kWpix][lt] * cs_f[kE][lt];
+                        scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc);
+                    }
+                }
+            }
+            if (next) {
+                mode = (li == 0 && (flags & kHas1)) ? 2 : 0;
+                if (mode == 0 && (flags & kDead)) finish(cs_f[kL][lt]);
+                else op = kOpBegin;
+            }
         }
     }
 }

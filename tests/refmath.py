@@ -86,3 +86,37 @@ def planar_transmittance(z0, z1, dz, sigma, proj):
     """Closed form of exp(-int sigma_t) along a ray crossing heights z0 -> z1 through the planar
     medium with density rho(z) = d/dz ln Phi(z/sigma): (Phi(z0/s)/Phi(z1/s))^(proj/dz)."""
     return math.exp(proj / dz * (special.log_ndtr(z0 / sigma) - special.log_ndtr(z1 / sigma)))
+
+
+def aniso_cov(G, s, sn):
+    """Sigma = s^2 (I - n n^T) + sn^2 n n^T about n = G/|G| (z when G = 0), as a 3x3 matrix."""
+    G = np.asarray(G, float)
+    g = np.linalg.norm(G)
+    n = G / g if g > 0 else np.array([0.0, 0.0, 1.0])
+    return s * s * (np.eye(3) - np.outer(n, n)) + sn * sn * np.outer(n, n)
+
+
+def ndf_by_gdf_full(wm, mean, cov):
+    """Eq. gdf_to_ndf for g ~ N(mean, cov) with a full covariance matrix (1D quadrature)."""
+    wm = np.asarray(wm, float)
+    mean = np.asarray(mean, float)
+    inv = np.linalg.inv(cov)
+    norm = 1.0 / math.sqrt((2 * np.pi) ** 3 * np.linalg.det(cov))
+
+    def f(t):
+        r = t * wm - mean
+        return norm * math.exp(-0.5 * float(r @ inv @ r)) * t ** 3
+
+    val, _ = integrate.quad(f, 0.0, np.inf, epsabs=0.0, epsrel=1e-12, limit=400)
+    return val
+
+
+def projected_area_full(d, mean, cov):
+    """E[max(0, -d.g)] for g ~ N(mean, cov): -d.g ~ N(-d.mean, d^T cov d)."""
+    d = np.asarray(d, float)
+    m = -float(np.dot(d, mean))
+    sd = math.sqrt(float(d @ cov @ d))
+    f = lambda x: x * stats.norm.pdf(x, m, sd)
+    hi = max(m, 0.0) + 40 * sd
+    val, _ = integrate.quad(f, 0.0, hi, epsabs=0.0, epsrel=1e-12, limit=400, points=[max(m, 0.0)])
+    return val

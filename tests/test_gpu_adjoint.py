@@ -29,17 +29,21 @@ def _dloss(theta0, target):
     return 2.0 * (I - T) / I.size
 
 
+@pytest.mark.parametrize("kernel", ["persistent", "mega"])
 @pytest.mark.parametrize("perturbed", [False, True])
-def test_adjoint_matches_oracle_dual_gradient(G, perturbed):
+def test_adjoint_matches_oracle_dual_gradient(G, perturbed, kernel):
+    """The scheduled replay (default) and the one-thread-per-path replay against the
+    oracle's forward-mode gradient of the same frozen-sampling estimator."""
     s0 = _small(False)
     if perturbed:   # theta0 with non-zero offsets, so that every gradient term is exercised
         s0.offset_grid = np.random.default_rng(9).normal(0, 0.01, s0.offset_grid.shape).astype(np.float32)
     tgt = _small(True)
     dl = _dloss(s0, tgt)
     ids = [-1, -2, -3] + [int(i) for i in sc.grad_param_indices(s0)]
-    print(f"[adjoint] perturbed={perturbed} {s0.width}x{s0.height} spp {s0.spp} params {len(ids)}", flush=True)
+    print(f"[adjoint] {kernel} perturbed={perturbed} {s0.width}x{s0.height} spp {s0.spp} params {len(ids)}",
+          flush=True)
     g_orc, _ = orc.OracleScene(s0).render_grad(dl, ids)
-    g = G.GpssScene(s0)
+    g = G.GpssScene(s0, kernel=kernel)
     g_off, g_sc = g.render_adjoint(torch.as_tensor(dl, dtype=torch.float32))
     torch.cuda.synchronize()
     g_off = g_off.cpu().numpy().ravel()

@@ -448,3 +448,65 @@ def test_pixel_list_render_equals_full_render():
     r = o.render_pixels(px)
     assert np.array_equal(r["mean"], full["mean"].ravel()[px])
     assert np.allclose(r["var"], full["var"].ravel()[px], rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Anisotropic kernel: lengthscale l across and l_n along the local mean-gradient direction
+# (Eq. se_kernel in the frame of the geometric normal; Eqs. generalized_lambda and
+# macro_ndf with alpha_x = alpha_y != alpha_z)
+# ---------------------------------------------------------------------------
+def _aniso_cases(rng, n):
+    for k in range(n):
+        G = np.zeros(3) if k % 5 == 0 else _rand_dir(rng) * rng.choice([1.0, 0.5, 1.6])
+        s = float(rng.choice([0.05, 0.3, 1.0]))
+        sn = float(rng.choice([0.01, 0.2, 0.7, 2.5]))
+        yield G, s, sn, _rand_dir(rng)
+
+
+def test_anisotropic_projected_area_is_negative_part_mean():
+    rng = np.random.default_rng(31)
+    for G, s, sn, d in _aniso_cases(rng, 40):
+        want = ref.projected_area_full(d, G, ref.aniso_cov(G, s, sn))
+        assert orc.sigma_proj_n(G, s, sn, d) == pytest.approx(want, rel=1e-8, abs=1e-300)
+
+
+def test_anisotropic_ndf_equals_gdf_integral():
+    rng = np.random.default_rng(32)
+    for G, s, sn, wm in _aniso_cases(rng, 40):
+        want = ref.ndf_by_gdf_full(wm, G, ref.aniso_cov(G, s, sn))
+        assert orc.ndf_n(G, s, sn, wm) == pytest.approx(want, rel=1e-7, abs=1e-300)
+
+
+def test_anisotropic_identities_on_the_sphere():
+    """Signed projected area (Eq. spa) and vNDF normalizer = projected area
+    (Fig. generalized_projected_area) for alpha_z != alpha_x = alpha_y."""
+    rng = np.random.default_rng(33)
+    for G, s, sn in [(np.array([0.0, 0.0, 1.0]), 0.4, 0.05), (np.array([0.3, -0.5, 0.8]), 0.2, 0.9),
+                     (np.zeros(3), 0.5, 0.2)]:
+        dirs, W = ref.sphere_grid(G if np.linalg.norm(G) > 0 else [0, 0, 1.0], 400, 256)
+        D = np.array([orc.ndf_n(G, s, sn, w) for w in dirs])
+        for _ in range(3):
+            w = _rand_dir(rng)
+            signed = float(np.sum(W * (dirs @ w) * D))
+            assert signed == pytest.approx(float(np.dot(w, G)), abs=2e-6 * max(1.0, np.linalg.norm(G)))
+            # visible part: a hemisphere grid about -w, aligned with the kink of max(0, .)
+            hd, hw = ref.sphere_grid(-w, 600, 400, hemisphere=True)
+            vis = float(np.sum(hw * (hd @ (-w)) * np.array([orc.ndf_n(G, s, sn, m) for m in hd])))
+            assert vis == pytest.approx(orc.sigma_proj_n(G, s, sn, w), rel=2e-5)
+
+
+def test_anisotropic_reduces_to_isotropic_and_height_field():
+    rng = np.random.default_rng(34)
+    for _ in range(10):
+        G = _rand_dir(rng) * 0.8
+        s = 0.3
+        w = _rand_dir(rng)
+        assert orc.sigma_proj_n(G, s, s, w) == pytest.approx(orc.sigma_proj(G, s, w), rel=1e-13)
+        assert orc.ndf_n(G, s, s, w) == pytest.approx(orc.ndf(G, s, w), rel=1e-13)
+    # s_n -> 0 about n = z with |G| = 1: the Beckmann NDF of roughness sqrt(2) s (height field)
+    s = 0.25
+    for c in (0.95, 0.8, 0.5):
+        wm = np.array([math.sqrt(1 - c * c), 0.0, c])
+        e1 = abs(orc.ndf_n([0, 0, 1.0], s, 1e-3, wm) / ref.beckmann_D(math.sqrt(2) * s, c) - 1)
+        e2 = abs(orc.ndf_n([0, 0, 1.0], s, 5e-4, wm) / ref.beckmann_D(math.sqrt(2) * s, c) - 1)
+        assert e1 < 2e-3 and e2 < 0.3 * e1 + 1e-9
