@@ -33,6 +33,9 @@ MEAN_CONST = 2      # mu(x) = mean_const (+ offset): a homogeneous medium
 CAM_ORTHO = 0
 CAM_PINHOLE = 1
 
+NDF_GENERALIZED = 0   # Sec. 4.2: the GP macrofacet (Eqs. generalized_lambda, macro_ndf)
+NDF_GGX = 1           # end of Sec. 4.1: GGX height-field macrofacet
+
 
 @dataclasses.dataclass
 class Scene:
@@ -67,6 +70,7 @@ class Scene:
     seed: int = 0
     scene_id: int = 0
     lengthscale_n: float = 0.0             # lengthscale along the local mean-gradient direction (0: isotropic)
+    ndf_kind: int = 0                      # NDF_GENERALIZED (Eq. macro_ndf) or NDF_GGX (height field)
 
     @property
     def n_pixels(self) -> int:
@@ -143,6 +147,22 @@ def sphere_scene(lengthscale: float = 0.1, width: int = 512, height: int = 512,
         width=width, height=height, spp=spp, max_depth=max_depth, seed=seed,
         scene_id=scene_id,
     )
+
+
+# ---------------------------------------------------------------------------
+# Anisotropic kernel (Fig. cmp_aniso): the sphere workload with roughness alpha = 0.8 across
+# the local normal and alpha_z along it; alpha = sqrt(2) sigma / l (Eq. roughness).
+# ---------------------------------------------------------------------------
+ANISO_ALPHA_T = 0.8
+ANISO_ALPHAS_Z = (0.01, 0.8)
+
+
+def aniso_sphere_scene(alpha_z: float = 0.01, alpha_t: float = ANISO_ALPHA_T, **kw) -> Scene:
+    variance = kw.pop("variance", 0.0025)
+    sigma = float(np.sqrt(np.float32(variance)))
+    s = sphere_scene(lengthscale=float(np.sqrt(2.0) * sigma / alpha_t), variance=variance, **kw)
+    return s.replace(name=f"aniso_sphere_az{alpha_z:g}",
+                     lengthscale_n=float(np.sqrt(2.0) * sigma / alpha_z))
 
 
 # ---------------------------------------------------------------------------

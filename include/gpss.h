@@ -63,7 +63,7 @@ typedef struct {
     float variance;                /* sigma^2 > 0, used when variance_grid is NULL */
     const float* variance_grid;    /* nullable: trilinear grid of sigma^2 (locally stationary) */
     uint32_t var_res[3];
-    float lengthscale;             /* l > 0; gradient std is sigma / l (Eq. roughness) */
+    float lengthscale;             /* l > 0; gradient std is sigma / l (Eq. roughness); see lengthscale_n */
     /* medium */
     float albedo;                  /* F of the conductor phase function, in [0, 1] */
     int32_t albedo_per_prim;       /* nonzero: albedo of the primitive with the smallest SDF */
@@ -85,6 +85,11 @@ typedef struct {
     uint32_t max_depth;            /* maximum number of real scattering events per path */
     uint64_t seed;
     uint32_t scene_id;
+    /* kernel anisotropy (Eq. se_kernel in the frame of the local geometric normal, i.e. the
+     * mean-gradient direction, z where grad mu = 0): lengthscale along that direction;
+     * `lengthscale` applies across it.  0 = isotropic (l_n = l).  Sec. 4.2.1: alpha_z =
+     * sqrt(2) sigma / l_n in Eqs. generalized_lambda and macro_ndf. */
+    float lengthscale_n;
 } gpss_scene_desc;
 
 /* Create a scene: validates `desc`, uploads primitives and grids, and builds the

@@ -41,6 +41,7 @@ struct oracle_scene {
     double variance, l, albedo;
     double l_n;            // lengthscale along the local mean-gradient direction (= l: isotropic)
     bool aniso;            // l_n != l
+    bool ggx;              // GGX height-field macrofacet (NDF and Lambda of GGX) instead of Eq. macro_ndf
     bool albedo_per_prim;
     double lo[3], hi[3], ext[3];
     double R;
@@ -187,6 +188,7 @@ struct PointQ {
     T s;       // gradient standard deviation across n: sigma / l
     T sn;      // gradient standard deviation along n: sigma / l_n
     T albedo;
+    bool ggx = false;   // GGX height-field macrofacet
 };
 
 template <class T>
@@ -236,6 +238,7 @@ PointQ<T> eval_point(const Params<T>& P, const double x[3]) {
     q.sigma = t_sqrt(variance);
     q.s = q.sigma / mk<T>(S.l, P.slot_l);
     q.sn = S.aniso ? q.sigma / T(S.l_n) : q.s;
+    q.ggx = S.ggx;
     if (S.albedo_per_prim && which >= 0) q.albedo = T(S.prims[which].albedo);
     else q.albedo = mk<T>(S.albedo, P.slot_alb);
     return q;
@@ -286,9 +289,34 @@ T ndf_general(const T& ax, const T& ay, const T& az, const T& c, const T& tx2, c
 // normal n = G/|G| with roughnesses alpha_x = alpha_y = sqrt(2) s / |G| and
 // alpha_z = sqrt(2) s_n / |G| (Eq. roughness), scaled by |G|, the length of the mean
 // gradient.  Where grad mu = 0: E[max(0, -d.g)] = s_d / sqrt(2 pi), s_d^2 = d^T Sigma d.
+// GGX height-field macrofacet (end of Sec. 4.1: any NDF may replace Beckmann under the
+// Smith assumption).  About n = G/|G| with roughness alpha = sqrt(2) s / |G| (Eq. roughness)
+// and scaled by |G| as the generalized forms are:
+//   D(wm) = alpha^2 / (pi ((n.wm)^2 (alpha^2 - 1) + 1)^2) for n.wm > 0 (0 below),
+//   sigma(d) = Lambda(w) cos(theta) over the microsurface, w = -d, cos = w.n of either sign:
+//     cos (1 + Lambda(w)) entering from above, |cos| Lambda(-w) from below,
+//     Lambda = (-1 + sqrt(1 + alpha^2 tan^2)) / 2,
+//   which is (cos + sqrt(cos^2 + alpha^2 (1 - cos^2))) / 2 for both signs.
+template <class T>
+T ggx_lambda_cos(const T& alpha, const T& c) {
+    return 0.5 * (c + t_sqrt(c * c + alpha * alpha * (1.0 - c * c)));
+}
+template <class T>
+T ggx_D(const T& alpha, const T& c) {
+    if (val(c) <= 0.0) return T(0.0);
+    const T den = c * c * (alpha * alpha - 1.0) + 1.0;
+    return alpha * alpha / (kPi * den * den);
+}
+
 template <class T>
 T sigma_proj(const PointQ<T>& q, const double d[3]) {
     const T g2 = q.G[0] * q.G[0] + q.G[1] * q.G[1] + q.G[2] * q.G[2];
+    if (q.ggx) {
+        if (val(g2) == 0.0) return T(0.0);
+        const T gn = t_sqrt(g2);
+        const T c = -(q.G[0] * d[0] + q.G[1] * d[1] + q.G[2] * d[2]) / gn;
+        return gn * ggx_lambda_cos(kSqrt2 * q.s / gn, c);
+    }
     if (val(g2) == 0.0) {
         const T sd = t_sqrt(q.s * q.s * (1.0 - d[2] * d[2]) + q.sn * q.sn * (d[2] * d[2]));
         return sd / kSqrt2Pi;
@@ -306,6 +334,12 @@ T sigma_proj(const PointQ<T>& q, const double d[3]) {
 template <class T>
 T ndf(const PointQ<T>& q, const double wm[3]) {
     const T g2 = q.G[0] * q.G[0] + q.G[1] * q.G[1] + q.G[2] * q.G[2];
+    if (q.ggx) {
+        if (val(g2) == 0.0) return T(0.0);
+        const T gn = t_sqrt(g2);
+        const T c = (q.G[0] * wm[0] + q.G[1] * wm[1] + q.G[2] * wm[2]) / gn;
+        return gn * ggx_D(kSqrt2 * q.s / gn, c);
+    }
     if (val(g2) == 0.0) {
         const double c2 = wm[2] * wm[2];
         const T A = (1.0 - c2) / (q.s * q.s) + c2 / (q.sn * q.sn);
@@ -335,7 +369,8 @@ double beckmann_lambda(double a) {
 // v = -d.  The Beckmann part is used only while v is above the local horizon.
 // ---------------------------------------------------------------------------
 struct Proposal {
-    bool beck;          // Beckmann component available
+    bool beck;          // visible-normal component available (Beckmann, or GGX for a GGX macrofacet)
+    bool ggx;
     double Reff;
     double N[3], T[3], B[3];
     double alpha, cosv, a;  // a = cot(theta_v) in the stretched configuration
@@ -345,6 +380,7 @@ Proposal make_proposal(const PointQ<double>& q, double R, const double v[3]) {
     Proposal p;
     const double gn = std::sqrt(dot3(q.G, q.G));
     p.beck = false;
+    p.ggx = q.ggx;
     p.Reff = 0.0;
     if (gn > 0.0) {
         p.N[0] = q.G[0] / gn; p.N[1] = q.G[1] / gn; p.N[2] = q.G[2] / gn;
@@ -373,6 +409,10 @@ double beckmann_vndf_pdf(const Proposal& p, const double v[3], const double wm[3
     if (!p.beck) return 0.0;
     const double cm = dot3(wm, p.N);
     if (cm <= 0.0) return 0.0;
+    if (p.ggx) {   // GGX visible normals: <v, wm> D(wm) / (cos_v (1 + Lambda(v)))
+        const double vm = std::max(0.0, dot3(v, wm));
+        return vm * ggx_D(p.alpha, cm) / ggx_lambda_cos(p.alpha, p.cosv);
+    }
     double cr[3];
     cross3(wm, p.N, cr);
     const double D = beckmann_D(p.alpha, cm, dot3(cr, cr));
@@ -417,7 +457,34 @@ double sample_slope_x(double a, double u) {
 void sample_half_vector(const Proposal& p, const double v[3], double u_sel, uint32_t ua24,
                         uint32_t ub24, double wm[3]) {
     const double ua = ua24 * 0x1p-24, ub = ub24 * 0x1p-24;
-    if (u_sel < p.Reff) {
+    if (u_sel < p.Reff && p.ggx) {
+        // GGX visible normals (Heitz 2018): stretch v to the alpha = 1 configuration, sample
+        // the projected hemisphere as a disk whose far half is foreshortened by the view,
+        // lift the point to the hemisphere and unstretch.  Local frame (T, B, N).
+        const double vx = dot3(v, p.T), vy = dot3(v, p.B), vz = p.cosv;
+        double h[3] = {p.alpha * vx, p.alpha * vy, vz};
+        const double hn = std::sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+        for (double& c : h) c /= hn;
+        const double l2 = h[0] * h[0] + h[1] * h[1];
+        double t1[3] = {1.0, 0.0, 0.0};
+        if (l2 > 0.0) {
+            const double il = 1.0 / std::sqrt(l2);
+            t1[0] = -h[1] * il; t1[1] = h[0] * il; t1[2] = 0.0;
+        }
+        double t2[3];
+        cross3(h, t1, t2);
+        const double r = std::sqrt(ua), phi = 2.0 * kPi * ub;
+        const double a1 = r * std::cos(phi);
+        double a2 = r * std::sin(phi);
+        const double sh = 0.5 * (1.0 + h[2]);
+        a2 = (1.0 - sh) * std::sqrt(std::max(0.0, 1.0 - a1 * a1)) + sh * a2;
+        const double a3 = std::sqrt(std::max(0.0, 1.0 - a1 * a1 - a2 * a2));
+        double m[3];
+        for (int k = 0; k < 3; ++k) m[k] = a1 * t1[k] + a2 * t2[k] + a3 * h[k];
+        double e[3] = {p.alpha * m[0], p.alpha * m[1], std::max(0.0, m[2])};
+        const double en = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        for (int k = 0; k < 3; ++k) wm[k] = (e[0] * p.T[k] + e[1] * p.B[k] + e[2] * p.N[k]) / en;
+    } else if (u_sel < p.Reff) {
         const double xs = sample_slope_x(p.a, ua);
         const double ys = erfinv_d((2.0 * ub24 + 1.0) * 0x1p-24 - 1.0);
         const double x = p.alpha * xs, y = p.alpha * ys;
@@ -529,7 +596,9 @@ void build_majorants(Scene& S) {
                 const double s_max = smax_f / std::min(S.l, S.l_n);
                 const double rho_max = r_ratio(mu_min / (mu_min > 0.0 ? smax_f : smin_f)) / smin_f;
                 const double z = gmax / s_max;
-                const double proj_max = gmax * Phi_d(z) + s_max * phi_d(z);
+                // GGX height field: sigma <= (|G| + sqrt(|G|^2 + 2 s^2)) / 2
+                const double proj_max = S.ggx ? 0.5 * (gmax + std::sqrt(gmax * gmax + 2.0 * s_max * s_max))
+                                              : gmax * Phi_d(z) + s_max * phi_d(z);
                 S.maj[((int64_t)kz * S.M[1] + ky) * S.M[0] + kx] = quantize_majorant(rho_max * proj_max);
             }
 }
@@ -858,6 +927,8 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
     if (D->width <= 0 || D->height <= 0 || D->spp <= 0 || D->max_depth < 0) return -1;
     if (!(D->lengthscale > 0.0) || !(D->albedo >= 0.0 && D->albedo <= 1.0)) return -1;
     if (!(D->lengthscale_n >= 0.0)) return -1;
+    if (D->ndf_kind != 0 && D->ndf_kind != 1) return -1;
+    if (D->ndf_kind == 1 && D->mean_kind == 2) return -1;   // GGX needs a macro-surface normal
     if (!D->var_grid && !(D->variance > 0.0)) return -1;
     for (int a = 0; a < 3; ++a) {
         if (!(D->bounds[3 + a] > D->bounds[a])) return -1;
@@ -889,6 +960,7 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
     S->l = D->lengthscale;
     S->l_n = D->lengthscale_n > 0.0 ? D->lengthscale_n : D->lengthscale;
     S->aniso = S->l_n != S->l;
+    S->ggx = D->ndf_kind == 1;
     S->albedo = D->albedo;
     S->albedo_per_prim = D->albedo_per_prim != 0;
     for (int a = 0; a < 3; ++a) {
@@ -1075,8 +1147,9 @@ double oracle_erfcx(double x) { return erfcx_d(x); }
 double oracle_erfinv(double y) { return erfinv_d(y); }
 double oracle_rho(double mu, double sigma) { return rho_of(mu, sigma); }
 
-static PointQ<double> point_from(const double G[3], double s, double albedo, double sn = 0.0) {
+static PointQ<double> point_from(const double G[3], double s, double albedo, double sn = 0.0, bool ggx = false) {
     PointQ<double> q;
+    q.ggx = ggx;
     q.mu = 0.0;
     for (int a = 0; a < 3; ++a) q.G[a] = G[a];
     q.sigma = 0.0;
@@ -1106,17 +1179,19 @@ double oracle_ndf_aniso(double ax, double ay, double az, const double wm[3]) {
 double oracle_lambda_aniso(double ax, double ay, double az, const double w[3]) {
     return lambda_cos_general<double>(ax, ay, az, w[2], w[0] * w[0], w[1] * w[1]) / w[2];
 }
-double oracle_phase_eval(const double G[3], double s, double albedo, const double d[3], const double wi[3]) {
-    return phase_eval(point_from(G, s, albedo), d, wi);
+static double phase_eval_k(const double G[3], double s, double albedo, const double d[3], const double wi[3],
+                           bool ggx) {
+    return phase_eval(point_from(G, s, albedo, 0.0, ggx), d, wi);
 }
-double oracle_mixture_pdf(const double G[3], double s, double R, const double d[3], const double wm[3]) {
+static double mixture_pdf_k(const double G[3], double s, double R, const double d[3], const double wm[3],
+                            bool ggx) {
     const double v[3] = {-d[0], -d[1], -d[2]};
-    const Proposal p = make_proposal(point_from(G, s, 1.0), R, v);
+    const Proposal p = make_proposal(point_from(G, s, 1.0, 0.0, ggx), R, v);
     return mixture_pdf(p, v, wm);
 }
-int oracle_phase_sample(const double G[3], double s, double albedo, double R, const double d[3],
-                        const double u[3], double* wi, double* wm, double* weight, double* pdf) {
-    const PointQ<double> q = point_from(G, s, albedo);
+static int phase_sample_k(const double G[3], double s, double albedo, double R, const double d[3],
+                          const double u[3], double* wi, double* wm, double* weight, double* pdf, bool ggx) {
+    const PointQ<double> q = point_from(G, s, albedo, 0.0, ggx);
     const double v[3] = {-d[0], -d[1], -d[2]};
     const Proposal p = make_proposal(q, R, v);
     const uint32_t ua = (uint32_t)(u[1] * 0x1p24), ub = (uint32_t)(u[2] * 0x1p24);
@@ -1128,12 +1203,38 @@ int oracle_phase_sample(const double G[3], double s, double albedo, double R, co
     *weight = albedo * vm * ndf(q, wm) / (sigma_proj(q, d) * *pdf);
     return 0;
 }
+double oracle_phase_eval(const double G[3], double s, double albedo, const double d[3], const double wi[3]) {
+    return phase_eval_k(G, s, albedo, d, wi, false);
+}
+double oracle_mixture_pdf(const double G[3], double s, double R, const double d[3], const double wm[3]) {
+    return mixture_pdf_k(G, s, R, d, wm, false);
+}
+int oracle_phase_sample(const double G[3], double s, double albedo, double R, const double d[3],
+                        const double u[3], double* wi, double* wm, double* weight, double* pdf) {
+    return phase_sample_k(G, s, albedo, R, d, u, wi, wm, weight, pdf, false);
+}
+double oracle_sigma_proj_ggx(const double G[3], double s, const double d[3]) {
+    return sigma_proj(point_from(G, s, 1.0, 0.0, true), d);
+}
+double oracle_ndf_ggx(const double G[3], double s, const double wm[3]) {
+    return ndf(point_from(G, s, 1.0, 0.0, true), wm);
+}
+double oracle_phase_eval_ggx(const double G[3], double s, double albedo, const double d[3], const double wi[3]) {
+    return phase_eval_k(G, s, albedo, d, wi, true);
+}
+double oracle_mixture_pdf_ggx(const double G[3], double s, double R, const double d[3], const double wm[3]) {
+    return mixture_pdf_k(G, s, R, d, wm, true);
+}
+int oracle_phase_sample_ggx(const double G[3], double s, double albedo, double R, const double d[3],
+                            const double u[3], double* wi, double* wm, double* weight, double* pdf) {
+    return phase_sample_k(G, s, albedo, R, d, u, wi, wm, weight, pdf, true);
+}
 
-int oracle_eval_point(const oracle_scene* sc, const double x[3], double out[7]) {
+int oracle_eval_point(const oracle_scene* sc, const double x[3], double out[8]) {
     if (!sc) return -1;
     const PointQ<double> q = eval_point(plain_params(sc), x);
     out[0] = q.mu; out[1] = q.G[0]; out[2] = q.G[1]; out[3] = q.G[2];
-    out[4] = q.sigma; out[5] = q.s; out[6] = q.albedo;
+    out[4] = q.sigma; out[5] = q.s; out[6] = q.albedo; out[7] = q.sn;
     return 0;
 }
 

@@ -37,6 +37,7 @@ class _Desc(C.Structure):
         ("up", C.c_double * 3), ("fov_deg", C.c_double), ("window", C.c_double * 2),
         ("width", C.c_int32), ("height", C.c_int32), ("spp", C.c_int32), ("max_depth", C.c_int32),
         ("seed", C.c_uint64), ("scene_id", C.c_uint32), ("lengthscale_n", C.c_double),
+        ("ndf_kind", C.c_int32),
     ]
 
 
@@ -83,11 +84,17 @@ def lib():
         L.oracle_sigma_proj.restype = C.c_double
         L.oracle_ndf.argtypes = [dp, C.c_double, dp]
         L.oracle_ndf.restype = C.c_double
-        L.oracle_phase_eval.argtypes = [dp, C.c_double, C.c_double, dp, dp]
-        L.oracle_phase_eval.restype = C.c_double
-        L.oracle_mixture_pdf.argtypes = [dp, C.c_double, C.c_double, dp, dp]
-        L.oracle_mixture_pdf.restype = C.c_double
+        for sfx in ("", "_ggx"):
+            getattr(L, "oracle_phase_eval" + sfx).argtypes = [dp, C.c_double, C.c_double, dp, dp]
+            getattr(L, "oracle_phase_eval" + sfx).restype = C.c_double
+            getattr(L, "oracle_mixture_pdf" + sfx).argtypes = [dp, C.c_double, C.c_double, dp, dp]
+            getattr(L, "oracle_mixture_pdf" + sfx).restype = C.c_double
+        for name in ("oracle_sigma_proj_ggx", "oracle_ndf_ggx"):
+            getattr(L, name).argtypes = [dp, C.c_double, dp]
+            getattr(L, name).restype = C.c_double
         L.oracle_phase_sample.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp,
+                                          dp, dp]
+        L.oracle_phase_sample_ggx.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp,
                                           dp, dp]
         L.oracle_eval_point.argtypes = [C.c_void_p, dp, dp]
         L.oracle_sigma_t.argtypes = [C.c_void_p, dp, dp]
@@ -154,6 +161,7 @@ class OracleScene:
         d.seed = int(s.seed)
         d.scene_id = int(s.scene_id)
         d.lengthscale_n = f32(s.lengthscale_n)
+        d.ndf_kind = int(s.ndf_kind)
         self._desc = d
         h = C.c_void_p()
         rc = lib().oracle_scene_create(C.byref(d), C.byref(h))
@@ -246,10 +254,10 @@ class OracleScene:
 
     # ---- point functions ----
     def eval_point(self, x):
-        out = np.zeros(7)
+        out = np.zeros(8)
         lib().oracle_eval_point(self.handle, _dp(_vec(x)), _dp(out))
         return {"mu": out[0], "G": out[1:4].copy(), "sigma": out[4], "s": out[5],
-                "albedo": out[6]}
+                "albedo": out[6], "sn": out[7]}
 
     def sigma_t(self, x, d) -> float:
         return lib().oracle_sigma_t(self.handle, _dp(_vec(x)), _dp(_vec(d)))
@@ -328,18 +336,30 @@ def beckmann_lambda(a: float) -> float:
     return lib().oracle_beckmann_lambda(float(a))
 
 
-def phase_eval(G, s, albedo, d, wi) -> float:
-    return lib().oracle_phase_eval(_dp(_vec(G)), float(s), float(albedo), _dp(_vec(d)),
-                                   _dp(_vec(wi)))
+def phase_eval(G, s, albedo, d, wi, ggx: bool = False) -> float:
+    f = lib().oracle_phase_eval_ggx if ggx else lib().oracle_phase_eval
+    return f(_dp(_vec(G)), float(s), float(albedo), _dp(_vec(d)), _dp(_vec(wi)))
 
 
-def mixture_pdf(G, s, R, d, wm) -> float:
-    return lib().oracle_mixture_pdf(_dp(_vec(G)), float(s), float(R), _dp(_vec(d)), _dp(_vec(wm)))
+def mixture_pdf(G, s, R, d, wm, ggx: bool = False) -> float:
+    f = lib().oracle_mixture_pdf_ggx if ggx else lib().oracle_mixture_pdf
+    return f(_dp(_vec(G)), float(s), float(R), _dp(_vec(d)), _dp(_vec(wm)))
 
 
-def phase_sample(G, s, albedo, R, d, u):
+def phase_sample(G, s, albedo, R, d, u, ggx: bool = False):
     wi, wm = np.zeros(3), np.zeros(3)
     w, p = np.zeros(1), np.zeros(1)
-    lib().oracle_phase_sample(_dp(_vec(G)), float(s), float(albedo), float(R), _dp(_vec(d)),
-                              _dp(_vec(u)), _dp(wi), _dp(wm), _dp(w), _dp(p))
+    f = lib().oracle_phase_sample_ggx if ggx else lib().oracle_phase_sample
+    f(_dp(_vec(G)), float(s), float(albedo), float(R), _dp(_vec(d)), _dp(_vec(u)), _dp(wi), _dp(wm),
+      _dp(w), _dp(p))
     return wi, wm, float(w[0]), float(p[0])
+
+
+def sigma_proj_ggx(G, s: float, d) -> float:
+    """Projected area of the GGX height-field macrofacet (roughness sqrt(2) s / |G|)."""
+    return lib().oracle_sigma_proj_ggx(_dp(_vec(G)), float(s), _dp(_vec(d)))
+
+
+def ndf_ggx(G, s: float, wm) -> float:
+    """GGX NDF about G/|G| with roughness sqrt(2) s / |G|, scaled by |G|."""
+    return lib().oracle_ndf_ggx(_dp(_vec(G)), float(s), _dp(_vec(wm)))

@@ -185,6 +185,8 @@ int validate_desc(const gpss_scene_desc* D) {
     }
     if (!(D->lengthscale > 0.0f) || !std::isfinite(D->lengthscale))
         return set_error(GPSS_ERR_INVALID_ARG, "lengthscale must be > 0");
+    if (!(D->lengthscale_n >= 0.0f) || !std::isfinite(D->lengthscale_n))
+        return set_error(GPSS_ERR_INVALID_ARG, "lengthscale_n must be >= 0 (0: isotropic)");
     if (!(D->albedo >= 0.0f && D->albedo <= 1.0f)) return set_error(GPSS_ERR_INVALID_ARG, "albedo not in [0,1]");
     if (!(D->mix_R >= 0.0f && D->mix_R <= 1.0f)) return set_error(GPSS_ERR_INVALID_ARG, "mix_R not in [0,1]");
     if (!finite3(D->bounds, 6)) return set_error(GPSS_ERR_INVALID_ARG, "bounds not finite");
@@ -236,6 +238,13 @@ void free_scene(gpss_scene* s) {
     delete s;
 }
 
+// (l / l_n)^2 - 1: the kernel's anisotropy as the scene record carries it (0: isotropic).
+float aniso_k(const gpss_scene_desc& D) {
+    if (!(D.lengthscale_n > 0.0f) || D.lengthscale_n == D.lengthscale) return 0.0f;
+    const float r = D.lengthscale / D.lengthscale_n;
+    return r * r - 1.0f;
+}
+
 void fill_dev(gpss_scene* s) {
     const gpss_scene_desc& D = s->desc;
     gpss::SceneDev& V = s->dev;
@@ -247,6 +256,7 @@ void fill_dev(gpss_scene* s) {
     V.var_grid = s->d_var;
     V.variance = D.variance;
     V.lengthscale = D.lengthscale;
+    V.aniso_k = aniso_k(D);
     V.albedo = D.albedo;
     V.albedo_per_prim = D.albedo_per_prim ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
@@ -440,6 +450,7 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
     scene->desc.albedo = albedo;
     scene->dev.variance = variance;
     scene->dev.lengthscale = lengthscale;
+    scene->dev.aniso_k = aniso_k(scene->desc);
     scene->dev.albedo = albedo;
     scene->dev_version++;
     scene->maj_h_stale = true;
@@ -452,6 +463,8 @@ int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float
     if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
     if (scene->d_offset && !grad_offset_dev)
         return set_error(GPSS_ERR_INVALID_ARG, "scene has a mean-offset grid: grad_offset_dev is required");
+    if (scene->dev.aniso_k != 0.0f)
+        return set_error(GPSS_ERR_UNSUPPORTED, "the adjoint supports the isotropic kernel only (lengthscale_n = 0)");
     return gpss::launch_adjoint(scene, dloss_dimage_dev, grad_offset_dev, grad_scalars_dev, s0, s1 - s0,
                                 reinterpret_cast<hipStream_t>(stream));
 }

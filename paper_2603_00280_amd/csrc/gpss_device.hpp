@@ -41,6 +41,7 @@ struct SceneDev {
     int var_res[3];
     float var_scale[3];
     float lengthscale;
+    float aniso_k;                // (l / l_n)^2 - 1 for lengthscale l_n along the mean gradient; 0: isotropic
     float albedo;
     int albedo_per_prim;
     float lo[3], hi[3];
@@ -267,12 +268,15 @@ __device__ __forceinline__ float tri_eval(const float* __restrict__ g, const int
 }
 
 // GP statistics at x (Sec. 3.1, Eq. joint_fg): f ~ N(mu, sigma^2) and, independent at the
-// same point, g ~ N(grad mu, s^2 I) with s = sigma / l for the isotropic SE kernel.
+// same point, g ~ N(grad mu, Sigma) with Sigma = s^2 (I - n n^T) + s_n^2 n n^T about the
+// local mean-gradient direction n (z where grad mu = 0), s = sigma / l, s_n = sigma / l_n;
+// ak = (s_n / s)^2 - 1 (0 for the isotropic kernel, Sigma = s^2 I).
 struct PointQ {
     float mu;
     float3 G;
     float sigma;
     float s;
+    float ak;
     float albedo;
 };
 
@@ -293,6 +297,7 @@ __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
     }
     q.sigma = sqrtf(var);
     q.s = q.sigma / S.lengthscale;
+    q.ak = S.aniso_k;
     q.albedo = (S.albedo_per_prim && which >= 0) ? S.prims[2 * which + 1].w : S.albedo;
     return q;
 }
@@ -306,41 +311,58 @@ __device__ __forceinline__ float rho_of(float mu, float sigma) {
     return kSqrt2OverPi / (sigma * erfcxf(-z * kInvSqrt2));
 }
 
-// Projected area sigma(d) = E[max(0, -d.g)], g ~ N(G, s^2 I): with m = d.G, z = m / s,
-//   s phi(z) - m Phi(-z) = max(-m, 0) + s phi(z) (1 - |z| sqrt(pi/2) erfcx(|z|/sqrt2)),
-// one scaled complementary error function for either sign of z (Phi of a non-positive
-// argument written as sqrt(pi/2) phi erfcx).  Equals the paper's Lambda(w) cos(theta) for G
-// of unit length; scales with |G| otherwise.
-__device__ __forceinline__ float sigma_proj(float3 G, float s, float3 d) {
-    const float m = dot(d, G);
-    const float z = m / s;
-    const float az = fabsf(z);
-    const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
-    return fmaxf(-m, 0.0f) + s * ph * (1.0f - az * kSqrtHalfPi * erfcxf(az * kInvSqrt2));
+// Cosine between a unit direction and the local mean-gradient direction (z where G = 0).
+__device__ __forceinline__ float cos_to_normal(float3 G, float3 w) {
+    const float g2 = dot(G, G);
+    return g2 > 0.0f ? dot(w, G) * rsqrtf(g2) : w.z;
 }
 
-// Generalized NDF (Sec. 4.2.2) for g ~ N(G, s^2 I): int_0^inf P(t wm) t^3 dt in closed form,
-//   D = s (2 pi)^(-3/2) [ (k^2 + 2) e^{-|G|^2/(2 s^2)} + sqrt(2 pi) k (k^2 + 3) e^{-q/2} Phi(k) ],
-// k = G.wm / s, q = |G x wm|^2 / s^2 (so |G|^2/s^2 = k^2 + q).  With e^{-q/2} Phi(k) written
-// through erfcx(|k|/sqrt2) for either sign of k:
-//   D = s (2 pi)^(-3/2) [ e^{-|G|^2/(2s^2)} ((k^2+2) - sqrt(pi/2) |k| (k^2+3) erfcx(|k|/sqrt2))
-//                         + [k > 0] sqrt(2 pi) k (k^2+3) e^{-q/2} ].
-__device__ __forceinline__ float ndf(float3 G, float s, float3 wm) {
+// Projected area sigma(d) = E[max(0, -d.g)], g ~ N(G, Sigma): -d.g is Gaussian with mean
+// -m, m = d.G, and standard deviation s_d = s sqrt(1 + ak c^2), c = d.n; with z = m / s_d,
+//   s_d phi(z) - m Phi(-z) = max(-m, 0) + s_d phi(z) (1 - |z| sqrt(pi/2) erfcx(|z|/sqrt2)),
+// one scaled complementary error function for either sign of z (Phi of a non-positive
+// argument written as sqrt(pi/2) phi erfcx).  Equals the paper's Lambda(w) cos(theta)
+// (Eq. generalized_lambda, alpha_x = alpha_y = sqrt2 s, alpha_z = sqrt2 s_n) for G of unit
+// length; scales with |G| otherwise.
+__device__ __forceinline__ float sigma_proj(float3 G, float s, float ak, float3 d) {
+    const float m = dot(d, G);
+    const float c = cos_to_normal(G, d);
+    const float sd = s * sqrtf(1.0f + ak * (c * c));
+    const float z = m / sd;
+    const float az = fabsf(z);
+    const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
+    return fmaxf(-m, 0.0f) + sd * ph * (1.0f - az * kSqrtHalfPi * erfcxf(az * kInvSqrt2));
+}
+
+// Generalized NDF (Sec. 4.2.2) for g ~ N(G, Sigma): int_0^inf P(t wm) t^3 dt in closed form.
+// With c = wm.n, r^2 = 1 + ak = (s_n / s)^2 and a = 1 - c^2 ak / (1 + ak) (wm^T Sigma^-1 wm
+// = a / s^2), the exponent of P(t wm) is -(a/s^2)(t - t0)^2 / 2 - q / 2 with
+//   k = G.wm / (s r^2 sqrt(a)),  q = |G|^2 (1 - c^2) / (s^2 r^2 a),  |G|^2/(s r)^2 = k^2 + q,
+// so that (Eq. macro_ndf with alpha_x = alpha_y = sqrt2 s, alpha_z = sqrt2 s_n)
+//   D = s / (r a^2) (2 pi)^(-3/2) [ (k^2 + 2) e^{-|G|^2/(2 s^2 r^2)} + sqrt(2 pi) k (k^2 + 3) e^{-q/2} Phi(k) ],
+// and, with e^{-q/2} Phi(k) written through erfcx(|k|/sqrt2) for either sign of k,
+//   D = s / (r a^2) (2 pi)^(-3/2) [ e^{-|G|^2/(2 s^2 r^2)} ((k^2+2) - sqrt(pi/2) |k| (k^2+3) erfcx(|k|/sqrt2))
+//                                   + [k > 0] sqrt(2 pi) k (k^2+3) e^{-q/2} ].
+// For the isotropic kernel (ak = 0): r = a = 1, k = G.wm / s, q = |G x wm|^2 / s^2.
+__device__ __forceinline__ float ndf(float3 G, float s, float ak, float3 wm) {
+    const float r2 = 1.0f + ak;
+    const float c = cos_to_normal(G, wm);
+    const float a = 1.0f - (c * c) * (ak / r2);
     const float is = 1.0f / s;
-    const float k = dot(G, wm) * is;
-    const float3 c = cross(G, wm);
-    const float q = dot(c, c) * is * is;
-    const float g2 = dot(G, G) * is * is;
-    const float eG = expf(-0.5f * g2);
-    const float pre = s * kInv2PiPow1p5;
-    const float k2 = k * k, ak = fabsf(k);
-    const float b = (k2 + 2.0f) - kSqrtHalfPi * ak * (k2 + 3.0f) * erfcxf(ak * kInvSqrt2);
+    const float isr2 = is * is / r2;
+    const float g2 = dot(G, G);
+    const float k = dot(G, wm) * is * rsqrtf(a) / r2;
+    const float q = g2 * fmaxf(1.0f - c * c, 0.0f) * isr2 / a;
+    const float eG = expf(-0.5f * g2 * isr2);
+    const float pre = s * kInv2PiPow1p5 * rsqrtf(r2) / (a * a);
+    const float k2 = k * k, akk = fabsf(k);
+    const float b = (k2 + 2.0f) - kSqrtHalfPi * akk * (k2 + 3.0f) * erfcxf(akk * kInvSqrt2);
     const float up = k > 0.0f ? kSqrt2Pi * k * (k2 + 3.0f) * expf(-0.5f * q) : 0.0f;
     return pre * fmaxf(eG * b + up, 0.0f);
 }
 
 __device__ __forceinline__ float sigma_t_of(const PointQ& q, float3 d) {
-    return rho_of(q.mu, q.sigma) * sigma_proj(q.G, q.s, d);
+    return rho_of(q.mu, q.sigma) * sigma_proj(q.G, q.s, q.ak, d);
 }
 
 // Conductor phase function with F = albedo for travel direction d, scattered direction wi.
@@ -349,7 +371,7 @@ __device__ __forceinline__ float phase_eval(const PointQ& q, float3 d, float3 wi
     const float hn = sqrtf(dot(h, h));
     if (hn < 1e-7f) return 0.0f;
     h = (1.0f / hn) * h;
-    return q.albedo * ndf(q.G, q.s, h) / (4.0f * sigma_proj(q.G, q.s, d));
+    return q.albedo * ndf(q.G, q.s, q.ak, h) / (4.0f * sigma_proj(q.G, q.s, q.ak, d));
 }
 
 // ---------------------------------------------------------------------------

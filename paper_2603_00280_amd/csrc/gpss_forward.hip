@@ -155,7 +155,8 @@ int launch_majorants(gpss_scene* s, hipStream_t stream) {
         A.M[a] = (int)D.majorant_res[a];
     }
     A.variance = D.variance;
-    A.lengthscale = D.lengthscale;
+    // the largest gradient standard deviation: sigma over the smaller of the two lengthscales
+    A.lengthscale = D.lengthscale_n > 0.0f ? fminf(D.lengthscale, D.lengthscale_n) : D.lengthscale;
     const int n = A.M[0] * A.M[1] * A.M[2];
     hipLaunchKernelGGL(majorant_kernel, dim3((n + 127) / 128), dim3(128), 0, stream, A, s->d_maj);
     return check_hip(hipGetLastError(), "majorant_kernel launch");
@@ -269,7 +270,7 @@ __global__ void eval_kernel(SceneDev S, const float* __restrict__ pts, const flo
     const float3 d = f3(dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]);
     const PointQ q = eval_point(S, x);
     const float r = rho_of(q.mu, q.sigma);
-    const float sp = sigma_proj(q.G, q.s, d);
+    const float sp = sigma_proj(q.G, q.s, q.ak, d);
     float* o = out + 8 * i;
     o[0] = q.mu;
     o[1] = q.sigma;
@@ -277,7 +278,7 @@ __global__ void eval_kernel(SceneDev S, const float* __restrict__ pts, const flo
     o[3] = r;
     o[4] = sp;
     o[5] = r * sp;
-    o[6] = ndf(q.G, q.s, d);
+    o[6] = ndf(q.G, q.s, q.ak, d);
     o[7] = q.albedo;
 }
 

@@ -120,3 +120,18 @@ def projected_area_full(d, mean, cov):
     hi = max(m, 0.0) + 40 * sd
     val, _ = integrate.quad(f, 0.0, hi, epsabs=0.0, epsrel=1e-12, limit=400, points=[max(m, 0.0)])
     return val
+
+
+def ggx_D(alpha, cos_m):
+    """Textbook GGX (Trowbridge-Reitz) NDF, zero below the horizon."""
+    if cos_m <= 0.0:
+        return 0.0
+    c2 = cos_m * cos_m
+    t2 = (1.0 - c2) / c2
+    return alpha * alpha / (math.pi * c2 * c2 * (alpha * alpha + t2) ** 2)
+
+
+def ggx_lambda(alpha, cos_t):
+    """Textbook GGX Smith Lambda for a direction above the horizon."""
+    t2 = (1.0 - cos_t * cos_t) / (cos_t * cos_t)
+    return 0.5 * (-1.0 + math.sqrt(1.0 + alpha * alpha * t2))

@@ -510,3 +510,125 @@ def test_anisotropic_reduces_to_isotropic_and_height_field():
         e1 = abs(orc.ndf_n([0, 0, 1.0], s, 1e-3, wm) / ref.beckmann_D(math.sqrt(2) * s, c) - 1)
         e2 = abs(orc.ndf_n([0, 0, 1.0], s, 5e-4, wm) / ref.beckmann_D(math.sqrt(2) * s, c) - 1)
         assert e1 < 2e-3 and e2 < 0.3 * e1 + 1e-9
+
+
+def test_planar_single_scattering_anisotropic():
+    """The depth-1 planar closed form with an anisotropic kernel (l_n along the plane normal):
+    the same formula with the full-covariance projected areas and NDF (Eqs.
+    generalized_lambda, macro_ndf with alpha_z != alpha_x = alpha_y)."""
+    ln = 0.2
+    s = sc.plane_scene(width=32, height=32, spp=256, max_depth=1).replace(lengthscale_n=ln)
+    r = orc.OracleScene(s).render()
+    assert r["counters"]["violations"] == 0
+    sigma = math.sqrt(orc.f32(0.01))
+    s0, sn = sigma / orc.f32(0.05), sigma / orc.f32(ln)
+    G = np.array([0, 0, 1.0])
+    cov = ref.aniso_cov(G, s0, sn)
+    v = np.array([math.sin(math.pi / 4), 0, math.cos(math.pi / 4)])
+    ld = np.asarray(s.dir_light[:3], float)
+    n = ref.projected_area_full(-v, G, cov) / v[2] + ref.projected_area_full(ld, G, cov) / ld[2]
+    h = (v + ld) / np.linalg.norm(v + ld)
+    D = ref.ndf_by_gdf_full(h, G, cov)
+    leak = (special.ndtr(-0.4 / sigma) / special.ndtr(0.4 / sigma)) ** n
+    want = 0.9 * 1.0 * D / (4 * v[2] * n) * (1 - leak)
+    inner = r["mean"][10:22, 10:22]
+    se = math.sqrt(r["var"][10:22, 10:22].mean() / (s.spp * inner.size))
+    assert abs(inner.mean() - want) < 5 * se
+    # and it differs from the isotropic value by far more than the noise
+    assert abs(want - 0.087221) > 20 * se
+
+
+# ---------------------------------------------------------------------------
+# GGX height-field macrofacet (end of Sec. 4.1: the NDF may be chosen freely under the
+# Smith assumption; Fig. cmp_ggx): D and Lambda of GGX about n = G/|G|, roughness
+# sqrt(2) s / |G|, scaled by |G|
+# ---------------------------------------------------------------------------
+def test_ggx_ndf_identities_by_quadrature():
+    rng = np.random.default_rng(41)
+    for G, s in ((np.array([0, 0, 1.0]), 0.3), (np.array([0.4, -0.3, 0.7]), 0.6), (np.array([0.0, 1.3, 0.0]), 0.1)):
+        dirs, W = ref.sphere_grid(G, 1200, 96, hemisphere=True)
+        D = np.array([orc.ndf_ggx(G, s, m) for m in dirs])
+        gn = np.linalg.norm(G)
+        n = G / gn
+        assert float(np.sum(W * (dirs @ n) * D)) == pytest.approx(gn, rel=2e-5)   # projected area of the micro-surface
+        for _ in range(3):
+            w = _rand_dir(rng)
+            assert float(np.sum(W * (dirs @ w) * D)) == pytest.approx(float(w @ G), abs=5e-5 * gn)
+            vis = float(np.sum(W * np.maximum(0.0, dirs @ (-w)) * D))
+            assert vis == pytest.approx(orc.sigma_proj_ggx(G, s, w), rel=1e-3, abs=1e-6)
+        # textbook values about the normal
+        alpha = math.sqrt(2) * s / gn
+        for c in (1.0, 0.9, 0.5):
+            m = c * n + math.sqrt(1 - c * c) * ref.frame(n)[0]
+            assert orc.ndf_ggx(G, s, m) == pytest.approx(gn * ref.ggx_D(alpha, c), rel=1e-12)
+
+
+def test_ggx_projected_area_is_cos_one_plus_lambda():
+    rng = np.random.default_rng(42)
+    for _ in range(30):
+        G = _rand_dir(rng) * rng.choice([1.0, 0.6, 1.4])
+        s = float(rng.choice([0.05, 0.3, 1.0]))
+        w = _rand_dir(rng)
+        gn = np.linalg.norm(G)
+        alpha = math.sqrt(2) * s / gn
+        c = -float(w @ G) / gn   # cosine of the back-travel direction with n
+        want = gn * (c * (1 + ref.ggx_lambda(alpha, c)) if c > 0 else -c * ref.ggx_lambda(alpha, -c))
+        assert orc.sigma_proj_ggx(G, s, w) == pytest.approx(want, rel=1e-12, abs=1e-15)
+
+
+def test_ggx_phase_normalization_and_sampler():
+    rng = np.random.default_rng(43)
+    G, s, alb = np.array([0.2, 0.1, 0.9]), 0.25, 0.7
+    for d in (np.array([0.5, 0.0, -math.sqrt(0.75)]), np.array([0.0, 0.6, 0.8])):
+        dirs, W = ref.sphere_grid(-d, 600, 400)
+        p = np.array([orc.phase_eval(G, s, alb, d, wi, ggx=True) for wi in dirs])
+        assert float(np.sum(p * W)) == pytest.approx(alb, rel=2e-3)
+        n = 20000
+        U = _u24(rng, n)
+        ws = np.array([orc.phase_sample(G, s, alb, 0.5, d, U[k], ggx=True)[2] for k in range(n)])
+        assert abs(ws.mean() - alb) < 5 * ws.std() / math.sqrt(n) + 1e-12
+
+
+def test_ggx_vndf_sampler_histogram():
+    """R = 1: half vectors follow the textbook GGX visible-normal density
+    <v, m> D(m) / (cos_v (1 + Lambda(v)))."""
+    rng = np.random.default_rng(44)
+    G, s = np.array([0, 0, 1.0]), 0.35
+    alpha = math.sqrt(2) * s
+    d = np.array([0.6, 0.0, -0.8])
+    v = -d
+    n = 40000
+    U = _u24(rng, n)
+    U[:, 0] = 0.0
+    ms = np.array([orc.phase_sample(G, s, 1.0, 1.0, d, U[k], ggx=True)[1] for k in range(n)])
+    edges = np.linspace(0.3, 1.0, 15)
+    obs, _ = np.histogram(ms[:, 2], bins=edges)
+    dirs, W = ref.sphere_grid(G, 600, 256, hemisphere=True)
+    pdf = np.array([max(0.0, float(m @ v)) * ref.ggx_D(alpha, m[2]) for m in dirs])
+    pdf /= v[2] * (1 + ref.ggx_lambda(alpha, v[2]))
+    exp = np.array([np.sum((pdf * W)[(dirs[:, 2] >= a) & (dirs[:, 2] < b)])
+                    for a, b in zip(edges[:-1], edges[1:])]) * n
+    chi2 = float(np.sum((obs - exp) ** 2 / exp))
+    assert stats.chi2.sf(chi2, len(obs) - 1) > 1e-3
+    assert np.all(ms[:, 2] > 0)
+
+
+def test_planar_single_scattering_ggx_surface_limit():
+    """Depth 1 on a GGX planar macrofacet: the GGX microfacet BRDF with the Smith
+    height-correlated masking-shadowing, I = albedo E D(h) / (4 cos_v (1 + L(v) + L(l)))
+    (surface limit, Fig. cmp_ggx), up to the bounded shell's leak."""
+    s = sc.plane_scene(width=32, height=32, spp=256, max_depth=1).replace(ndf_kind=sc.NDF_GGX)
+    r = orc.OracleScene(s).render()
+    assert r["counters"]["violations"] == 0
+    sigma = math.sqrt(orc.f32(0.01))
+    alpha = math.sqrt(2) * sigma / orc.f32(0.05)
+    v = np.array([math.sin(math.pi / 4), 0, math.cos(math.pi / 4)])
+    ld = np.asarray(s.dir_light[:3], float)
+    h = (v + ld) / np.linalg.norm(v + ld)
+    lv, ll = ref.ggx_lambda(alpha, v[2]), ref.ggx_lambda(alpha, ld[2])
+    n = (1 + lv) + ll
+    leak = (special.ndtr(-0.4 / sigma) / special.ndtr(0.4 / sigma)) ** n
+    want = 0.9 * 1.0 * ref.ggx_D(alpha, h[2]) / (4 * v[2] * n) * (1 - leak)
+    inner = r["mean"][10:22, 10:22]
+    se = math.sqrt(r["var"][10:22, 10:22].mean() / (s.spp * inner.size))
+    assert abs(inner.mean() - want) < 5 * se
