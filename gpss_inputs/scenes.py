@@ -166,6 +166,20 @@ def aniso_sphere_scene(alpha_z: float = 0.01, alpha_t: float = ANISO_ALPHA_T, **
 
 
 # ---------------------------------------------------------------------------
+# GGX height-field macrofacet (Fig. cmp_ggx): the sphere with a thin shell (variance 1e-4,
+# sigma = 0.01, as in the paper's microfacet comparisons) and GGX roughness
+# alpha = sqrt(2) sigma / l in 0.1 .. 1.0.
+# ---------------------------------------------------------------------------
+GGX_ALPHAS = (0.1, 0.5, 1.0)
+
+
+def ggx_sphere_scene(alpha: float = 0.5, variance: float = 1e-4, **kw) -> Scene:
+    sigma = float(np.sqrt(np.float32(variance)))
+    s = sphere_scene(lengthscale=float(np.sqrt(2.0) * sigma / alpha), variance=variance, **kw)
+    return s.replace(name=f"ggx_sphere_a{alpha:g}", ndf_kind=NDF_GGX)
+
+
+# ---------------------------------------------------------------------------
 # Workload 3: union of 16 seeded primitives, value-noise variance grid.
 # ---------------------------------------------------------------------------
 def _smoothstep(t):

@@ -47,6 +47,7 @@ enum {
 enum { GPSS_MEAN_PLANE = 0, GPSS_MEAN_SDF = 1, GPSS_MEAN_CONST = 2 };
 enum { GPSS_PRIM_SPHERE = 0, GPSS_PRIM_BOX = 1 };
 enum { GPSS_CAM_ORTHO = 0, GPSS_CAM_PINHOLE = 1 };
+enum { GPSS_NDF_GENERALIZED = 0, GPSS_NDF_GGX = 1 };
 
 /* Statement of one rendering problem (all host memory, copied by gpss_scene_create).
  * Grids are float32, x fastest, node-centred over `bounds` (node i at lo + i/(res-1)*ext). */
@@ -90,6 +91,12 @@ typedef struct {
      * `lengthscale` applies across it.  0 = isotropic (l_n = l).  Sec. 4.2.1: alpha_z =
      * sqrt(2) sigma / l_n in Eqs. generalized_lambda and macro_ndf. */
     float lengthscale_n;
+    /* NDF of the macrofacet: GPSS_NDF_GENERALIZED (the GP macrofacet of Sec. 4.2, Eqs.
+     * generalized_lambda and macro_ndf) or GPSS_NDF_GGX (height-field macrofacet with the GGX
+     * NDF and Smith Lambda about the mean gradient, roughness sqrt(2) sigma / l; end of
+     * Sec. 4.1, Fig. cmp_ggx).  GGX needs a mean with a gradient (not GPSS_MEAN_CONST) and
+     * the isotropic kernel. */
+    int32_t ndf_kind;
 } gpss_scene_desc;
 
 /* Create a scene: validates `desc`, uploads primitives and grids, and builds the

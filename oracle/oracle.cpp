@@ -299,7 +299,10 @@ T ndf_general(const T& ax, const T& ay, const T& az, const T& c, const T& tx2, c
 //   which is (cos + sqrt(cos^2 + alpha^2 (1 - cos^2))) / 2 for both signs.
 template <class T>
 T ggx_lambda_cos(const T& alpha, const T& c) {
-    return 0.5 * (c + t_sqrt(c * c + alpha * alpha * (1.0 - c * c)));
+    const T e = alpha * alpha * (1.0 - c * c);
+    const T r = t_sqrt(c * c + e);
+    // (c + r) / 2; for c < 0 (from below) the same value as e / (2 (r - c)), free of cancellation
+    return val(c) < 0.0 ? 0.5 * e / (r - c) : 0.5 * (c + r);
 }
 template <class T>
 T ggx_D(const T& alpha, const T& c) {

@@ -187,6 +187,12 @@ int validate_desc(const gpss_scene_desc* D) {
         return set_error(GPSS_ERR_INVALID_ARG, "lengthscale must be > 0");
     if (!(D->lengthscale_n >= 0.0f) || !std::isfinite(D->lengthscale_n))
         return set_error(GPSS_ERR_INVALID_ARG, "lengthscale_n must be >= 0 (0: isotropic)");
+    if (D->ndf_kind != GPSS_NDF_GENERALIZED && D->ndf_kind != GPSS_NDF_GGX)
+        return set_error(GPSS_ERR_INVALID_ARG, "unknown ndf_kind %d", D->ndf_kind);
+    if (D->ndf_kind == GPSS_NDF_GGX && D->mean_kind == GPSS_MEAN_CONST)
+        return set_error(GPSS_ERR_INVALID_ARG, "the GGX macrofacet needs a mean with a gradient");
+    if (D->ndf_kind == GPSS_NDF_GGX && D->lengthscale_n > 0.0f && D->lengthscale_n != D->lengthscale)
+        return set_error(GPSS_ERR_INVALID_ARG, "the GGX macrofacet takes the isotropic kernel");
     if (!(D->albedo >= 0.0f && D->albedo <= 1.0f)) return set_error(GPSS_ERR_INVALID_ARG, "albedo not in [0,1]");
     if (!(D->mix_R >= 0.0f && D->mix_R <= 1.0f)) return set_error(GPSS_ERR_INVALID_ARG, "mix_R not in [0,1]");
     if (!finite3(D->bounds, 6)) return set_error(GPSS_ERR_INVALID_ARG, "bounds not finite");
@@ -257,6 +263,7 @@ void fill_dev(gpss_scene* s) {
     V.variance = D.variance;
     V.lengthscale = D.lengthscale;
     V.aniso_k = aniso_k(D);
+    V.ggx = D.ndf_kind == GPSS_NDF_GGX;
     V.albedo = D.albedo;
     V.albedo_per_prim = D.albedo_per_prim ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
@@ -463,8 +470,9 @@ int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float
     if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
     if (scene->d_offset && !grad_offset_dev)
         return set_error(GPSS_ERR_INVALID_ARG, "scene has a mean-offset grid: grad_offset_dev is required");
-    if (scene->dev.aniso_k != 0.0f)
-        return set_error(GPSS_ERR_UNSUPPORTED, "the adjoint supports the isotropic kernel only (lengthscale_n = 0)");
+    if (scene->dev.aniso_k != 0.0f || scene->dev.ggx)
+        return set_error(GPSS_ERR_UNSUPPORTED,
+                         "the adjoint supports the generalized macrofacet with the isotropic kernel only");
     return gpss::launch_adjoint(scene, dloss_dimage_dev, grad_offset_dev, grad_scalars_dev, s0, s1 - s0,
                                 reinterpret_cast<hipStream_t>(stream));
 }

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const 
         src.spp = B.spp;
         const AdjointIo io{};
         GradAcc acc{0.0f, 0.0f, 0.0f};
-        run_scheduled<false, false>(B.S, src, paths, st, io, acc);
+        run_scheduled<false, false, -1>(B.S, src, paths, st, io, acc);
     }
 }
 

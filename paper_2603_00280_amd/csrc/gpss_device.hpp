@@ -42,6 +42,7 @@ struct SceneDev {
     float var_scale[3];
     float lengthscale;
     float aniso_k;                // (l / l_n)^2 - 1 for lengthscale l_n along the mean gradient; 0: isotropic
+    int ggx;                      // GGX height-field macrofacet instead of the generalized one
     float albedo;
     int albedo_per_prim;
     float lo[3], hi[3];
@@ -278,6 +279,7 @@ struct PointQ {
     float s;
     float ak;
     float albedo;
+    int ggx;        // GGX height-field macrofacet (scene-wide)
 };
 
 __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
@@ -298,6 +300,7 @@ __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
     q.sigma = sqrtf(var);
     q.s = q.sigma / S.lengthscale;
     q.ak = S.aniso_k;
+    q.ggx = S.ggx;
     q.albedo = (S.albedo_per_prim && which >= 0) ? S.prims[2 * which + 1].w : S.albedo;
     return q;
 }
@@ -361,8 +364,43 @@ __device__ __forceinline__ float ndf(float3 G, float s, float ak, float3 wm) {
     return pre * fmaxf(eG * b + up, 0.0f);
 }
 
+// GGX height-field macrofacet (any NDF may replace Beckmann under the Smith assumption, end
+// of Sec. 4.1), about n = G/|G| with roughness alpha = sqrt(2) s / |G|, scaled by |G|:
+//   sigma(d) = |G| (c + sqrt(c^2 + alpha^2 (1 - c^2))) / 2, c = -d.n of either sign
+//            = (-m + sqrt(m^2 + 2 s^2 (1 - c^2))) / 2, m = d.G
+// (cos (1 + Lambda) entering from above, |cos| Lambda from below, Lambda the GGX Smith
+// function), and D(wm) = |G| alpha^2 / (pi ((n.wm)^2 (alpha^2 - 1) + 1)^2) for n.wm > 0.
+__device__ __forceinline__ float sigma_proj_ggx(float3 G, float s, float3 d) {
+    const float g2 = dot(G, G);
+    if (!(g2 > 0.0f)) return 0.0f;
+    const float m = dot(d, G);
+    const float3 cr = cross(G, d);
+    const float e = 2.0f * s * s * dot(cr, cr) / g2;   // 2 s^2 sin^2, sin from |G x d|
+    const float r = sqrtf(m * m + e);
+    // (-m + r) / 2, rationalized where it would cancel (rays leaving the surface, m > 0)
+    return m > 0.0f ? 0.5f * e / (m + r) : 0.5f * (r - m);
+}
+__device__ __forceinline__ float ndf_ggx(float3 G, float s, float3 wm) {
+    const float g2 = dot(G, G);
+    if (!(g2 > 0.0f)) return 0.0f;
+    const float ign = rsqrtf(g2);
+    const float c = dot(wm, G) * ign;
+    if (!(c > 0.0f)) return 0.0f;
+    const float a2 = 2.0f * s * s / g2;
+    const float den = c * c * (a2 - 1.0f) + 1.0f;
+    return (1.0f / ign) * a2 / (kPi * den * den);
+}
+
+// The medium's projected area and NDF at a point (generalized or GGX macrofacet).
+__device__ __forceinline__ float sigma_proj_at(const PointQ& q, float3 d) {
+    return q.ggx ? sigma_proj_ggx(q.G, q.s, d) : sigma_proj(q.G, q.s, q.ak, d);
+}
+__device__ __forceinline__ float ndf_at(const PointQ& q, float3 wm) {
+    return q.ggx ? ndf_ggx(q.G, q.s, wm) : ndf(q.G, q.s, q.ak, wm);
+}
+
 __device__ __forceinline__ float sigma_t_of(const PointQ& q, float3 d) {
-    return rho_of(q.mu, q.sigma) * sigma_proj(q.G, q.s, q.ak, d);
+    return rho_of(q.mu, q.sigma) * sigma_proj_at(q, d);
 }
 
 // Conductor phase function with F = albedo for travel direction d, scattered direction wi.
@@ -371,7 +409,7 @@ __device__ __forceinline__ float phase_eval(const PointQ& q, float3 d, float3 wi
     const float hn = sqrtf(dot(h, h));
     if (hn < 1e-7f) return 0.0f;
     h = (1.0f / hn) * h;
-    return q.albedo * ndf(q.G, q.s, q.ak, h) / (4.0f * sigma_proj(q.G, q.s, q.ak, d));
+    return q.albedo * ndf_at(q, h) / (4.0f * sigma_proj_at(q, d));
 }
 
 // ---------------------------------------------------------------------------
@@ -382,12 +420,14 @@ struct Proposal {
     float3 N, T, B;
     float alpha, cosv, a;   // a = cot(theta_v) after stretching to unit roughness
     float Reff;
-    bool beck;
+    bool beck;              // visible-normal component available (Beckmann, or GGX for a GGX macrofacet)
+    bool ggx;
 };
 
 __device__ __forceinline__ Proposal make_proposal(const PointQ& q, float R, float3 v) {
     Proposal p;
     p.beck = false;
+    p.ggx = q.ggx != 0;
     p.Reff = 0.0f;
     const float g2 = dot(q.G, q.G);
     if (g2 > 0.0f) {
@@ -423,7 +463,16 @@ __device__ __forceinline__ float mixture_pdf(const Proposal& p, float3 v, float3
     const float vm = dot(v, wm);
     if (vm <= 0.0f) return 0.0f;
     float pb = 0.0f;
-    if (p.beck) {
+    if (p.beck && p.ggx) {   // GGX visible normals: <v, wm> D(wm) / (cos_v (1 + Lambda(v)))
+        const float cm = dot(wm, p.N);
+        if (cm > 0.0f) {
+            const float a2 = p.alpha * p.alpha;
+            const float den = cm * cm * (a2 - 1.0f) + 1.0f;
+            const float D = a2 / (kPi * den * den);
+            const float lc = 0.5f * (p.cosv + sqrtf(p.cosv * p.cosv + a2 * (1.0f - p.cosv * p.cosv)));
+            pb = vm * D / lc;
+        }
+    } else if (p.beck) {
         const float cm = dot(wm, p.N);
         if (cm > 0.0f) {
             const float3 cr = cross(wm, p.N);
@@ -465,6 +514,30 @@ __device__ __forceinline__ float sample_slope_x(float a, float u) {
 __device__ __forceinline__ float3 sample_half_vector(const Proposal& p, float3 v, float usel, uint32_t ua24,
                                                      uint32_t ub24) {
     const float ua = (float)ua24 * 0x1p-24f, ub = (float)ub24 * 0x1p-24f;
+    if (usel < p.Reff && p.ggx) {
+        // GGX visible normals (Heitz 2018): stretch v to unit roughness, sample the projected
+        // hemisphere as a disk whose far half is foreshortened, lift and unstretch.
+        const float vx = dot(v, p.T), vy = dot(v, p.B);
+        float3 h = f3(p.alpha * vx, p.alpha * vy, p.cosv);
+        h = normalize(h);
+        const float l2 = h.x * h.x + h.y * h.y;
+        float3 t1 = f3(1.0f, 0.0f, 0.0f);
+        if (l2 > 0.0f) {
+            const float il = rsqrtf(l2);
+            t1 = f3(-h.y * il, h.x * il, 0.0f);
+        }
+        const float3 t2 = cross(h, t1);
+        const float r = sqrtf(ua);
+        float sp, cp;
+        sincosf(2.0f * kPi * ub, &sp, &cp);
+        const float a1 = r * cp;
+        const float sh = 0.5f * (1.0f + h.z);
+        const float a2 = (1.0f - sh) * sqrtf(fmaxf(0.0f, 1.0f - a1 * a1)) + sh * (r * sp);
+        const float a3 = sqrtf(fmaxf(0.0f, 1.0f - a1 * a1 - a2 * a2));
+        const float3 m = a1 * t1 + a2 * t2 + a3 * h;
+        const float3 e = normalize(f3(p.alpha * m.x, p.alpha * m.y, fmaxf(0.0f, m.z)));
+        return e.x * p.T + e.y * p.B + e.z * p.N;
+    }
     if (usel < p.Reff) {
         const float xs = sample_slope_x(p.a, ua);
         // (2 k + 1) / 2^24 - 1, exact in float

@@ -28,6 +28,7 @@ struct MajArgs {
     int var_res[3];
     float variance;
     float lengthscale;
+    int ggx;
     float lo[3], hi[3];
     int M[3];
 };
@@ -132,10 +133,16 @@ __global__ void majorant_kernel(MajArgs A, float* __restrict__ out) {
     const double s_max = smax / (double)A.lengthscale;
     const double zr = mu_min / (mu_min > 0.0 ? smax : smin);
     const double rho_max = sqrt(2.0 / 3.14159265358979323846) / erfcx(-zr / 1.41421356237309504880) / smin;
-    const double z = gmax / s_max;
-    const double Phi = 0.5 * erfc(-z / 1.41421356237309504880);
-    const double phi = exp(-0.5 * z * z) / 2.50662827463100050242;
-    out[cell] = (float)quantize_majorant(rho_max * (gmax * Phi + s_max * phi));
+    double proj_max;
+    if (A.ggx) {   // GGX height field: sigma <= (|G| + sqrt(|G|^2 + 2 s^2)) / 2
+        proj_max = 0.5 * (gmax + sqrt(gmax * gmax + 2.0 * s_max * s_max));
+    } else {
+        const double z = gmax / s_max;
+        const double Phi = 0.5 * erfc(-z / 1.41421356237309504880);
+        const double phi = exp(-0.5 * z * z) / 2.50662827463100050242;
+        proj_max = gmax * Phi + s_max * phi;
+    }
+    out[cell] = (float)quantize_majorant(rho_max * proj_max);
 }
 
 int launch_majorants(gpss_scene* s, hipStream_t stream) {
@@ -157,6 +164,7 @@ int launch_majorants(gpss_scene* s, hipStream_t stream) {
     A.variance = D.variance;
     // the largest gradient standard deviation: sigma over the smaller of the two lengthscales
     A.lengthscale = D.lengthscale_n > 0.0f ? fminf(D.lengthscale, D.lengthscale_n) : D.lengthscale;
+    A.ggx = D.ndf_kind == GPSS_NDF_GGX;
     const int n = A.M[0] * A.M[1] * A.M[2];
     hipLaunchKernelGGL(majorant_kernel, dim3((n + 127) / 128), dim3(128), 0, stream, A, s->d_maj);
     return check_hip(hipGetLastError(), "majorant_kernel launch");
@@ -270,7 +278,7 @@ __global__ void eval_kernel(SceneDev S, const float* __restrict__ pts, const flo
     const float3 d = f3(dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]);
     const PointQ q = eval_point(S, x);
     const float r = rho_of(q.mu, q.sigma);
-    const float sp = sigma_proj(q.G, q.s, q.ak, d);
+    const float sp = sigma_proj_at(q, d);
     float* o = out + 8 * i;
     o[0] = q.mu;
     o[1] = q.sigma;
@@ -278,7 +286,7 @@ __global__ void eval_kernel(SceneDev S, const float* __restrict__ pts, const flo
     o[3] = r;
     o[4] = sp;
     o[5] = r * sp;
-    o[6] = ndf(q.G, q.s, q.ak, d);
+    o[6] = ndf_at(q, d);
     o[7] = q.albedo;
 }
 

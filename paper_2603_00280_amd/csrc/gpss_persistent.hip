@@ -26,7 +26,7 @@ __global__ void sched_reset_kernel(uint32_t* head) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *head = 0u;
 }
 
-template <bool STATS>
+template <bool STATS, int NDFK>
 __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_render_kernel(
     const SceneDev* __restrict__ Sp, float* __restrict__ paths, uint32_t* head, unsigned long long* counters,
     uint32_t s0, uint32_t ns, uint32_t npaths) {
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_render_kernel
     src.ns = ns;
     const AdjointIo io{};
     GradAcc acc{0.0f, 0.0f, 0.0f};
-    run_scheduled<STATS, false>(S, src, paths, st, io, acc);
+    run_scheduled<STATS, false, NDFK>(S, src, paths, st, io, acc);
     flush_stats_sched<STATS>(st, counters);
 }
 
@@ -54,11 +54,19 @@ int sched_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, u
     hipLaunchKernelGGL(sched_reset_kernel, dim3(1), dim3(64), 0, stream, s->d_head);
     const dim3 blk(256);
     const dim3 grid(s->sched_grid);
-    if (counters)
-        hipLaunchKernelGGL(sched_render_kernel<true>, grid, blk, 0, stream, s->d_dev, paths, s->d_head,
-                           reinterpret_cast<unsigned long long*>(counters), s0, ns, (uint32_t)npaths);
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
+    const bool ggx = s->dev.ggx != 0;
+    if (counters && ggx)
+        hipLaunchKernelGGL((sched_render_kernel<true, 1>), grid, blk, 0, stream, s->d_dev, paths, s->d_head, cnt, s0,
+                           ns, (uint32_t)npaths);
+    else if (counters)
+        hipLaunchKernelGGL((sched_render_kernel<true, 0>), grid, blk, 0, stream, s->d_dev, paths, s->d_head, cnt, s0,
+                           ns, (uint32_t)npaths);
+    else if (ggx)
+        hipLaunchKernelGGL((sched_render_kernel<false, 1>), grid, blk, 0, stream, s->d_dev, paths, s->d_head, nullptr,
+                           s0, ns, (uint32_t)npaths);
     else
-        hipLaunchKernelGGL(sched_render_kernel<false>, grid, blk, 0, stream, s->d_dev, paths, s->d_head, nullptr,
+        hipLaunchKernelGGL((sched_render_kernel<false, 0>), grid, blk, 0, stream, s->d_dev, paths, s->d_head, nullptr,
                            s0, ns, (uint32_t)npaths);
     return check_hip(hipGetLastError(), "sched_render_kernel launch");
 }

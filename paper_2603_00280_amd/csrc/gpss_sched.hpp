@@ -83,7 +83,9 @@ struct AdjointIo {
 // (frozen-sampling estimator; the terms are those of the one-thread replay in
 // gpss_adjoint.hip) into io.grad_off and acc.  Must be called by whole waves; returns when
 // the source is exhausted and every lane's path has ended.
-template <bool STATS, bool ADJ, class Source>
+// NDFK: the scene's NDF kind when the kernel is specialized for it (0 generalized, 1 GGX), so
+// that the other kind's code is not compiled in; -1 takes it from the scene record.
+template <bool STATS, bool ADJ, int NDFK, class Source>
 __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, float* __restrict__ paths,
                                               PathStats& st, const AdjointIo& io, GradAcc& acc) {
     // Cold per-lane state (touched once per segment or vertex) lives in LDS, one column per
@@ -108,6 +110,11 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
     Segment sg;
     sg.o = d3(0.0, 0.0, 0.0);
     Rng rng;
+    auto point = [&](float3 x) {   // medium statistics at x, with the specialized NDF kind
+        PointQ q = eval_point(S, x);
+        if (NDFK >= 0) q.ggx = NDFK;
+        return q;
+    };
     auto finish = [&](float L) {   // the path's radiance to its output slot; the lane falls idle
         if (!ADJ) paths[cs_u[kSlot][lt]] = L;
         op = kOpIdle;
@@ -169,7 +176,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 const D3 d = sg.d;
                 const float3 df = to_f3(d);
                 const float3 xf = to_f3(x);
-                const PointQ q = eval_point(S, xf);
+                const PointQ q = point(xf);
                 const float beta = cs_f[kBeta][lt];
                 flags = 0;
 #pragma unroll
@@ -233,7 +240,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                         flags &= ~kVertex;
                         const float Lafter = cs_f[kL][lt] - cs_f[kEtot][lt];
                         if (Lafter != 0.0f) {
-                            const PointQ q = eval_point(S, to_f3(sg.o));
+                            const PointQ q = point(to_f3(sg.o));
                             const float3 wm = f3(cs_f[kWm][lt], cs_f[kWm + 1][lt], cs_f[kWm + 2][lt]);
                             float3 dG;
                             float ds;
@@ -293,7 +300,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 if (!capped && mode == 0) u2 = rng.uniform();
                 const float3 xf = sg.pos();
                 const float3 df = to_f3(sg.d);   // single-precision travel direction
-                const PointQ q = eval_point(S, xf);
+                const PointQ q = point(xf);
                 const float sig = sigma_t_of(q, df);
                 if (capped) {
                     if (STATS) st.capped++;
@@ -385,7 +392,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 float ds;
                 if (hn >= 1e-7f) {
                     const float3 xf = to_f3(sg.o);
-                    const PointQ q = eval_point(S, xf);
+                    const PointQ q = point(xf);
                     if (dlog_ndf(q.G, q.s, (1.0f / hn) * h, dG, ds)) {
                         const float c = cs_f[kWpix][lt] * cs_f[kE][lt];
                         scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc);

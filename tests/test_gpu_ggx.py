@@ -1,0 +1,105 @@
+"""GPU parity of the GGX height-field macrofacet (GGX NDF and Smith Lambda about the mean
+gradient; end of Sec. 4.1, Fig. cmp_ggx) with the FP64 oracle, through the C-ABI."""
+import numpy as np
+import pytest
+
+from gpss_inputs import scenes as sc
+from oracle import oracle as orc
+from tests import gpu_helpers as gh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_00280_amd import gpss
+    return gpss
+
+
+def _small(alpha, **kw):
+    return sc.ggx_sphere_scene(alpha, **{**dict(width=64, height=64, spp=8), **kw})
+
+
+def _plane():
+    return sc.plane_scene().replace(ndf_kind=sc.NDF_GGX, name="plane_ggx")
+
+
+def test_ggx_majorants_match_oracle_bitwise(G):
+    for s in (_small(0.1), _small(1.0), _plane()):
+        print(f"[ggx] majorants {s.name}", flush=True)
+        a = G.GpssScene(s).majorants()
+        b = orc.OracleScene(s).majorants()
+        assert np.array_equal(a.view(np.uint32), b.astype(np.float32).view(np.uint32))
+
+
+def test_ggx_medium_matches_oracle(G):
+    rng = np.random.default_rng(5)
+    for s in (_small(0.1), _small(1.0), _plane()):
+        n = 3000
+        lo, hi = s.bounds[:3], s.bounds[3:]
+        pts = (lo + rng.random((n, 3)) * (hi - lo)).astype(np.float32)
+        dirs = rng.normal(size=(n, 3))
+        dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+        print(f"[ggx] medium {s.name} n={n}", flush=True)
+        out = G.GpssScene(s).eval_medium(pts, dirs).cpu().numpy().astype(np.float64)
+        o = orc.OracleScene(s)
+        worst = {}
+        for i in range(n):
+            x, d = pts[i].astype(np.float64), dirs[i].astype(np.float64)
+            e = o.eval_point(x)
+            sp = orc.sigma_proj_ggx(e["G"], e["s"], d)
+            D = orc.ndf_ggx(e["G"], e["s"], d)
+            st = o.sigma_t(x, d)
+            for name, gv, ov in (("proj", out[i, 4], sp), ("sigma_t", out[i, 5], st), ("ndf", out[i, 6], D)):
+                err = abs(gv - ov) / max(abs(ov), 1e-6)
+                worst[name] = max(worst.get(name, 0.0), err)
+        print("   ", {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+        assert worst["proj"] < 1e-4 and worst["sigma_t"] < 1e-4 and worst["ndf"] < 1e-4
+
+
+@pytest.mark.parametrize("alpha", sc.GGX_ALPHAS)
+def test_ggx_sphere_parity(G, alpha):
+    s = _small(alpha)
+    print(f"[ggx] parity {s.name} {s.width}x{s.height} spp {s.spp}", flush=True)
+    img = G.GpssScene(s).render().cpu().numpy()
+    ref = orc.OracleScene(s).render()
+    st = gh.compare_images(img, ref, s.spp, s.name)
+    print("   ", gh.fmt(st), flush=True)
+    assert ref["counters"]["violations"] == 0
+    gh.assert_parity(st)
+
+
+def test_ggx_plane_parity(G):
+    s = _plane()
+    print(f"[ggx] parity {s.name}", flush=True)
+    img = G.GpssScene(s).render().cpu().numpy()
+    ref = orc.OracleScene(s).render()
+    st = gh.compare_images(img, ref, s.spp, s.name)
+    print("   ", gh.fmt(st), flush=True)
+    gh.assert_parity(st)
+
+
+def test_ggx_full_size_sampled(G):
+    """512^2, 64 spp, depth 32 at alpha = 0.5: the GPU image at 400 oracle-traced pixels."""
+    s = sc.ggx_sphere_scene(0.5)
+    rng = np.random.default_rng(8)
+    px = np.sort(rng.choice(s.n_pixels, 400, replace=False)).astype(np.int64)
+    print(f"[ggx] full size {s.name} {s.width}x{s.height} spp {s.spp}", flush=True)
+    img = G.GpssScene(s).render().cpu().numpy().ravel()
+    ref = orc.OracleScene(s).render_pixels(px)
+    st = gh.compare_sampled(img[px], ref, s.spp, s.name)
+    print("   ", st, flush=True)
+    gh.assert_sampled_parity(st)
+
+
+def test_ggx_rejections(G):
+    with pytest.raises(G.GpssError):   # constant mean: no macro-surface normal
+        G.GpssScene(sc.plane_scene().replace(ndf_kind=sc.NDF_GGX, mean_kind=sc.MEAN_CONST))
+    s = _small(0.5)
+    g = G.GpssScene(s)
+    with pytest.raises(G.GpssError):   # the adjoint is the generalized macrofacet's
+        g.render_adjoint(torch.zeros(s.height, s.width, dtype=torch.float32))

@@ -28,6 +28,7 @@ CASES = {
     "furnace": lambda: sc.plane_scene(width=16, height=16, spp=8, max_depth=40, albedo=1.0,
                                       env=1.0, light_E=0.0),
     "aniso_sphere": lambda: sc.aniso_sphere_scene(0.01, width=48, height=48, spp=4),
+    "ggx_sphere": lambda: sc.ggx_sphere_scene(0.3, width=48, height=48, spp=4),
 }
 
 
