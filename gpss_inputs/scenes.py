@@ -71,6 +71,8 @@ class Scene:
     scene_id: int = 0
     lengthscale_n: float = 0.0             # lengthscale along the local mean-gradient direction (0: isotropic)
     ndf_kind: int = 0                      # NDF_GENERALIZED (Eq. macro_ndf) or NDF_GGX (height field)
+    fresnel_eta: float = 0.0               # conductor IOR eta + i k of the Fresnel term (eta = 0: F = albedo)
+    fresnel_k: float = 0.0
 
     @property
     def n_pixels(self) -> int:
@@ -177,6 +179,25 @@ def ggx_sphere_scene(alpha: float = 0.5, variance: float = 1e-4, **kw) -> Scene:
     sigma = float(np.sqrt(np.float32(variance)))
     s = sphere_scene(lengthscale=float(np.sqrt(2.0) * sigma / alpha), variance=variance, **kw)
     return s.replace(name=f"ggx_sphere_a{alpha:g}", ndf_kind=NDF_GGX)
+
+
+# ---------------------------------------------------------------------------
+# Conductor Fresnel (the F of Eq. phase with a complex index of refraction), one channel per
+# scene; an RGB image is three scenes (rendered together with gpss_render_batch).  Indices
+# of refraction at about 650, 550 and 450 nm (eta, k per channel; approximate handbook values).
+# ---------------------------------------------------------------------------
+METAL_IOR = {
+    "gold": ((0.18, 0.42, 1.37), (3.42, 2.35, 1.77)),
+    "copper": ((0.27, 0.68, 1.22), (3.61, 2.63, 2.29)),
+}
+
+
+def fresnel_rgb_scenes(scene: Scene, metal: str = "gold") -> list:
+    """The scene once per color channel with that channel's conductor IOR (albedo 1)."""
+    etas, ks = METAL_IOR[metal]
+    return [scene.replace(name=f"{scene.name}_{metal}_{c}", fresnel_eta=float(e), fresnel_k=float(k), albedo=1.0,
+                          scene_id=scene.scene_id + i)
+            for i, (c, e, k) in enumerate(zip("rgb", etas, ks))]
 
 
 # ---------------------------------------------------------------------------

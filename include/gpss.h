@@ -97,6 +97,9 @@ typedef struct {
      * Sec. 4.1, Fig. cmp_ggx).  GGX needs a mean with a gradient (not GPSS_MEAN_CONST) and
      * the isotropic kernel. */
     int32_t ndf_kind;
+    /* conductor Fresnel term (Eq. phase): index of refraction eta + i k of the microflakes;
+     * F = albedo x Fresnel reflectance at the half vector.  eta = 0: F = albedo. */
+    float fresnel_eta, fresnel_k;
 } gpss_scene_desc;
 
 /* Create a scene: validates `desc`, uploads primitives and grids, and builds the

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <unordered_map>
 #include <vector>
@@ -42,6 +43,7 @@ struct oracle_scene {
     double l_n;            // lengthscale along the local mean-gradient direction (= l: isotropic)
     bool aniso;            // l_n != l
     bool ggx;              // GGX height-field macrofacet (NDF and Lambda of GGX) instead of Eq. macro_ndf
+    double f_eta, f_k;     // conductor index of refraction eta + i k of the Fresnel term (eta = 0: F = albedo)
     bool albedo_per_prim;
     double lo[3], hi[3], ext[3];
     double R;
@@ -189,6 +191,7 @@ struct PointQ {
     T sn;      // gradient standard deviation along n: sigma / l_n
     T albedo;
     bool ggx = false;   // GGX height-field macrofacet
+    double f_eta = 0.0, f_k = 0.0;   // conductor Fresnel (eta = 0: none)
 };
 
 template <class T>
@@ -239,6 +242,8 @@ PointQ<T> eval_point(const Params<T>& P, const double x[3]) {
     q.s = q.sigma / mk<T>(S.l, P.slot_l);
     q.sn = S.aniso ? q.sigma / T(S.l_n) : q.s;
     q.ggx = S.ggx;
+    q.f_eta = S.f_eta;
+    q.f_k = S.f_k;
     if (S.albedo_per_prim && which >= 0) q.albedo = T(S.prims[which].albedo);
     else q.albedo = mk<T>(S.albedo, P.slot_alb);
     return q;
@@ -795,13 +800,36 @@ void camera_ray(const Scene& S, uint32_t pixel, double ux, double uy, double o[3
 // Conductor phase function (Eqs. phase and microfacet_vndf) with F = albedo, for travel
 // direction d and scattered direction wi: albedo * D(wm) / (4 sigma_proj(d)), wm the half
 // vector of v = -d and wi.
+// Fresnel reflectance of a conductor with index of refraction n = eta + i k at incidence
+// cosine c (the F of Eq. phase), from the Fresnel equations with complex amplitudes:
+// w = n cos(theta_t) = sqrt(n^2 - sin^2), r_s = (c - w)/(c + w), r_p = (n^2 c - w)/(n^2 c + w),
+// unpolarized F = (|r_s|^2 + |r_p|^2) / 2.
+double fresnel_conductor(double c, double eta, double k) {
+    c = std::min(std::max(c, 0.0), 1.0);
+    const std::complex<double> n(eta, k);
+    const std::complex<double> n2 = n * n;
+    const std::complex<double> w = std::sqrt(n2 - (1.0 - c * c));
+    const std::complex<double> rs = (c - w) / (c + w);
+    const std::complex<double> rp = (n2 * c - w) / (n2 * c + w);
+    return 0.5 * (std::norm(rs) + std::norm(rp));
+}
+
+// F(-w_o, w_m) of Eq. phase: the albedo, times the conductor Fresnel reflectance at the
+// microflake when an index of refraction is given.
+template <class T>
+T fresnel_F(const PointQ<T>& q, double cos_d) {
+    if (!(q.f_eta > 0.0)) return q.albedo;
+    return q.albedo * fresnel_conductor(cos_d, q.f_eta, q.f_k);
+}
+
 template <class T>
 T phase_eval(const PointQ<T>& q, const double d[3], const double wi[3]) {
     double h[3] = {wi[0] - d[0], wi[1] - d[1], wi[2] - d[2]};
     const double hn = std::sqrt(dot3(h, h));
     if (hn < 1e-7) return T(0.0);
     h[0] /= hn; h[1] /= hn; h[2] /= hn;
-    return q.albedo * ndf(q, h) / (4.0 * sigma_proj(q, d));
+    const double cos_d = -dot3(d, h);   // <v, w_h>, v = -d
+    return fresnel_F(q, cos_d) * ndf(q, h) / (4.0 * sigma_proj(q, d));
 }
 
 // One light path; returns its radiance estimate.
@@ -900,8 +928,8 @@ T trace_path(const Params<double>& P0, const Params<T>& P1, bool frozen, uint32_
         normalize3(wi);
         // beta *= albedo * D_{w_o}(wm) / pdf, D_{w_o}(wm) = <v, wm> D(wm) / sigma_proj(d)
         T wgt;
-        if (frozen) wgt = q1.albedo * vm * ndf(q1, wm) / (sigma_proj(q1, d) * pdf);
-        else wgt = T(q0.albedo * vm * ndf(q0, wm) / (sigma_proj(q0, d) * pdf));
+        if (frozen) wgt = fresnel_F(q1, vm) * vm * ndf(q1, wm) / (sigma_proj(q1, d) * pdf);
+        else wgt = T(fresnel_F(q0, vm) * vm * ndf(q0, wm) / (sigma_proj(q0, d) * pdf));
         beta = beta * wgt;
         if (r) {
             r[9] = wm[0]; r[10] = wm[1]; r[11] = wm[2]; r[12] = pdf; r[13] = val(wgt);
@@ -932,6 +960,7 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
     if (!(D->lengthscale_n >= 0.0)) return -1;
     if (D->ndf_kind != 0 && D->ndf_kind != 1) return -1;
     if (D->ndf_kind == 1 && D->mean_kind == 2) return -1;   // GGX needs a macro-surface normal
+    if (!(D->fresnel_eta >= 0.0) || !(D->fresnel_k >= 0.0)) return -1;
     if (!D->var_grid && !(D->variance > 0.0)) return -1;
     for (int a = 0; a < 3; ++a) {
         if (!(D->bounds[3 + a] > D->bounds[a])) return -1;
@@ -964,6 +993,8 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
     S->l_n = D->lengthscale_n > 0.0 ? D->lengthscale_n : D->lengthscale;
     S->aniso = S->l_n != S->l;
     S->ggx = D->ndf_kind == 1;
+    S->f_eta = D->fresnel_eta;
+    S->f_k = D->fresnel_k;
     S->albedo = D->albedo;
     S->albedo_per_prim = D->albedo_per_prim != 0;
     for (int a = 0; a < 3; ++a) {
@@ -1147,6 +1178,7 @@ void oracle_uniforms(uint64_t seed, uint32_t scene_id, uint32_t pixel, uint32_t 
 }
 
 double oracle_erfcx(double x) { return erfcx_d(x); }
+double oracle_fresnel_conductor(double c, double eta, double k) { return fresnel_conductor(c, eta, k); }
 double oracle_erfinv(double y) { return erfinv_d(y); }
 double oracle_rho(double mu, double sigma) { return rho_of(mu, sigma); }
 
@@ -1203,7 +1235,7 @@ static int phase_sample_k(const double G[3], double s, double albedo, double R, 
     const double vm = dot3(v, wm);
     for (int k = 0; k < 3; ++k) wi[k] = 2.0 * vm * wm[k] - v[k];
     normalize3(wi);
-    *weight = albedo * vm * ndf(q, wm) / (sigma_proj(q, d) * *pdf);
+    *weight = fresnel_F(q, vm) * vm * ndf(q, wm) / (sigma_proj(q, d) * *pdf);
     return 0;
 }
 double oracle_phase_eval(const double G[3], double s, double albedo, const double d[3], const double wi[3]) {
@@ -1239,6 +1271,10 @@ int oracle_eval_point(const oracle_scene* sc, const double x[3], double out[8]) 
     out[0] = q.mu; out[1] = q.G[0]; out[2] = q.G[1]; out[3] = q.G[2];
     out[4] = q.sigma; out[5] = q.s; out[6] = q.albedo; out[7] = q.sn;
     return 0;
+}
+
+double oracle_phase_eval_at(const oracle_scene* sc, const double x[3], const double d[3], const double wi[3]) {
+    return phase_eval(eval_point(plain_params(sc), x), d, wi);
 }
 
 double oracle_sigma_t(const oracle_scene* sc, const double x[3], const double d[3]) {

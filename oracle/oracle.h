@@ -59,6 +59,7 @@ typedef struct {
     uint32_t scene_id;
     double lengthscale_n;       /* lengthscale along the local mean-gradient direction (0: = lengthscale) */
     int32_t ndf_kind;           /* 0: generalized macrofacet (Eq. macro_ndf); 1: GGX height field */
+    double fresnel_eta, fresnel_k;  /* conductor IOR eta + i k of the Fresnel term; eta = 0: F = albedo */
 } oracle_scene_desc;
 
 typedef struct oracle_scene oracle_scene;
@@ -141,6 +142,8 @@ double oracle_mixture_pdf(const double G[3], double s, double R, const double d[
 int oracle_phase_sample(const double G[3], double s, double albedo, double R,
                         const double d[3], const double u[3], double* wi, double* wm,
                         double* weight, double* pdf);
+/* unpolarized Fresnel reflectance of a conductor (IOR eta + i k) at incidence cosine c */
+double oracle_fresnel_conductor(double c, double eta, double k);
 /* the same for the GGX height-field macrofacet (NDF kind 1) */
 double oracle_sigma_proj_ggx(const double G[3], double s, const double d[3]);
 double oracle_ndf_ggx(const double G[3], double s, const double wm[3]);
@@ -151,6 +154,8 @@ int oracle_phase_sample_ggx(const double G[3], double s, double albedo, double R
 /* mu, G[3], sigma, s (across n), albedo, s_n (along n) at a point */
 int oracle_eval_point(const oracle_scene* sc, const double x[3], double out[8]);
 double oracle_sigma_t(const oracle_scene* sc, const double x[3], const double d[3]);
+/* phase function of the scene's medium at x for travel direction d, scattered direction wi */
+double oracle_phase_eval_at(const oracle_scene* sc, const double x[3], const double d[3], const double wi[3]);
 /* ratio-tracking transmittance estimates of n independent streams (pixel index = i) */
 int oracle_ratio_tracking(const oracle_scene* sc, const double o[3], const double d[3],
                           double tmax, int32_t n, double* out_T);

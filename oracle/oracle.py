@@ -37,7 +37,7 @@ class _Desc(C.Structure):
         ("up", C.c_double * 3), ("fov_deg", C.c_double), ("window", C.c_double * 2),
         ("width", C.c_int32), ("height", C.c_int32), ("spp", C.c_int32), ("max_depth", C.c_int32),
         ("seed", C.c_uint64), ("scene_id", C.c_uint32), ("lengthscale_n", C.c_double),
-        ("ndf_kind", C.c_int32),
+        ("ndf_kind", C.c_int32), ("fresnel_eta", C.c_double), ("fresnel_k", C.c_double),
     ]
 
 
@@ -89,6 +89,10 @@ def lib():
             getattr(L, "oracle_phase_eval" + sfx).restype = C.c_double
             getattr(L, "oracle_mixture_pdf" + sfx).argtypes = [dp, C.c_double, C.c_double, dp, dp]
             getattr(L, "oracle_mixture_pdf" + sfx).restype = C.c_double
+        L.oracle_phase_eval_at.argtypes = [C.c_void_p, dp, dp, dp]
+        L.oracle_phase_eval_at.restype = C.c_double
+        L.oracle_fresnel_conductor.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.oracle_fresnel_conductor.restype = C.c_double
         for name in ("oracle_sigma_proj_ggx", "oracle_ndf_ggx"):
             getattr(L, name).argtypes = [dp, C.c_double, dp]
             getattr(L, name).restype = C.c_double
@@ -162,6 +166,8 @@ class OracleScene:
         d.scene_id = int(s.scene_id)
         d.lengthscale_n = f32(s.lengthscale_n)
         d.ndf_kind = int(s.ndf_kind)
+        d.fresnel_eta = f32(s.fresnel_eta)
+        d.fresnel_k = f32(s.fresnel_k)
         self._desc = d
         h = C.c_void_p()
         rc = lib().oracle_scene_create(C.byref(d), C.byref(h))
@@ -259,6 +265,9 @@ class OracleScene:
         return {"mu": out[0], "G": out[1:4].copy(), "sigma": out[4], "s": out[5],
                 "albedo": out[6], "sn": out[7]}
 
+    def phase_eval_at(self, x, d, wi) -> float:
+        return lib().oracle_phase_eval_at(self.handle, _dp(_vec(x)), _dp(_vec(d)), _dp(_vec(wi)))
+
     def sigma_t(self, x, d) -> float:
         return lib().oracle_sigma_t(self.handle, _dp(_vec(x)), _dp(_vec(d)))
 
@@ -353,6 +362,10 @@ def phase_sample(G, s, albedo, R, d, u, ggx: bool = False):
     f(_dp(_vec(G)), float(s), float(albedo), float(R), _dp(_vec(d)), _dp(_vec(u)), _dp(wi), _dp(wm),
       _dp(w), _dp(p))
     return wi, wm, float(w[0]), float(p[0])
+
+
+def fresnel_conductor(c: float, eta: float, k: float) -> float:
+    return lib().oracle_fresnel_conductor(float(c), float(eta), float(k))
 
 
 def sigma_proj_ggx(G, s: float, d) -> float:

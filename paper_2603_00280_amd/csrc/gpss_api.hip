@@ -187,6 +187,9 @@ int validate_desc(const gpss_scene_desc* D) {
         return set_error(GPSS_ERR_INVALID_ARG, "lengthscale must be > 0");
     if (!(D->lengthscale_n >= 0.0f) || !std::isfinite(D->lengthscale_n))
         return set_error(GPSS_ERR_INVALID_ARG, "lengthscale_n must be >= 0 (0: isotropic)");
+    if (!(D->fresnel_eta >= 0.0f) || !(D->fresnel_k >= 0.0f) || !std::isfinite(D->fresnel_eta) ||
+        !std::isfinite(D->fresnel_k))
+        return set_error(GPSS_ERR_INVALID_ARG, "fresnel_eta and fresnel_k must be finite and >= 0");
     if (D->ndf_kind != GPSS_NDF_GENERALIZED && D->ndf_kind != GPSS_NDF_GGX)
         return set_error(GPSS_ERR_INVALID_ARG, "unknown ndf_kind %d", D->ndf_kind);
     if (D->ndf_kind == GPSS_NDF_GGX && D->mean_kind == GPSS_MEAN_CONST)
@@ -264,6 +267,8 @@ void fill_dev(gpss_scene* s) {
     V.lengthscale = D.lengthscale;
     V.aniso_k = aniso_k(D);
     V.ggx = D.ndf_kind == GPSS_NDF_GGX;
+    V.f_eta = D.fresnel_eta;
+    V.f_k = D.fresnel_k;
     V.albedo = D.albedo;
     V.albedo_per_prim = D.albedo_per_prim ? 1 : 0;
     for (int a = 0; a < 3; ++a) {

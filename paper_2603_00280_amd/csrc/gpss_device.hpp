@@ -43,6 +43,7 @@ struct SceneDev {
     float lengthscale;
     float aniso_k;                // (l / l_n)^2 - 1 for lengthscale l_n along the mean gradient; 0: isotropic
     int ggx;                      // GGX height-field macrofacet instead of the generalized one
+    float f_eta, f_k;             // conductor IOR eta + i k of the Fresnel term (eta = 0: F = albedo)
     float albedo;
     int albedo_per_prim;
     float lo[3], hi[3];
@@ -280,6 +281,7 @@ struct PointQ {
     float ak;
     float albedo;
     int ggx;        // GGX height-field macrofacet (scene-wide)
+    float feta, fk; // conductor Fresnel IOR (scene-wide; feta = 0: none)
 };
 
 __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
@@ -301,6 +303,8 @@ __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
     q.s = q.sigma / S.lengthscale;
     q.ak = S.aniso_k;
     q.ggx = S.ggx;
+    q.feta = S.f_eta;
+    q.fk = S.f_k;
     q.albedo = (S.albedo_per_prim && which >= 0) ? S.prims[2 * which + 1].w : S.albedo;
     return q;
 }
@@ -403,13 +407,34 @@ __device__ __forceinline__ float sigma_t_of(const PointQ& q, float3 d) {
     return rho_of(q.mu, q.sigma) * sigma_proj_at(q, d);
 }
 
-// Conductor phase function with F = albedo for travel direction d, scattered direction wi.
+// Unpolarized Fresnel reflectance of a conductor with IOR eta + i k at incidence cosine c
+// (real form of the Fresnel equations: a^2 + b^2 = |n^2 - sin^2|, a = Re sqrt(n^2 - sin^2)).
+__device__ __forceinline__ float fresnel_conductor(float c, float eta, float k) {
+    c = fminf(fmaxf(c, 0.0f), 1.0f);
+    const float c2 = c * c, s2 = 1.0f - c2;
+    const float t0 = eta * eta - k * k - s2;
+    const float a2b2 = sqrtf(t0 * t0 + 4.0f * eta * eta * k * k);
+    const float a = sqrtf(fmaxf(0.5f * (a2b2 + t0), 0.0f));
+    const float t1 = a2b2 + c2, t2 = 2.0f * c * a;
+    const float rs = (t1 - t2) / (t1 + t2);
+    const float t3 = c2 * a2b2 + s2 * s2, t4 = t2 * s2;
+    const float rp = rs * (t3 - t4) / (t3 + t4);
+    return 0.5f * (rp + rs);
+}
+
+// F(-w_o, w_m) of Eq. phase at <v, w_m> = c: the albedo, times the conductor Fresnel
+// reflectance when an index of refraction is given.
+__device__ __forceinline__ float fresnel_F(const PointQ& q, float c) {
+    return q.feta > 0.0f ? q.albedo * fresnel_conductor(c, q.feta, q.fk) : q.albedo;
+}
+
+// Conductor phase function for travel direction d, scattered direction wi.
 __device__ __forceinline__ float phase_eval(const PointQ& q, float3 d, float3 wi) {
     float3 h = wi - d;
     const float hn = sqrtf(dot(h, h));
     if (hn < 1e-7f) return 0.0f;
     h = (1.0f / hn) * h;
-    return q.albedo * ndf_at(q, h) / (4.0f * sigma_proj_at(q, d));
+    return fresnel_F(q, -dot(d, h)) * ndf_at(q, h) / (4.0f * sigma_proj_at(q, d));
 }
 
 // ---------------------------------------------------------------------------

@@ -194,7 +194,7 @@ __device__ __forceinline__ bool sample_scatter(const SceneDev& S, const PointQ& 
     const D3 wmd = d3(wm);
     const D3 vd = -d;
     wi = normalize((2.0 * dot(vd, wmd)) * wmd - vd);
-    wgt = q.albedo * vm * ndf_at(q, wm) / (sigma_proj_at(q, df) * pdf);
+    wgt = fresnel_F(q, vm) * vm * ndf_at(q, wm) / (sigma_proj_at(q, df) * pdf);
     return true;
 }
 

@@ -55,7 +55,7 @@ class gpss_scene_desc(C.Structure):
         ("cam_up", C.c_float * 3), ("cam_fov_deg", C.c_float), ("cam_window", C.c_float * 2),
         ("width", C.c_uint32), ("height", C.c_uint32), ("spp", C.c_uint32), ("max_depth", C.c_uint32),
         ("seed", C.c_uint64), ("scene_id", C.c_uint32), ("lengthscale_n", C.c_float),
-        ("ndf_kind", C.c_int32),
+        ("ndf_kind", C.c_int32), ("fresnel_eta", C.c_float), ("fresnel_k", C.c_float),
     ]
 
 
@@ -157,6 +157,8 @@ def make_desc(scene):
     d.scene_id = int(scene.scene_id)
     d.lengthscale_n = float(getattr(scene, "lengthscale_n", 0.0))
     d.ndf_kind = int(getattr(scene, "ndf_kind", 0))
+    d.fresnel_eta = float(getattr(scene, "fresnel_eta", 0.0))
+    d.fresnel_k = float(getattr(scene, "fresnel_k", 0.0))
     return d, keep
 
 

@@ -135,3 +135,15 @@ def ggx_lambda(alpha, cos_t):
     """Textbook GGX Smith Lambda for a direction above the horizon."""
     t2 = (1.0 - cos_t * cos_t) / (cos_t * cos_t)
     return 0.5 * (-1.0 + math.sqrt(1.0 + alpha * alpha * t2))
+
+
+def fresnel_conductor_snell(c, eta, k):
+    """Unpolarized Fresnel reflectance for IOR n = eta + i k from Snell's law with complex
+    angles: cos_t = sqrt(1 - sin^2 / n^2), r_s = (c - n cos_t)/(c + n cos_t),
+    r_p = (n c - cos_t)/(n c + cos_t)."""
+    n = complex(eta, k)
+    sin2 = 1.0 - c * c
+    cos_t = np.sqrt(1.0 - sin2 / (n * n) + 0j)
+    rs = (c - n * cos_t) / (c + n * cos_t)
+    rp = (n * c - cos_t) / (n * c + cos_t)
+    return 0.5 * (abs(rs) ** 2 + abs(rp) ** 2)

@@ -632,3 +632,63 @@ def test_planar_single_scattering_ggx_surface_limit():
     inner = r["mean"][10:22, 10:22]
     se = math.sqrt(r["var"][10:22, 10:22].mean() / (s.spp * inner.size))
     assert abs(inner.mean() - want) < 5 * se
+
+
+# ---------------------------------------------------------------------------
+# Conductor Fresnel term (the F of Eq. phase with a complex index of refraction)
+# ---------------------------------------------------------------------------
+def test_fresnel_conductor_against_snell_form():
+    for eta, k in ((0.2, 3.0), (1.5, 0.0), (0.05, 4.2), (2.5, 1.1), (1.0, 0.5)):
+        for c in np.linspace(0.0, 1.0, 41):
+            want = ref.fresnel_conductor_snell(c, eta, k)
+            assert orc.fresnel_conductor(c, eta, k) == pytest.approx(want, rel=1e-12, abs=1e-15)
+        # normal incidence and grazing limits
+        assert orc.fresnel_conductor(1.0, eta, k) == pytest.approx(((eta - 1) ** 2 + k * k) / ((eta + 1) ** 2 + k * k),
+                                                                   rel=1e-12)
+        assert orc.fresnel_conductor(0.0, eta, k) == pytest.approx(1.0, rel=1e-12)
+
+
+def test_planar_single_scattering_with_fresnel():
+    """The planar depth-1 closed form with F = albedo x conductor Fresnel at the half vector
+    (gold, approximately eta = 0.2, k = 3.0 at 600 nm)."""
+    eta, k = 0.2, 3.0
+    s = sc.plane_scene(width=32, height=32, spp=256, max_depth=1).replace(fresnel_eta=eta, fresnel_k=k)
+    r = orc.OracleScene(s).render()
+    assert r["counters"]["violations"] == 0
+    sigma = math.sqrt(orc.f32(0.01))
+    s0 = sigma / orc.f32(0.05)
+    cov = np.full(3, s0 * s0)
+    G = np.array([0, 0, 1.0])
+    v = np.array([math.sin(math.pi / 4), 0, math.cos(math.pi / 4)])
+    ld = np.asarray(s.dir_light[:3], float)
+    n = (ref.projected_area_by_expectation(-v, G, cov) / v[2]
+         + ref.projected_area_by_expectation(ld, G, cov) / ld[2])
+    h = (v + ld) / np.linalg.norm(v + ld)
+    D = ref.ndf_by_gdf(h, G, cov)
+    F = 0.9 * ref.fresnel_conductor_snell(float(v @ h), orc.f32(eta), orc.f32(k))
+    leak = (special.ndtr(-0.4 / sigma) / special.ndtr(0.4 / sigma)) ** n
+    want = F * D / (4 * v[2] * n) * (1 - leak)
+    inner = r["mean"][10:22, 10:22]
+    se = math.sqrt(r["var"][10:22, 10:22].mean() / (s.spp * inner.size))
+    assert abs(inner.mean() - want) < 5 * se
+
+
+def test_fresnel_phase_normalization_and_sampler():
+    """int p dwi = int F(<v, m>) D_v(m) dm (< albedo) and E[weight] equals it."""
+    rng = np.random.default_rng(45)
+    # the phase entry points take the scene-less form; a scene point carries the Fresnel term
+    s = sc.plane_scene(width=4, height=4, spp=1).replace(fresnel_eta=0.2, fresnel_k=3.0)
+    o = orc.OracleScene(s)
+    x = np.array([0.5, 0.5, 0.02])
+    d = np.array([0.5, 0.0, -math.sqrt(0.75)])
+    e = o.eval_point(x)
+    assert e["G"][2] == pytest.approx(1.0)
+    dirs, W = ref.sphere_grid(-d, 300, 300)
+    vis_d, vis_w = ref.sphere_grid(e["G"], 600, 256, hemisphere=False)
+    D = np.array([orc.ndf(e["G"], e["s"], m) for m in vis_d])
+    vm = np.maximum(0.0, vis_d @ (-d))
+    Fm = np.array([orc.f32(e["albedo"]) * ref.fresnel_conductor_snell(c, orc.f32(0.2), orc.f32(3.0)) for c in vm])
+    want = float(np.sum(vis_w * Fm * vm * D)) / orc.sigma_proj(e["G"], e["s"], d)
+    got = float(np.sum(W * np.array([o.phase_eval_at(x, d, wi) for wi in dirs])))
+    assert got == pytest.approx(want, rel=2e-3)
+    assert want < e["albedo"]
