@@ -20,9 +20,6 @@ FLAGS = [
     "-ffp-contract=on",
     # hardware floating-point atomics for gradient accumulation (device memory from hipMalloc)
     "-munsafe-fp-atomics",
-    # single-precision division and square root from the hardware reciprocal and square-root
-    # approximations (a few ulp) instead of the correctly rounded sequences
-    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 

@@ -212,7 +212,8 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_adjoint_kerne
     src.s0 = s0;
     src.ns = ns;
     GradAcc acc{0.0f, 0.0f, 0.0f};
-    run_scheduled<false, true, 0>(S, src, nullptr, st, io, acc);
+    __shared__ SchedLds<true> lds;
+    run_scheduled<false, true, kMedIso>(S, src, nullptr, st, io, acc, lds);
     float v[3] = {acc.var, acc.len, acc.alb};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {

@@ -71,6 +71,7 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const 
     const uint32_t lane = threadIdx.x & 63;
     PathStats st;
     st.clear();
+    __shared__ SchedLds<false> lds;
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(cursor, 1u);
@@ -85,7 +86,11 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const 
         src.spp = B.spp;
         const AdjointIo io{};
         GradAcc acc{0.0f, 0.0f, 0.0f};
-        run_scheduled<false, false, -1>(B.S, src, paths, st, io, acc);
+        // the same specialization per medium as the single-scene kernel (identical images)
+        const int med = medium_of(B.S);
+        if (med == kMedGgx) run_scheduled<false, false, kMedGgx>(B.S, src, paths, st, io, acc, lds);
+        else if (med == kMedAniso) run_scheduled<false, false, kMedAniso>(B.S, src, paths, st, io, acc, lds);
+        else run_scheduled<false, false, kMedIso>(B.S, src, paths, st, io, acc, lds);
     }
 }
 

@@ -333,8 +333,11 @@ __device__ __forceinline__ float cos_to_normal(float3 G, float3 w) {
 // length; scales with |G| otherwise.
 __device__ __forceinline__ float sigma_proj(float3 G, float s, float ak, float3 d) {
     const float m = dot(d, G);
-    const float c = cos_to_normal(G, d);
-    const float sd = s * sqrtf(1.0f + ak * (c * c));
+    float sd = s;
+    if (ak != 0.0f) {
+        const float c = cos_to_normal(G, d);
+        sd = s * sqrtf(1.0f + ak * (c * c));
+    }
     const float z = m / sd;
     const float az = fabsf(z);
     const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
@@ -352,16 +355,25 @@ __device__ __forceinline__ float sigma_proj(float3 G, float s, float ak, float3 
 //                                   + [k > 0] sqrt(2 pi) k (k^2+3) e^{-q/2} ].
 // For the isotropic kernel (ak = 0): r = a = 1, k = G.wm / s, q = |G x wm|^2 / s^2.
 __device__ __forceinline__ float ndf(float3 G, float s, float ak, float3 wm) {
-    const float r2 = 1.0f + ak;
-    const float c = cos_to_normal(G, wm);
-    const float a = 1.0f - (c * c) * (ak / r2);
     const float is = 1.0f / s;
-    const float isr2 = is * is / r2;
     const float g2 = dot(G, G);
-    const float k = dot(G, wm) * is * rsqrtf(a) / r2;
-    const float q = g2 * fmaxf(1.0f - c * c, 0.0f) * isr2 / a;
+    float k, q, isr2, pre;
+    if (ak != 0.0f) {
+        const float r2 = 1.0f + ak;
+        const float c = cos_to_normal(G, wm);
+        const float a = 1.0f - (c * c) * (ak / r2);
+        isr2 = is * is / r2;
+        k = dot(G, wm) * is * rsqrtf(a) / r2;
+        q = g2 * fmaxf(1.0f - c * c, 0.0f) * isr2 / a;
+        pre = s * kInv2PiPow1p5 * rsqrtf(r2) / (a * a);
+    } else {   // isotropic kernel: r = a = 1, q = |G x wm|^2 / s^2
+        const float3 cr = cross(G, wm);
+        isr2 = is * is;
+        k = dot(G, wm) * is;
+        q = dot(cr, cr) * isr2;
+        pre = s * kInv2PiPow1p5;
+    }
     const float eG = expf(-0.5f * g2 * isr2);
-    const float pre = s * kInv2PiPow1p5 * rsqrtf(r2) / (a * a);
     const float k2 = k * k, akk = fabsf(k);
     const float b = (k2 + 2.0f) - kSqrtHalfPi * akk * (k2 + 3.0f) * erfcxf(akk * kInvSqrt2);
     const float up = k > 0.0f ? kSqrt2Pi * k * (k2 + 3.0f) * expf(-0.5f * q) : 0.0f;

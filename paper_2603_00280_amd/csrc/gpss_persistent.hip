@@ -26,7 +26,7 @@ __global__ void sched_reset_kernel(uint32_t* head) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *head = 0u;
 }
 
-template <bool STATS, int NDFK>
+template <bool STATS, int MED>
 __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_render_kernel(
     const SceneDev* __restrict__ Sp, float* __restrict__ paths, uint32_t* head, unsigned long long* counters,
     uint32_t s0, uint32_t ns, uint32_t npaths) {
@@ -40,7 +40,8 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_render_kernel
     src.ns = ns;
     const AdjointIo io{};
     GradAcc acc{0.0f, 0.0f, 0.0f};
-    run_scheduled<STATS, false, NDFK>(S, src, paths, st, io, acc);
+    __shared__ SchedLds<false> lds;
+    run_scheduled<STATS, false, MED>(S, src, paths, st, io, acc, lds);
     flush_stats_sched<STATS>(st, counters);
 }
 
@@ -55,19 +56,20 @@ int sched_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, u
     const dim3 blk(256);
     const dim3 grid(s->sched_grid);
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
-    const bool ggx = s->dev.ggx != 0;
-    if (counters && ggx)
-        hipLaunchKernelGGL((sched_render_kernel<true, 1>), grid, blk, 0, stream, s->d_dev, paths, s->d_head, cnt, s0,
-                           ns, (uint32_t)npaths);
-    else if (counters)
-        hipLaunchKernelGGL((sched_render_kernel<true, 0>), grid, blk, 0, stream, s->d_dev, paths, s->d_head, cnt, s0,
-                           ns, (uint32_t)npaths);
-    else if (ggx)
-        hipLaunchKernelGGL((sched_render_kernel<false, 1>), grid, blk, 0, stream, s->d_dev, paths, s->d_head, nullptr,
-                           s0, ns, (uint32_t)npaths);
-    else
-        hipLaunchKernelGGL((sched_render_kernel<false, 0>), grid, blk, 0, stream, s->d_dev, paths, s->d_head, nullptr,
-                           s0, ns, (uint32_t)npaths);
+    const int med = medium_of(s->dev);
+#define GPSS_SCHED_LAUNCH(ST, M)                                                                                    \
+    hipLaunchKernelGGL((sched_render_kernel<ST, M>), grid, blk, 0, stream, s->d_dev, paths, s->d_head,            \
+                       ST ? cnt : nullptr, s0, ns, (uint32_t)npaths)
+    if (counters) {
+        if (med == kMedGgx) GPSS_SCHED_LAUNCH(true, kMedGgx);
+        else if (med == kMedAniso) GPSS_SCHED_LAUNCH(true, kMedAniso);
+        else GPSS_SCHED_LAUNCH(true, kMedIso);
+    } else {
+        if (med == kMedGgx) GPSS_SCHED_LAUNCH(false, kMedGgx);
+        else if (med == kMedAniso) GPSS_SCHED_LAUNCH(false, kMedAniso);
+        else GPSS_SCHED_LAUNCH(false, kMedIso);
+    }
+#undef GPSS_SCHED_LAUNCH
     return check_hip(hipGetLastError(), "sched_render_kernel launch");
 }
 

@@ -83,17 +83,32 @@ struct AdjointIo {
 // (frozen-sampling estimator; the terms are those of the one-thread replay in
 // gpss_adjoint.hip) into io.grad_off and acc.  Must be called by whole waves; returns when
 // the source is exhausted and every lane's path has ended.
-// NDFK: the scene's NDF kind when the kernel is specialized for it (0 generalized, 1 GGX), so
-// that the other kind's code is not compiled in; -1 takes it from the scene record.
-template <bool STATS, bool ADJ, int NDFK, class Source>
+// MED: the scene's medium when the kernel is specialized for it (kMedIso generalized with the
+// isotropic kernel, kMedGgx, kMedAniso generalized with the anisotropic kernel), so that
+// the other media's code is not compiled in; kMedAny takes everything from the scene record.
+enum { kMedAny = -1, kMedIso = 0, kMedGgx = 1, kMedAniso = 2 };
+
+__host__ __device__ inline int medium_of(const SceneDev& S) {
+    return S.ggx ? kMedGgx : (S.aniso_k != 0.0f ? kMedAniso : kMedIso);
+}
+
+// Cold per-lane state (touched once per segment or vertex) lives in LDS, one column per
+// lane, so that registers hold what the cell walk and the medium evaluation use.  The
+// kernel declares it (__shared__) and hands it to run_scheduled.
+template <bool ADJ>
+struct SchedLds {
+    uint32_t u[3][kSchedBlock];             // output slot, pixel, sample
+    float f[ADJ ? 15 : 6][kSchedBlock];     // beta, L, beta*phase and Le per light (+ adjoint terms)
+    double d[3][kSchedBlock];               // direction of the next track segment
+};
+
+template <bool STATS, bool ADJ, int MED, class Source>
 __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, float* __restrict__ paths,
-                                              PathStats& st, const AdjointIo& io, GradAcc& acc) {
-    // Cold per-lane state (touched once per segment or vertex) lives in LDS, one column per
-    // lane, so that registers hold what the cell walk and the medium evaluation use.
-    constexpr int kNf = ADJ ? 15 : 6;
-    __shared__ uint32_t cs_u[3][kSchedBlock];   // output slot, pixel, sample
-    __shared__ float cs_f[kNf][kSchedBlock];    // beta, L, beta*phase and Le per light (+ adjoint terms)
-    __shared__ double cs_d[3][kSchedBlock];     // direction of the next track segment
+                                              PathStats& st, const AdjointIo& io, GradAcc& acc,
+                                              SchedLds<ADJ>& lds) {
+    auto& cs_u = lds.u;
+    auto& cs_f = lds.f;
+    auto& cs_d = lds.d;
     const int lt = threadIdx.x;
     enum { kSlot = 0, kPixel = 1, kSample = 2 };
     // forward: kL = radiance so far; adjoint: kL = remaining radiance L_rem of the replay
@@ -112,7 +127,10 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
     Rng rng;
     auto point = [&](float3 x) {   // medium statistics at x, with the specialized NDF kind
         PointQ q = eval_point(S, x);
-        if (NDFK >= 0) q.ggx = NDFK;
+        if (MED != kMedAny) {
+            q.ggx = MED == kMedGgx;
+            if (MED != kMedAniso) q.ak = 0.0f;
+        }
         return q;
     };
     auto finish = [&](float L) {   // the path's radiance to its output slot; the lane falls idle
