@@ -73,6 +73,8 @@ class Scene:
     ndf_kind: int = 0                      # NDF_GENERALIZED (Eq. macro_ndf) or NDF_GGX (height field)
     fresnel_eta: float = 0.0               # conductor IOR eta + i k of the Fresnel term (eta = 0: F = albedo)
     fresnel_k: float = 0.0
+    observations: Optional[np.ndarray] = None   # (n, 4) float32: x, y, z, observed value (Eq. condition_gp)
+    obs_noise: float = 0.0                 # observation-noise variance (> 0 when observations are given)
 
     @property
     def n_pixels(self) -> int:
@@ -198,6 +200,56 @@ def fresnel_rgb_scenes(scene: Scene, metal: str = "gold") -> list:
     return [scene.replace(name=f"{scene.name}_{metal}_{c}", fresnel_eta=float(e), fresnel_k=float(k), albedo=1.0,
                           scene_id=scene.scene_id + i)
             for i, (c, e, k) in enumerate(zip("rgb", etas, ks))]
+
+
+# ---------------------------------------------------------------------------
+# GP conditioned on point observations (Eq. condition_gp), the surface-reconstruction use of
+# GPISes: a seeded point cloud with observed SDF values.
+#   cond_sphere_scene: the sphere prior (unit-sphere SDF mean) observed at n points whose
+#     radii are jittered by U(-jitter, jitter) with observed value 0, i.e. the surface is
+#     pulled through them; directions on a Fibonacci sphere.
+#   cond_blob_scene: a constant prior mean (outside, one prior standard deviation) and a point
+#     cloud on an ellipsoid (value 0) plus points at half the semi-axes inside (value -0.2).
+# Observation noise is obs_noise_frac x the kernel variance.
+# ---------------------------------------------------------------------------
+MAX_OBSERVATIONS = 32
+
+
+def fibonacci_directions(n: int) -> np.ndarray:
+    i = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * i / n
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    ph = math.pi * (3.0 - math.sqrt(5.0)) * i
+    return np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1)
+
+
+def cond_sphere_scene(n_obs: int = 32, jitter: float = 0.08, lengthscale: float = 0.25,
+                      variance: float = 0.0025, obs_noise_frac: float = 0.05, obs_seed: int = 6,
+                      **kw) -> Scene:
+    rng = np.random.default_rng(obs_seed)
+    dirs = fibonacci_directions(n_obs)
+    rad = 1.0 + rng.uniform(-jitter, jitter, n_obs)
+    obs = np.concatenate([dirs * rad[:, None], np.zeros((n_obs, 1))], axis=1)
+    s = sphere_scene(lengthscale=lengthscale, variance=variance, **kw)
+    return s.replace(name=f"cond_sphere_n{n_obs}", observations=_f32(obs),
+                     obs_noise=float(obs_noise_frac * variance))
+
+
+def cond_blob_scene(n_surface: int = 26, axes=(0.6, 0.45, 0.35), lengthscale: float = 0.3,
+                    variance: float = 0.04, obs_noise_frac: float = 0.05, width: int = 512,
+                    height: int = 512, spp: int = 64, max_depth: int = 32, seed: int = 7,
+                    majorant_res=(64, 64, 64)) -> Scene:
+    ax = np.asarray(axes, np.float64)
+    surf = fibonacci_directions(n_surface) * ax
+    inner = np.concatenate([np.diag(0.5 * ax), -np.diag(0.5 * ax)])
+    obs = np.concatenate([np.concatenate([surf, np.zeros((n_surface, 1))], axis=1),
+                          np.concatenate([inner, np.full((6, 1), -0.2)], axis=1)])
+    sigma = math.sqrt(variance)
+    s = sphere_scene(lengthscale=lengthscale, variance=variance, width=width, height=height, spp=spp,
+                     max_depth=max_depth, seed=seed, majorant_res=majorant_res)
+    return s.replace(name=f"cond_blob_n{obs.shape[0]}", mean_kind=MEAN_CONST, mean_const=float(sigma),
+                     prims=np.zeros((0, 8), np.float32), bounds=_f32([-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]),
+                     observations=_f32(obs), obs_noise=float(obs_noise_frac * variance))
 
 
 # ---------------------------------------------------------------------------

@@ -45,6 +45,13 @@ struct oracle_scene {
     bool ggx;              // GGX height-field macrofacet (NDF and Lambda of GGX) instead of Eq. macro_ndf
     double f_eta, f_k;     // conductor index of refraction eta + i k of the Fresnel term (eta = 0: F = albedo)
     bool albedo_per_prim;
+    // GP conditioned on point observations (Eq. condition_gp): positions (3 per point),
+    // observed values, noise variance, the Cholesky factor of kappa(C, C) + noise I (row-major,
+    // lower) and the weights alpha = (kappa(C, C) + noise I)^-1 (m - mu(C)).
+    bool cond;
+    int n_obs;
+    std::vector<double> obs_x, obs_m, obs_L, obs_alpha;
+    double obs_noise;
     double lo[3], hi[3], ext[3];
     double R;
     int M[3];
@@ -176,6 +183,148 @@ void trilinear(const Grid& G, const Scene& S, const double x[3], Tri& t) {
 }
 
 // ---------------------------------------------------------------------------
+// GP conditioned on point observations (Sec. 3.1, Eq. condition_gp).  The observations
+// (C, m) carry independent Gaussian noise of variance s_n^2 > 0, which adds s_n^2 I to
+// kappa(C, C); s_n -> 0 is the equation as printed.  The posterior of the value and the
+// gradient at x follows from the same equation applied to the jointly Gaussian vector
+// (f(x), grad f(x)) (Eq. joint_fg), whose covariances with f(C) are kappa(x, C) and
+// grad_x kappa(x, C), and whose prior covariance at one point is diag(sigma^2, sigma^2/l^2 I)
+// for the squared-exponential kernel (Eq. se_kernel).
+// ---------------------------------------------------------------------------
+double se_kernel(const Scene& S, const double x[3], const double y[3]) {
+    const double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+    return S.variance * std::exp(-dot3(d, d) / (2.0 * S.l * S.l));
+}
+
+// In-place Cholesky factor (lower, row-major) of a symmetric positive definite matrix.
+bool cholesky(std::vector<double>& a, int n) {
+    for (int j = 0; j < n; ++j) {
+        double d = a[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= a[(size_t)j * n + k] * a[(size_t)j * n + k];
+        if (!(d > 0.0)) return false;
+        d = std::sqrt(d);
+        a[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double v = a[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= a[(size_t)i * n + k] * a[(size_t)j * n + k];
+            a[(size_t)i * n + j] = v / d;
+        }
+        for (int i = 0; i < j; ++i) a[(size_t)i * n + j] = 0.0;
+    }
+    return true;
+}
+
+// Solve (L L^T) x = b in place.
+void chol_solve(const std::vector<double>& L, int n, double* b) {
+    for (int i = 0; i < n; ++i) {
+        double v = b[i];
+        for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * b[k];
+        b[i] = v / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = b[i];
+        for (int k = i + 1; k < n; ++k) v -= L[(size_t)k * n + i] * b[k];
+        b[i] = v / L[(size_t)i * n + i];
+    }
+}
+
+// Posterior of (f(x), grad f(x)) given the observations, for prior mean mu0 and gradient g0 at x.
+struct Posterior {
+    double mu, g[3];     // posterior mean of f(x) and of grad f(x)
+    double var;          // posterior variance of f(x)
+    double c[3];         // posterior covariance of grad f(x) with f(x)
+    double Sgg[3][3];    // posterior covariance of grad f(x)
+};
+
+Posterior posterior_at(const Scene& S, const double x[3], double mu0, const double g0[3]) {
+    const int n = S.n_obs;
+    const double il2 = 1.0 / (S.l * S.l);
+    // U: 4 x n covariances of (f(x), d f(x) / dx_a) with f(x_j)
+    std::vector<double> U(4 * (size_t)n), Z;
+    for (int j = 0; j < n; ++j) {
+        const double* xj = &S.obs_x[3 * (size_t)j];
+        const double k = se_kernel(S, x, xj);
+        U[j] = k;
+        for (int a = 0; a < 3; ++a) U[(size_t)(1 + a) * n + j] = -k * (x[a] - xj[a]) * il2;
+    }
+    Posterior P;
+    P.mu = mu0;
+    for (int a = 0; a < 3; ++a) P.g[a] = g0[a];
+    for (int j = 0; j < n; ++j) {
+        P.mu += U[j] * S.obs_alpha[j];
+        for (int a = 0; a < 3; ++a) P.g[a] += U[(size_t)(1 + a) * n + j] * S.obs_alpha[j];
+    }
+    Z = U;
+    for (int r = 0; r < 4; ++r) chol_solve(S.obs_L, n, &Z[(size_t)r * n]);
+    double cov[4][4];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double v = r != c ? 0.0 : (r == 0 ? S.variance : S.variance * il2);
+            for (int j = 0; j < n; ++j) v -= U[(size_t)r * n + j] * Z[(size_t)c * n + j];
+            cov[r][c] = v;
+        }
+    P.var = cov[0][0];
+    for (int a = 0; a < 3; ++a) {
+        P.c[a] = cov[1 + a][0];
+        for (int b = 0; b < 3; ++b) P.Sgg[a][b] = cov[1 + a][1 + b];
+    }
+    return P;
+}
+
+// Prior mean at x (mean function plus the trilinear offset grid).
+double prior_mean(const Scene& S, const double x[3]) {
+    double f, g[3];
+    int which;
+    mean_geom(S, x, f, g, which);
+    if (!S.offset.empty()) {
+        Tri t;
+        trilinear(S.offset, S, x, t);
+        for (int n = 0; n < 8; ++n) f += t.w[n] * S.offset.v[t.idx[n]];
+    }
+    return f;
+}
+
+// Projected area E[max(0, -d.g)] for g ~ N(G, Sigma) with a full covariance: -d.g is
+// Gaussian with mean a = -d.G and variance d^T Sigma d.
+double sigma_proj_cov(const double G[3], const double Sg[3][3], const double d[3]) {
+    double v = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) v += d[i] * Sg[i][j] * d[j];
+    const double sd = std::sqrt(v);
+    const double a = -dot3(d, G);
+    return a * Phi_d(a / sd) + sd * phi_d(a / sd);
+}
+
+// Generalized NDF (Sec. 4.2.2) for g ~ N(G, Sigma) with a full covariance:
+//   D(w) = int_0^inf r^3 N(r w; G, Sigma) dr.
+// With A = w^T S^-1 w, B = w^T S^-1 G, C = G^T S^-1 G, b = B / sqrt(A), q = C - B^2/A the
+// exponent is -(A/2)(r - B/A)^2 - q/2, and the moments of the truncated Gaussian give
+//   D = [e^{-C/2} (b^2 + 2) + sqrt(2 pi) e^{-q/2} Phi(b) b (b^2 + 3)] / ((2 pi)^{3/2} |S|^{1/2} A^2).
+double ndf_cov(const double G[3], const double Sg[3][3], const double w[3]) {
+    const double det = Sg[0][0] * (Sg[1][1] * Sg[2][2] - Sg[1][2] * Sg[2][1]) -
+                       Sg[0][1] * (Sg[1][0] * Sg[2][2] - Sg[1][2] * Sg[2][0]) +
+                       Sg[0][2] * (Sg[1][0] * Sg[2][1] - Sg[1][1] * Sg[2][0]);
+    double inv[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            // cofactor of (j, i) over the determinant
+            const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+            inv[i][j] = (Sg[r0][c0] * Sg[r1][c1] - Sg[r0][c1] * Sg[r1][c0]) / det;
+        }
+    auto quad = [&inv](const double u[3], const double v[3]) {
+        double s = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) s += u[i] * inv[i][j] * v[j];
+        return s;
+    };
+    const double A = quad(w, w), B = quad(w, G), C = quad(G, G);
+    const double b = B / std::sqrt(A);
+    const double q = std::max(C - B * B / A, 0.0);
+    const double num = std::exp(-0.5 * C) * (b * b + 2.0) + kSqrt2Pi * std::exp(-0.5 * q) * Phi_d(b) * b * (b * b + 3.0);
+    return num / (2.0 * kPi * kSqrt2Pi * std::sqrt(det) * A * A);
+}
+
+// ---------------------------------------------------------------------------
 // GP statistics at a point (Sec. 3.1): f(x) ~ N(mu(x), sigma^2) and, independent of it
 // at the same point (Eq. joint_fg), g(x) ~ N(grad mu(x), Sigma) with, for the
 // squared-exponential kernel with lengthscale l across and l_n along the local
@@ -192,6 +341,9 @@ struct PointQ {
     T albedo;
     bool ggx = false;   // GGX height-field macrofacet
     double f_eta = 0.0, f_k = 0.0;   // conductor Fresnel (eta = 0: none)
+    // conditioned GP: G is the gradient mean given f(x) = 0 and cov its full covariance
+    bool cond = false;
+    double cov[3][3] = {};
 };
 
 template <class T>
@@ -246,6 +398,25 @@ PointQ<T> eval_point(const Params<T>& P, const double x[3]) {
     q.f_k = S.f_k;
     if (S.albedo_per_prim && which >= 0) q.albedo = T(S.prims[which].albedo);
     else q.albedo = mk<T>(S.albedo, P.slot_alb);
+    if (S.cond) {
+        // Conditioned GP: density from f(x) ~ N(mu_C, var_C); gradient distribution given
+        // f(x) = 0 (the surface), by the same Gaussian conditioning applied to the posterior
+        // pair (f(x), grad f(x)):  mean g_C - c mu_C / var_C, covariance Sgg - c c^T / var_C.
+        const double g0[3] = {val(q.G[0]), val(q.G[1]), val(q.G[2])};
+        const Posterior Q = posterior_at(S, x, val(q.mu), g0);
+        q.cond = true;
+        q.mu = T(Q.mu);
+        q.sigma = T(std::sqrt(Q.var));
+        double tr = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            q.G[a] = T(Q.g[a] - Q.c[a] * Q.mu / Q.var);
+            for (int b = 0; b < 3; ++b) q.cov[a][b] = Q.Sgg[a][b] - Q.c[a] * Q.c[b] / Q.var;
+            tr += q.cov[a][a];
+        }
+        // isotropic gradient spread of the same total variance, used by the proposal only
+        q.s = T(std::sqrt(tr / 3.0));
+        q.sn = q.s;
+    }
     return q;
 }
 
@@ -318,6 +489,10 @@ T ggx_D(const T& alpha, const T& c) {
 
 template <class T>
 T sigma_proj(const PointQ<T>& q, const double d[3]) {
+    if (q.cond) {
+        const double G[3] = {val(q.G[0]), val(q.G[1]), val(q.G[2])};
+        return T(sigma_proj_cov(G, q.cov, d));
+    }
     const T g2 = q.G[0] * q.G[0] + q.G[1] * q.G[1] + q.G[2] * q.G[2];
     if (q.ggx) {
         if (val(g2) == 0.0) return T(0.0);
@@ -341,6 +516,10 @@ T sigma_proj(const PointQ<T>& q, const double d[3]) {
 //   D = 2 / ((2 pi)^(3/2) s^2 s_n A^2),  A = (1 - c^2) / s^2 + c^2 / s_n^2,  c = wm_z.
 template <class T>
 T ndf(const PointQ<T>& q, const double wm[3]) {
+    if (q.cond) {
+        const double G[3] = {val(q.G[0]), val(q.G[1]), val(q.G[2])};
+        return T(ndf_cov(G, q.cov, wm));
+    }
     const T g2 = q.G[0] * q.G[0] + q.G[1] * q.G[1] + q.G[2] * q.G[2];
     if (q.ggx) {
         if (val(g2) == 0.0) return T(0.0);
@@ -536,6 +715,58 @@ void node_range(int k, int M, int R, int& lo, int& hi) {
     if (hi > R - 1) hi = R - 1;
 }
 
+// Bound for the conditioned GP (scalar prior variance s^2, isotropic kernel) over cell k,
+// given the prior mean's minimum mu_min and gradient bound gmax over the cell.  With d_j the
+// distances from observation j to the cell (nearest dmin_j, farthest dmax_j):
+//   mu_C >= mu_min + sum_j alpha_j kappa(d), kappa(d) = s^2 e^{-d^2/(2l^2)} taken at dmax_j for
+//           alpha_j > 0 and at dmin_j otherwise;
+//   |grad mu_C| <= gmax + sum_j |alpha_j| (s^2/l^2) d e^{-d^2/(2l^2)}, d = clamp(l, dmin_j, dmax_j)
+//           (the maximum of that profile over [dmin_j, dmax_j]);
+//   s_C^2 <= s^2 (conditioning never adds variance) and, writing f(x_j) = r_j f(x) + e_j with
+//           e_j independent of f(x) and the observation noise at least s_n^2 I,
+//           1/s_C^2 <= 1/s^2 + sum_j r_j^2 / s_n^2, r_j^2 = e^{-d_j^2/l^2} <= e^{-dmin_j^2/l^2};
+//   the conditioned gradient g ~ N(m, Sigma) has Sigma <= (s/l)^2 I and
+//           |m| <= |grad mu_C| + (s/l) |z|, z = mu_C / s_C (Cauchy-Schwarz on the posterior
+//           covariance of f(x) and grad f(x)), so sigma_proj <= |m| + (s/l) / sqrt(2 pi);
+//   rho = r(z) / s_C with r = phi / Phi decreasing, z >= z_lo = mu_lo / (mu_lo > 0 ? s : s_lo),
+//           and r(z) |z| <= max(0.3, r(z_lo) max(0, -z_lo)) (its supremum over z >= 0 is 0.2945).
+// Two more lower bounds from the posterior at the cell centre c and the half diagonal h:
+//   mu_C >= mu_C(c) - h |grad mu_C|max, and s_C >= s_C(c) - h s / l, since grad s_C =
+//   cov(grad f, f) / s_C has length at most s / l (the Cauchy-Schwarz bound above);
+// each of mu_lo and s_lo is the larger of its two bounds.
+double cond_bound(const Scene& S, const int k[3], const double cwv[3], double mu_min, double gmax) {
+    const double l = S.l, s2 = S.variance;
+    double mu_c = 0.0, g_c = 0.0, prec = 1.0 / s2;
+    for (int j = 0; j < S.n_obs; ++j) {
+        const double* xj = &S.obs_x[3 * (size_t)j];
+        double dn2 = 0.0, df2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double c0 = S.lo[a] + k[a] * cwv[a], c1 = S.lo[a] + (k[a] + 1) * cwv[a];
+            const double dn = xj[a] < c0 ? c0 - xj[a] : (xj[a] > c1 ? xj[a] - c1 : 0.0);
+            const double df = std::max(std::fabs(xj[a] - c0), std::fabs(xj[a] - c1));
+            dn2 += dn * dn;
+            df2 += df * df;
+        }
+        const double dmin = std::sqrt(dn2), dmax = std::sqrt(df2);
+        const double al = S.obs_alpha[j];
+        mu_c += al * s2 * std::exp(-(al > 0.0 ? df2 : dn2) / (2.0 * l * l));
+        const double dd = std::min(std::max(l, dmin), dmax);
+        g_c += std::fabs(al) * (s2 / (l * l)) * dd * std::exp(-dd * dd / (2.0 * l * l));
+        prec += std::exp(-dn2 / (l * l)) / S.obs_noise;
+    }
+    const double G1 = gmax + g_c;
+    const double s_hi = std::sqrt(s2), sl = s_hi / l;
+    double c[3], g0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) c[a] = S.lo[a] + (k[a] + 0.5) * cwv[a];
+    const double hdiag = 0.5 * std::sqrt(cwv[0] * cwv[0] + cwv[1] * cwv[1] + cwv[2] * cwv[2]);
+    const Posterior P = posterior_at(S, c, prior_mean(S, c), g0);
+    const double mu_lo = std::max(mu_min + mu_c, P.mu - hdiag * G1);
+    const double s_lo = std::max(1.0 / std::sqrt(prec), std::sqrt(std::max(P.var, 0.0)) - hdiag * sl);
+    const double z_lo = mu_lo / (mu_lo > 0.0 ? s_hi : s_lo);
+    const double R = r_ratio(z_lo);
+    return (R * (G1 + sl / kSqrt2Pi) + sl * std::max(0.3, R * std::max(0.0, -z_lo))) / s_lo;
+}
+
 void build_majorants(Scene& S) {
     const int64_t n = (int64_t)S.M[0] * S.M[1] * S.M[2];
     S.maj.assign(n, 0.0);
@@ -600,6 +831,10 @@ void build_majorants(Scene& S) {
                 }
                 mu_min += off_min;
                 gmax += off_g;
+                if (S.cond) {
+                    S.maj[((int64_t)kz * S.M[1] + ky) * S.M[0] + kx] = quantize_majorant(cond_bound(S, k, cwv, mu_min, gmax));
+                    continue;
+                }
                 const double smin_f = std::sqrt(vmin), smax_f = std::sqrt(vmax);
                 const double s_max = smax_f / std::min(S.l, S.l_n);
                 const double rho_max = r_ratio(mu_min / (mu_min > 0.0 ? smax_f : smin_f)) / smin_f;
@@ -969,6 +1204,12 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
         if (D->var_grid && D->var_res[a] < 2) return -1;
     }
     if (D->mean_kind == 1 && (D->n_prims <= 0 || !D->prims)) return -1;
+    if (D->n_obs < 0 || (D->n_obs > 0 && !D->observations)) return -1;
+    if (D->n_obs > 0) {
+        // conditioning is defined here for a scalar-variance, isotropic, generalized macrofacet
+        if (!(D->obs_noise > 0.0) || !std::isfinite(D->obs_noise) || D->var_grid || D->ndf_kind != 0) return -1;
+        if (D->lengthscale_n > 0.0 && D->lengthscale_n != D->lengthscale) return -1;
+    }
     auto* S = new oracle_scene();
     S->mean_kind = D->mean_kind;
     S->mean_const = D->mean_const;
@@ -1020,6 +1261,26 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
     S->W = D->width; S->H = D->height; S->spp = D->spp; S->max_depth = D->max_depth;
     S->key[0] = (uint32_t)(D->seed & 0xFFFFFFFFu);
     S->key[1] = (uint32_t)(D->seed >> 32) ^ D->scene_id;
+    S->cond = D->n_obs > 0;
+    S->n_obs = D->n_obs;
+    S->obs_noise = D->obs_noise;
+    if (S->cond) {
+        const int n = S->n_obs;
+        for (int j = 0; j < n; ++j) {
+            for (int a = 0; a < 3; ++a) S->obs_x.push_back(D->observations[4 * j + a]);
+            S->obs_m.push_back(D->observations[4 * j + 3]);
+        }
+        // kappa(C, C) + s_n^2 I, its Cholesky factor, and alpha = (.)^-1 (m - mu(C))
+        S->obs_L.assign((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                S->obs_L[(size_t)i * n + j] = se_kernel(*S, &S->obs_x[3 * (size_t)i], &S->obs_x[3 * (size_t)j]) +
+                                              (i == j ? S->obs_noise : 0.0);
+        if (!cholesky(S->obs_L, n)) { delete S; return -1; }
+        S->obs_alpha.resize(n);
+        for (int j = 0; j < n; ++j) S->obs_alpha[j] = S->obs_m[j] - prior_mean(*S, &S->obs_x[3 * (size_t)j]);
+        chol_solve(S->obs_L, n, S->obs_alpha.data());
+    }
     build_majorants(*S);
     *out = S;
     return 0;
@@ -1112,6 +1373,7 @@ int oracle_render_grad(const oracle_scene* s, int32_t s0, int32_t s1, const doub
                        int32_t n_params, const int64_t* param_ids, double* grad, double* mean,
                        int32_t nthreads) {
     if (!s || !dloss || !grad || n_params < 0 || n_params > Dual::N || s1 <= s0 || s0 < 0) return -1;
+    if (s->cond) return -1;   // derivatives through the posterior are not carried
     std::unordered_map<int64_t, int> slots;
     Params<Dual> P1;
     P1.S = s;
@@ -1271,6 +1533,47 @@ int oracle_eval_point(const oracle_scene* sc, const double x[3], double out[8]) 
     out[0] = q.mu; out[1] = q.G[0]; out[2] = q.G[1]; out[3] = q.G[2];
     out[4] = q.sigma; out[5] = q.s; out[6] = q.albedo; out[7] = q.sn;
     return 0;
+}
+
+int oracle_posterior(const oracle_scene* sc, const double x[3], double out[23]) {
+    if (!sc || !sc->cond) return -1;
+    double f, g[3];
+    int which;
+    mean_geom(*sc, x, f, g, which);
+    if (!sc->offset.empty()) {
+        Tri t;
+        trilinear(sc->offset, *sc, x, t);
+        for (int n = 0; n < 8; ++n) {
+            f += t.w[n] * sc->offset.v[t.idx[n]];
+            for (int a = 0; a < 3; ++a) g[a] += t.dw[n][a] * sc->offset.v[t.idx[n]];
+        }
+    }
+    const Posterior P = posterior_at(*sc, x, f, g);
+    out[0] = P.mu;
+    for (int a = 0; a < 3; ++a) out[1 + a] = P.g[a];
+    out[4] = P.var;
+    for (int a = 0; a < 3; ++a) out[5 + a] = P.c[a];
+    const PointQ<double> q = eval_point(plain_params(sc), x);
+    const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    for (int e = 0; e < 6; ++e) out[8 + e] = P.Sgg[ij[e][0]][ij[e][1]];
+    for (int a = 0; a < 3; ++a) out[14 + a] = q.G[a];
+    for (int e = 0; e < 6; ++e) out[17 + e] = q.cov[ij[e][0]][ij[e][1]];
+    return 0;
+}
+
+static void cov_from6(const double c6[6], double S[3][3]) {
+    S[0][0] = c6[0]; S[0][1] = S[1][0] = c6[1]; S[0][2] = S[2][0] = c6[2];
+    S[1][1] = c6[3]; S[1][2] = S[2][1] = c6[4]; S[2][2] = c6[5];
+}
+double oracle_sigma_proj_cov(const double G[3], const double cov6[6], const double d[3]) {
+    double S[3][3];
+    cov_from6(cov6, S);
+    return sigma_proj_cov(G, S, d);
+}
+double oracle_ndf_cov(const double G[3], const double cov6[6], const double wm[3]) {
+    double S[3][3];
+    cov_from6(cov6, S);
+    return ndf_cov(G, S, wm);
 }
 
 double oracle_phase_eval_at(const oracle_scene* sc, const double x[3], const double d[3], const double wi[3]) {

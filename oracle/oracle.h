@@ -60,6 +60,12 @@ typedef struct {
     double lengthscale_n;       /* lengthscale along the local mean-gradient direction (0: = lengthscale) */
     int32_t ndf_kind;           /* 0: generalized macrofacet (Eq. macro_ndf); 1: GGX height field */
     double fresnel_eta, fresnel_k;  /* conductor IOR eta + i k of the Fresnel term; eta = 0: F = albedo */
+    /* GP conditioning (Eq. condition_gp): n_obs x 4 (x, y, z, observed value), with
+     * observation-noise variance obs_noise > 0; needs a scalar variance, the isotropic
+     * kernel and the generalized NDF.  n_obs = 0: the unconditioned GP. */
+    const float* observations;
+    int32_t n_obs;
+    double obs_noise;
 } oracle_scene_desc;
 
 typedef struct oracle_scene oracle_scene;
@@ -151,6 +157,13 @@ double oracle_phase_eval_ggx(const double G[3], double s, double albedo, const d
 double oracle_mixture_pdf_ggx(const double G[3], double s, double R, const double d[3], const double wm[3]);
 int oracle_phase_sample_ggx(const double G[3], double s, double albedo, double R, const double d[3],
                             const double u[3], double* wi, double* wm, double* weight, double* pdf);
+/* Conditioned scenes: posterior at x, 23 doubles: mu_C, grad mu_C[3], var_C, c[3] = cov(grad f,
+ * f), Sgg[6] = cov(grad f) (xx xy xz yy yz zz), then the gradient distribution given f(x) = 0:
+ * mean[3], covariance[6].  -1 for an unconditioned scene. */
+int oracle_posterior(const oracle_scene* sc, const double x[3], double out[23]);
+/* projected area and NDF for g ~ N(G, Sigma), Sigma given as xx xy xz yy yz zz */
+double oracle_sigma_proj_cov(const double G[3], const double cov6[6], const double d[3]);
+double oracle_ndf_cov(const double G[3], const double cov6[6], const double wm[3]);
 /* mu, G[3], sigma, s (across n), albedo, s_n (along n) at a point */
 int oracle_eval_point(const oracle_scene* sc, const double x[3], double out[8]);
 double oracle_sigma_t(const oracle_scene* sc, const double x[3], const double d[3]);

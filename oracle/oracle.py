@@ -38,6 +38,7 @@ class _Desc(C.Structure):
         ("width", C.c_int32), ("height", C.c_int32), ("spp", C.c_int32), ("max_depth", C.c_int32),
         ("seed", C.c_uint64), ("scene_id", C.c_uint32), ("lengthscale_n", C.c_double),
         ("ndf_kind", C.c_int32), ("fresnel_eta", C.c_double), ("fresnel_k", C.c_double),
+        ("observations", C.POINTER(C.c_float)), ("n_obs", C.c_int32), ("obs_noise", C.c_double),
     ]
 
 
@@ -100,6 +101,10 @@ def lib():
                                           dp, dp]
         L.oracle_phase_sample_ggx.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp,
                                           dp, dp]
+        L.oracle_posterior.argtypes = [C.c_void_p, dp, dp]
+        for name in ("oracle_sigma_proj_cov", "oracle_ndf_cov"):
+            getattr(L, name).argtypes = [dp, dp, dp]
+            getattr(L, name).restype = C.c_double
         L.oracle_eval_point.argtypes = [C.c_void_p, dp, dp]
         L.oracle_sigma_t.argtypes = [C.c_void_p, dp, dp]
         L.oracle_sigma_t.restype = C.c_double
@@ -168,6 +173,12 @@ class OracleScene:
         d.ndf_kind = int(s.ndf_kind)
         d.fresnel_eta = f32(s.fresnel_eta)
         d.fresnel_k = f32(s.fresnel_k)
+        obs = getattr(s, "observations", None)
+        if obs is not None and len(obs):
+            self._obs = np.ascontiguousarray(obs, np.float32).reshape(-1, 4)
+            d.observations = self._obs.ctypes.data_as(C.POINTER(C.c_float))
+            d.n_obs = self._obs.shape[0]
+            d.obs_noise = f32(s.obs_noise)
         self._desc = d
         h = C.c_void_p()
         rc = lib().oracle_scene_create(C.byref(d), C.byref(h))
@@ -264,6 +275,15 @@ class OracleScene:
         lib().oracle_eval_point(self.handle, _dp(_vec(x)), _dp(out))
         return {"mu": out[0], "G": out[1:4].copy(), "sigma": out[4], "s": out[5],
                 "albedo": out[6], "sn": out[7]}
+
+    def posterior(self, x):
+        """Conditioned scenes: posterior of (f(x), grad f(x)) (Eq. condition_gp) and the
+        gradient distribution given f(x) = 0."""
+        out = np.zeros(23)
+        rc = lib().oracle_posterior(self.handle, _dp(_vec(x)), _dp(out))
+        assert rc == 0, "not a conditioned scene"
+        return {"mu": out[0], "grad": out[1:4].copy(), "var": out[4], "c": out[5:8].copy(),
+                "Sgg": _sym(out[8:14]), "mg": out[14:17].copy(), "Sg": _sym(out[17:23])}
 
     def phase_eval_at(self, x, d, wi) -> float:
         return lib().oracle_phase_eval_at(self.handle, _dp(_vec(x)), _dp(_vec(d)), _dp(_vec(wi)))
@@ -362,6 +382,26 @@ def phase_sample(G, s, albedo, R, d, u, ggx: bool = False):
     f(_dp(_vec(G)), float(s), float(albedo), float(R), _dp(_vec(d)), _dp(_vec(u)), _dp(wi), _dp(wm),
       _dp(w), _dp(p))
     return wi, wm, float(w[0]), float(p[0])
+
+
+def _sym(c6) -> np.ndarray:
+    xx, xy, xz, yy, yz, zz = c6
+    return np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]])
+
+
+def _six(S) -> np.ndarray:
+    S = np.asarray(S, np.float64)
+    return _vec([S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]])
+
+
+def sigma_proj_cov(G, Sigma, d) -> float:
+    """E[max(0, -d.g)] for g ~ N(G, Sigma) with a full 3x3 covariance."""
+    return lib().oracle_sigma_proj_cov(_dp(_vec(G)), _dp(_six(Sigma)), _dp(_vec(d)))
+
+
+def ndf_cov(G, Sigma, wm) -> float:
+    """Generalized NDF int_0^inf r^3 N(r wm; G, Sigma) dr with a full 3x3 covariance."""
+    return lib().oracle_ndf_cov(_dp(_vec(G)), _dp(_six(Sigma)), _dp(_vec(wm)))
 
 
 def fresnel_conductor(c: float, eta: float, k: float) -> float:
