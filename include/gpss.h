@@ -100,6 +100,19 @@ typedef struct {
     /* conductor Fresnel term (Eq. phase): index of refraction eta + i k of the microflakes;
      * F = albedo x Fresnel reflectance at the half vector.  eta = 0: F = albedo. */
     float fresnel_eta, fresnel_k;
+    /* GP conditioned on point observations (Sec. 3.1, Eq. condition_gp): n_obs (0..32) rows of
+     * (x, y, z, observed value) taken with independent Gaussian noise of variance obs_noise > 0,
+     * which adds obs_noise I to kappa(C, C) (a zero noise, the equation as printed, would let
+     * the posterior variance vanish at the observations and the density become singular).
+     * The medium is then the conditioned GP's: f(x) ~ N(mu_C, kappa_C(x, x)), and the gradient
+     * given f(x) = 0 has the posterior's full 3x3 covariance (Eq. joint_fg conditioned the same
+     * way).  Needs a scalar variance, no mean offset grid, the isotropic kernel and the
+     * generalized NDF.  Rendered by the persistent kernel; GPSS_KERNEL_MEGA and _WAVEFRONT,
+     * gpss_render_batch, gpss_render_adjoint, gpss_scene_set_params and gpss_debug_trace return
+     * GPSS_ERR_UNSUPPORTED for such a scene.  n_obs = 0: the unconditioned GP. */
+    const float* observations;
+    uint32_t n_obs;
+    float obs_noise;
 } gpss_scene_desc;
 
 /* Create a scene: validates `desc`, uploads primitives and grids, and builds the

@@ -1207,7 +1207,8 @@ int oracle_scene_create(const oracle_scene_desc* D, oracle_scene** out) {
     if (D->n_obs < 0 || (D->n_obs > 0 && !D->observations)) return -1;
     if (D->n_obs > 0) {
         // conditioning is defined here for a scalar-variance, isotropic, generalized macrofacet
-        if (!(D->obs_noise > 0.0) || !std::isfinite(D->obs_noise) || D->var_grid || D->ndf_kind != 0) return -1;
+        if (!(D->obs_noise > 0.0) || !std::isfinite(D->obs_noise) || D->var_grid || D->offset || D->ndf_kind != 0)
+            return -1;
         if (D->lengthscale_n > 0.0 && D->lengthscale_n != D->lengthscale) return -1;
     }
     auto* S = new oracle_scene();

@@ -145,6 +145,8 @@ using gpss::kQNum;
 
 namespace {
 
+int upload(const float* src, size_t n, float** dst);
+
 int validate_desc(const gpss_scene_desc* D) {
     if (!D) return set_error(GPSS_ERR_INVALID_ARG, "desc is NULL");
     if (D->struct_size != sizeof(gpss_scene_desc))
@@ -225,7 +227,117 @@ int validate_desc(const gpss_scene_desc* D) {
         return set_error(GPSS_ERR_INVALID_ARG, "resolution");
     if (D->spp < 1) return set_error(GPSS_ERR_INVALID_ARG, "spp must be >= 1");
     if (D->max_depth > 65534) return set_error(GPSS_ERR_INVALID_ARG, "max_depth > 65534");
+    if (D->n_obs > 0) {
+        if (D->n_obs > (uint32_t)gpss::kMaxObs)
+            return set_error(GPSS_ERR_INVALID_ARG, "n_obs %u > %d", D->n_obs, gpss::kMaxObs);
+        if (!D->observations) return set_error(GPSS_ERR_INVALID_ARG, "observations is NULL");
+        if (!finite3(D->observations, 4 * (int)D->n_obs)) return set_error(GPSS_ERR_INVALID_ARG, "observations not finite");
+        if (!(D->obs_noise > 0.0f) || !std::isfinite(D->obs_noise))
+            return set_error(GPSS_ERR_INVALID_ARG, "obs_noise must be > 0");
+        if (D->variance_grid || D->mean_offset || D->ndf_kind != GPSS_NDF_GENERALIZED ||
+            (D->lengthscale_n > 0.0f && D->lengthscale_n != D->lengthscale))
+            return set_error(GPSS_ERR_UNSUPPORTED, "conditioning takes a scalar variance, no mean offset grid, the "
+                                                   "isotropic kernel and the generalized NDF");
+    }
     return GPSS_OK;
+}
+
+// Host SDF of one primitive row (kind, cx, cy, cz, a, b, c, albedo) in double.
+double sdf_prim_host(const float* p, const double x[3]) {
+    const double v[3] = {x[0] - (double)p[1], x[1] - (double)p[2], x[2] - (double)p[3]};
+    if (p[0] == 0.0f) return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - (double)p[4];
+    const double q[3] = {std::fabs(v[0]) - (double)p[4], std::fabs(v[1]) - (double)p[5], std::fabs(v[2]) - (double)p[6]};
+    const double qmax = std::fmax(q[0], std::fmax(q[1], q[2]));
+    if (qmax > 0.0) {
+        const double a = std::fmax(q[0], 0.0), b = std::fmax(q[1], 0.0), c = std::fmax(q[2], 0.0);
+        return std::sqrt(a * a + b * b + c * c);
+    }
+    return qmax;
+}
+
+// Conditioning on point observations (Eq. condition_gp), prepared once in double:
+// K = kappa(C, C) + s_n^2 I = L L^T, alpha = K^-1 (m - mu(C)) and L^-1.  The device takes
+// (position - origin, alpha) and L^-1 (padded to kMaxObs x kMaxObs) in single precision, the
+// majorant kernel positions, alpha and L^-1 in double.
+int prepare_observations(gpss_scene* s, const gpss_scene_desc& D) {
+    const int n = (int)D.n_obs;
+    const double s2 = D.variance, l = D.lengthscale, noise = D.obs_noise;
+    std::vector<double> X(3 * n), m(n), K((size_t)n * n), Li((size_t)n * n, 0.0), alpha(n);
+    for (int j = 0; j < n; ++j) {
+        for (int a = 0; a < 3; ++a) X[3 * j + a] = D.observations[4 * j + a];
+        m[j] = D.observations[4 * j + 3];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) d2 += (X[3 * i + a] - X[3 * j + a]) * (X[3 * i + a] - X[3 * j + a]);
+            K[(size_t)i * n + j] = s2 * std::exp(-d2 / (2.0 * l * l)) + (i == j ? noise : 0.0);
+        }
+    // Cholesky (lower) in place
+    for (int j = 0; j < n; ++j) {
+        double d = K[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= K[(size_t)j * n + k] * K[(size_t)j * n + k];
+        if (!(d > 0.0)) return set_error(GPSS_ERR_INVALID_ARG, "observation covariance not positive definite");
+        d = std::sqrt(d);
+        K[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double v = K[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= K[(size_t)i * n + k] * K[(size_t)j * n + k];
+            K[(size_t)i * n + j] = v / d;
+        }
+    }
+    // L^-1 column by column (forward substitution on unit vectors)
+    for (int c = 0; c < n; ++c)
+        for (int i = c; i < n; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) v -= K[(size_t)i * n + k] * Li[(size_t)k * n + c];
+            Li[(size_t)i * n + c] = v / K[(size_t)i * n + i];
+        }
+    // residuals m - mu(C) of the prior mean, then alpha = L^-T L^-1 r
+    for (int j = 0; j < n; ++j) {
+        const double* x = &X[3 * j];
+        double mu = 0.0;
+        if (D.mean_kind == GPSS_MEAN_PLANE) {
+            mu = x[2];
+        } else if (D.mean_kind == GPSS_MEAN_CONST) {
+            mu = D.mean_const;
+        } else {
+            mu = INFINITY;
+            for (uint32_t i = 0; i < D.n_prims; ++i) mu = std::fmin(mu, sdf_prim_host(D.prims + 8 * i, x));
+        }
+        alpha[j] = m[j] - mu;
+    }
+    std::vector<double> y(n);
+    for (int i = 0; i < n; ++i) {
+        double v = 0.0;
+        for (int k = 0; k <= i; ++k) v += Li[(size_t)i * n + k] * alpha[k];
+        y[i] = v;
+    }
+    for (int i = 0; i < n; ++i) {
+        double v = 0.0;
+        for (int k = i; k < n; ++k) v += Li[(size_t)k * n + i] * y[k];
+        alpha[i] = v;
+    }
+    float origin[3];
+    for (int a = 0; a < 3; ++a) origin[a] = 0.5f * (D.bounds[a] + D.bounds[3 + a]);
+    std::vector<float> F(4 * gpss::kMaxObs + gpss::kMaxObs * gpss::kMaxObs, 0.0f);
+    for (int j = 0; j < n; ++j) {
+        for (int a = 0; a < 3; ++a) F[4 * j + a] = D.observations[4 * j + a] - origin[a];
+        F[4 * j + 3] = (float)alpha[j];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) F[4 * gpss::kMaxObs + i * gpss::kMaxObs + j] = (float)Li[(size_t)i * n + j];
+    std::vector<double> Dd;
+    Dd.insert(Dd.end(), X.begin(), X.end());
+    Dd.insert(Dd.end(), alpha.begin(), alpha.end());
+    Dd.insert(Dd.end(), Li.begin(), Li.end());
+    int rc = upload(F.data(), F.size(), &s->d_obs);
+    if (!rc) rc = check_hip(hipMalloc(&s->d_obs_d, Dd.size() * sizeof(double)), "hipMalloc(observations)");
+    if (!rc)
+        rc = check_hip(hipMemcpy(s->d_obs_d, Dd.data(), Dd.size() * sizeof(double), hipMemcpyHostToDevice),
+                       "hipMemcpy observations");
+    for (int a = 0; a < 3; ++a) s->dev.obs_c[a] = origin[a];
+    return rc;
 }
 
 int upload(const float* src, size_t n, float** dst) {
@@ -240,6 +352,8 @@ void free_scene(gpss_scene* s) {
     (void)hipFree(s->d_offset);
     (void)hipFree(s->d_var);
     (void)hipFree(s->d_maj);
+    (void)hipFree(s->d_obs);
+    (void)hipFree(s->d_obs_d);
     (void)hipFree(s->d_scratch);
     (void)hipFree(s->wf_mem);
     (void)hipFree(s->d_head);
@@ -269,6 +383,9 @@ void fill_dev(gpss_scene* s) {
     V.ggx = D.ndf_kind == GPSS_NDF_GGX;
     V.f_eta = D.fresnel_eta;
     V.f_k = D.fresnel_k;
+    V.n_obs = (int)D.n_obs;
+    V.obs = reinterpret_cast<const float4*>(s->d_obs);
+    V.obs_linv = s->d_obs ? s->d_obs + 4 * gpss::kMaxObs : nullptr;
     V.albedo = D.albedo;
     V.albedo_per_prim = D.albedo_per_prim ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
@@ -363,11 +480,13 @@ int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out) {
             s->var_h.assign(D.variance_grid, D.variance_grid + n);
             rc = upload(s->var_h.data(), n, &s->d_var);
         }
+        if (!rc && D.n_obs > 0) rc = prepare_observations(s, D);
         const size_t nmaj = (size_t)D.majorant_res[0] * D.majorant_res[1] * D.majorant_res[2];
         if (!rc) rc = check_hip(hipMalloc(&s->d_maj, nmaj * sizeof(float)), "hipMalloc(majorants)");
         s->desc.prims = nullptr;
         s->desc.mean_offset = nullptr;
         s->desc.variance_grid = nullptr;
+        s->desc.observations = nullptr;
         if (!rc) {
             fill_dev(s);
             rc = gpss::launch_majorants(s, nullptr);
@@ -443,6 +562,8 @@ int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1, 
 int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, float variance, float lengthscale,
                           float albedo, gpss_stream_t stream) {
     if (!scene) return set_error(GPSS_ERR_INVALID_ARG, "scene is NULL");
+    if (scene->dev.n_obs > 0)
+        return set_error(GPSS_ERR_UNSUPPORTED, "parameters of a conditioned GP are fixed at creation");
     if (mean_offset_dev && !scene->d_offset)
         return set_error(GPSS_ERR_INVALID_ARG, "scene has no mean-offset grid");
     if (!(variance > 0.0f) || !std::isfinite(variance)) return set_error(GPSS_ERR_INVALID_ARG, "variance must be > 0");
@@ -475,9 +596,9 @@ int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float
     if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
     if (scene->d_offset && !grad_offset_dev)
         return set_error(GPSS_ERR_INVALID_ARG, "scene has a mean-offset grid: grad_offset_dev is required");
-    if (scene->dev.aniso_k != 0.0f || scene->dev.ggx)
-        return set_error(GPSS_ERR_UNSUPPORTED,
-                         "the adjoint supports the generalized macrofacet with the isotropic kernel only");
+    if (scene->dev.aniso_k != 0.0f || scene->dev.ggx || scene->dev.n_obs > 0)
+        return set_error(GPSS_ERR_UNSUPPORTED, "the adjoint supports the unconditioned generalized macrofacet "
+                                               "with the isotropic kernel only");
     return gpss::launch_adjoint(scene, dloss_dimage_dev, grad_offset_dev, grad_scalars_dev, s0, s1 - s0,
                                 reinterpret_cast<hipStream_t>(stream));
 }

@@ -316,6 +316,8 @@ static int validate_batch(gpss_scene* const* scenes, uint32_t n, float* const* i
         if (!scenes[i] || !images[i]) return set_error(GPSS_ERR_INVALID_ARG, "NULL scene or image %u", i);
         if (scenes[i]->device != scenes[0]->device)
             return set_error(GPSS_ERR_INVALID_ARG, "scenes of one batch must share a device");
+        if (scenes[i]->dev.n_obs > 0)
+            return set_error(GPSS_ERR_UNSUPPORTED, "scene %u is a conditioned GP: render it with gpss_render", i);
     }
     return GPSS_OK;
 }

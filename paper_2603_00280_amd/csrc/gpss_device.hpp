@@ -20,6 +20,7 @@ constexpr float kInv2PiPow1p5 = 0.06349363593424096978f;   // (2 pi)^(-3/2)
 constexpr float kSqrt2 = 1.41421356237309504880f;
 
 constexpr int kMaxPrims = 64;
+constexpr int kMaxObs = 32;                 // observations of a conditioned GP
 constexpr int kStepCap = 1 << 16;           // tentative collisions per segment
 constexpr float kRRThreshold = 0.0625f;     // shadow-ray Russian roulette below this transmittance
 
@@ -44,6 +45,10 @@ struct SceneDev {
     float aniso_k;                // (l / l_n)^2 - 1 for lengthscale l_n along the mean gradient; 0: isotropic
     int ggx;                      // GGX height-field macrofacet instead of the generalized one
     float f_eta, f_k;             // conductor IOR eta + i k of the Fresnel term (eta = 0: F = albedo)
+    int n_obs;                    // observations conditioning the GP (0: unconditioned)
+    const float4* obs;            // per observation: position relative to obs_c, weight alpha
+    const float* obs_linv;        // kMaxObs x kMaxObs: inverse Cholesky factor of kappa(C,C) + noise I
+    float obs_c[3];               // origin of the observation positions
     float albedo;
     int albedo_per_prim;
     float lo[3], hi[3];
@@ -282,6 +287,8 @@ struct PointQ {
     float albedo;
     int ggx;        // GGX height-field macrofacet (scene-wide)
     float feta, fk; // conductor Fresnel IOR (scene-wide; feta = 0: none)
+    int cond;       // conditioned GP: G is the gradient mean given f = 0 and L the Cholesky factor
+    float L[6];     // of its covariance (l00, l10, l11, l20, l21, l22)
 };
 
 __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
@@ -306,7 +313,80 @@ __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
     q.feta = S.f_eta;
     q.fk = S.f_k;
     q.albedo = (S.albedo_per_prim && which >= 0) ? S.prims[2 * which + 1].w : S.albedo;
+    q.cond = 0;
     return q;
+}
+
+// GP conditioned on noisy point observations (Sec. 3.1, Eq. condition_gp), applied to the
+// pair (f(x), grad f(x)) whose covariances with f(C) are k_j = kappa(x, x_j) and
+// grad_x k_j = -k_j (x - x_j) / l^2, prior covariance diag(sigma^2, sigma^2 / l^2 I):
+//   mu_C = mu + sum_j alpha_j k_j,   grad mu_C = grad mu - (1/l^2) sum_j alpha_j k_j (x - x_j),
+//   with w = L^-1 k and W_a = L^-1 d k / dx_a (L L^T = kappa(C,C) + noise I):
+//   var_C = sigma^2 - |w|^2,  c = cov(grad f, f) = -W^T w,  Sgg = sigma^2/l^2 I - W^T W.
+// W_a is formed as -(1/l^2) (x_a w - P_a), P_a = sum_j (L^-1)_ij k_j x_ja, so that one pass
+// over the lower triangle of L^-1 (uniform across the wave: scalar loads) gives all four
+// right-hand sides while only k_j is kept per lane, in that lane's column of an LDS array
+// (no lane reads another's column: no barrier).  The gradient given f(x) = 0 (the surface)
+// then has mean grad mu_C - c mu_C / var_C and covariance Sgg - c c^T / var_C, kept as its
+// Cholesky factor; s (used only by the proposal) is the root of a third of its trace.
+// Workgroups of at most kCondBlock threads.
+constexpr int kCondBlock = 256;
+__device__ __forceinline__ void condition_point(const SceneDev& S, float3 x, PointQ& q) {
+    __shared__ float kl[kMaxObs][kCondBlock];
+    const int lt = threadIdx.x;
+    const float il2 = 1.0f / (S.lengthscale * S.lengthscale);
+    const float var = S.variance;
+    const float3 xr = x - f3(S.obs_c[0], S.obs_c[1], S.obs_c[2]);
+    const int n = S.n_obs;
+    float am = 0.0f;
+    float3 amx = f3(0.0f, 0.0f, 0.0f);
+    for (int j = 0; j < n; ++j) {
+        const float4 o = S.obs[j];
+        const float3 d = xr - f3(o.x, o.y, o.z);
+        const float kj = var * expf(-0.5f * il2 * dot(d, d));
+        kl[j][lt] = kj;
+        const float ak = o.w * kj;
+        am += ak;
+        amx = amx + ak * f3(o.x, o.y, o.z);
+    }
+    const float mu = q.mu + am;
+    const float3 gm = q.G - il2 * (am * xr - amx);
+    float ww = 0.0f;
+    float3 c = f3(0.0f, 0.0f, 0.0f);
+    float sxx = 0.0f, sxy = 0.0f, sxz = 0.0f, syy = 0.0f, syz = 0.0f, szz = 0.0f;
+    for (int i = 0; i < n; ++i) {
+        const float* row = S.obs_linv + i * kMaxObs;
+        float w = 0.0f;
+        float3 P = f3(0.0f, 0.0f, 0.0f);
+        for (int j = 0; j <= i; ++j) {
+            const float t = row[j] * kl[j][lt];
+            const float4 o = S.obs[j];
+            w += t;
+            P = P + t * f3(o.x, o.y, o.z);
+        }
+        const float3 W = (-il2) * (w * xr - P);
+        ww += w * w;
+        c = c + w * W;
+        sxx += W.x * W.x; sxy += W.x * W.y; sxz += W.x * W.z;
+        syy += W.y * W.y; syz += W.y * W.z; szz += W.z * W.z;
+    }
+    const float vc = var - ww;
+    const float iv = 1.0f / vc;
+    c = -c;
+    const float sg = var * il2;
+    const float Sxx = sg - sxx - c.x * c.x * iv, Sxy = -sxy - c.x * c.y * iv, Sxz = -sxz - c.x * c.z * iv;
+    const float Syy = sg - syy - c.y * c.y * iv, Syz = -syz - c.y * c.z * iv, Szz = sg - szz - c.z * c.z * iv;
+    const float l00 = sqrtf(Sxx);
+    const float l10 = Sxy / l00, l20 = Sxz / l00;
+    const float l11 = sqrtf(fmaxf(Syy - l10 * l10, 0.0f));
+    const float l21 = (Syz - l20 * l10) / l11;
+    const float l22 = sqrtf(fmaxf(Szz - l20 * l20 - l21 * l21, 0.0f));
+    q.cond = 1;
+    q.mu = mu;
+    q.sigma = sqrtf(vc);
+    q.G = gm - (mu * iv) * c;
+    q.s = sqrtf((Sxx + Syy + Szz) * (1.0f / 3.0f));
+    q.L[0] = l00; q.L[1] = l10; q.L[2] = l11; q.L[3] = l20; q.L[4] = l21; q.L[5] = l22;
 }
 
 // ---------------------------------------------------------------------------
@@ -407,11 +487,46 @@ __device__ __forceinline__ float ndf_ggx(float3 G, float s, float3 wm) {
     return (1.0f / ign) * a2 / (kPi * den * den);
 }
 
-// The medium's projected area and NDF at a point (generalized or GGX macrofacet).
+// Projected area and generalized NDF for g ~ N(G, L L^T) with a full covariance (the
+// conditioned GP): -d.g has mean -d.G and standard deviation |L^T d|; with y = L^-1 wm and
+// u = L^-1 G the NDF's exponent is -(A/2)(t - B/A)^2 - q/2 with A = |y|^2, B = y.u and
+// q = |u x y|^2 / A, so the closed form above holds with k = B / sqrt(A), e^{-|u|^2/2} and the
+// prefactor (2 pi)^(-3/2) / (l00 l11 l22 A^2).
+__device__ __forceinline__ float sigma_proj_chol(float3 G, const float* L, float3 d) {
+    const float3 u = f3(L[0] * d.x + L[1] * d.y + L[3] * d.z, L[2] * d.y + L[4] * d.z, L[5] * d.z);
+    const float sd = sqrtf(dot(u, u));
+    const float m = dot(d, G);
+    const float z = m / sd;
+    const float az = fabsf(z);
+    const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
+    return fmaxf(-m, 0.0f) + sd * ph * (1.0f - az * kSqrtHalfPi * erfcxf(az * kInvSqrt2));
+}
+__device__ __forceinline__ float3 chol_solve3(const float* L, float3 b) {
+    const float y0 = b.x / L[0];
+    const float y1 = (b.y - L[1] * y0) / L[2];
+    return f3(y0, y1, (b.z - L[3] * y0 - L[4] * y1) / L[5]);
+}
+__device__ __forceinline__ float ndf_chol(float3 G, const float* L, float3 wm) {
+    const float3 y = chol_solve3(L, wm), u = chol_solve3(L, G);
+    const float A = dot(y, y);
+    const float k = dot(y, u) * rsqrtf(A);
+    const float3 cr = cross(u, y);
+    const float q = dot(cr, cr) / A;
+    const float pre = kInv2PiPow1p5 / (L[0] * L[2] * L[5] * A * A);
+    const float eG = expf(-0.5f * dot(u, u));
+    const float k2 = k * k, akk = fabsf(k);
+    const float b = (k2 + 2.0f) - kSqrtHalfPi * akk * (k2 + 3.0f) * erfcxf(akk * kInvSqrt2);
+    const float up = k > 0.0f ? kSqrt2Pi * k * (k2 + 3.0f) * expf(-0.5f * q) : 0.0f;
+    return pre * fmaxf(eG * b + up, 0.0f);
+}
+
+// The medium's projected area and NDF at a point (generalized, GGX or conditioned macrofacet).
 __device__ __forceinline__ float sigma_proj_at(const PointQ& q, float3 d) {
+    if (q.cond) return sigma_proj_chol(q.G, q.L, d);
     return q.ggx ? sigma_proj_ggx(q.G, q.s, d) : sigma_proj(q.G, q.s, q.ak, d);
 }
 __device__ __forceinline__ float ndf_at(const PointQ& q, float3 wm) {
+    if (q.cond) return ndf_chol(q.G, q.L, wm);
     return q.ggx ? ndf_ggx(q.G, q.s, wm) : ndf(q.G, q.s, q.ak, wm);
 }
 

@@ -31,6 +31,9 @@ struct MajArgs {
     int ggx;
     float lo[3], hi[3];
     int M[3];
+    int n_obs;                  // conditioned GP: observations (0: none)
+    const double* obs_d;        // 3 n positions, n weights alpha, n x n inverse Cholesky factor
+    double obs_noise;
 };
 
 __device__ double sdf_prim_d(float4 a, float4 b, const double x[3]) {
@@ -60,6 +63,75 @@ __device__ __forceinline__ void node_range(int k, int M, int R, int& lo, int& hi
     hi = (int)((((long long)(k + 1)) * (R - 1) + M - 1) / M);
     lo = max(lo, 0);
     hi = min(hi, R - 1);
+}
+
+// Bound for the GP conditioned on point observations (scalar variance s^2, isotropic
+// kernel), from the prior mean's minimum mu_min, gradient bound gmax and value mu_c at the
+// cell centre c.  With dmin_j, dmax_j the nearest and farthest distances from observation j
+// to the cell and kappa(d) = s^2 e^{-d^2/(2 l^2)}:
+//   mu_C >= mu_min + sum_j alpha_j kappa(alpha_j > 0 ? dmax_j : dmin_j), and
+//   mu_C >= mu_C(c) - h |grad mu_C|max (h the half diagonal), where
+//   |grad mu_C| <= gmax + sum_j |alpha_j| (s^2/l^2) d e^{-d^2/(2l^2)}, d = clamp(l, dmin_j, dmax_j);
+//   s_C <= s;  1/s_C^2 <= 1/s^2 + sum_j e^{-dmin_j^2/l^2} / s_n^2 (f(x_j) = r_j f(x) + e_j with
+//   e_j independent of f(x) and noise >= s_n^2 I), and s_C >= s_C(c) - h s/l (|grad s_C| =
+//   |cov(grad f, f)| / s_C <= s/l by Cauchy-Schwarz);
+//   the conditioned gradient g ~ N(m, Sigma): Sigma <= (s/l)^2 I, |m| <= |grad mu_C| + (s/l)|z|,
+//   so sigma_proj <= |m| + (s/l)/sqrt(2 pi);  rho = r(z)/s_C, r = phi/Phi decreasing,
+//   z >= z_lo = mu_lo / (mu_lo > 0 ? s : s_lo), r(z)|z| <= max(0.3, r(z_lo) max(0, -z_lo)).
+__device__ double cond_bound(const MajArgs& A, const int k[3], const double cw[3], double hdiag,
+                             double mu_min, double gmax, double mu_c) {
+    const int n = A.n_obs;
+    const double* X = A.obs_d;
+    const double* al = A.obs_d + 3 * n;
+    const double* Li = A.obs_d + 4 * n;
+    const double l = (double)A.lengthscale, s2 = (double)A.variance;
+    double c[3], lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (double)A.lo[a] + k[a] * cw[a];
+        hi[a] = (double)A.lo[a] + (k[a] + 1) * cw[a];
+        c[a] = (double)A.lo[a] + (k[a] + 0.5) * cw[a];
+    }
+    double mu_obs = 0.0, g_obs = 0.0, prec = 1.0 / s2, mu_p = mu_c;
+    double kc[kMaxObs];
+#pragma unroll
+    for (int j = 0; j < kMaxObs; ++j) {
+        kc[j] = 0.0;
+        if (j < n) {
+            double dn2 = 0.0, df2 = 0.0, dc2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double x = X[3 * j + a];
+                const double dn = x < lo[a] ? lo[a] - x : (x > hi[a] ? x - hi[a] : 0.0);
+                const double df = fmax(fabs(x - lo[a]), fabs(x - hi[a]));
+                dn2 += dn * dn;
+                df2 += df * df;
+                dc2 += (c[a] - x) * (c[a] - x);
+            }
+            const double a_j = al[j];
+            mu_obs += a_j * s2 * exp(-(a_j > 0.0 ? df2 : dn2) / (2.0 * l * l));
+            const double dd = fmin(fmax(l, sqrt(dn2)), sqrt(df2));
+            g_obs += fabs(a_j) * (s2 / (l * l)) * dd * exp(-dd * dd / (2.0 * l * l));
+            prec += exp(-dn2 / (l * l)) / A.obs_noise;
+            kc[j] = s2 * exp(-dc2 / (2.0 * l * l));
+            mu_p += kc[j] * a_j;
+        }
+    }
+    double ww = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double w = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxObs; ++j) {
+            if (j > i) break;
+            w += Li[i * n + j] * kc[j];
+        }
+        ww += w * w;
+    }
+    const double G1 = gmax + g_obs;
+    const double s_hi = sqrt(s2), sl = s_hi / l;
+    const double mu_lo = fmax(mu_min + mu_obs, mu_p - hdiag * G1);
+    const double s_lo = fmax(1.0 / sqrt(prec), sqrt(fmax(s2 - ww, 0.0)) - hdiag * sl);
+    const double z_lo = mu_lo / (mu_lo > 0.0 ? s_hi : s_lo);
+    const double R = sqrt(2.0 / 3.14159265358979323846) / erfcx(-z_lo / 1.41421356237309504880);
+    return (R * (G1 + sl / 2.50662827463100050242) + sl * fmax(0.3, R * fmax(0.0, -z_lo))) / s_lo;
 }
 
 __global__ void majorant_kernel(MajArgs A, float* __restrict__ out) {
@@ -112,12 +184,14 @@ __global__ void majorant_kernel(MajArgs A, float* __restrict__ out) {
                     vmax = fmax(vmax, v);
                 }
     }
-    double mu_min, gmax;
+    double mu_min, gmax, mu_centre;
     if (A.mean_kind == 0) {
         mu_min = (double)A.lo[2] + k[2] * cw[2];
+        mu_centre = (double)A.lo[2] + (k[2] + 0.5) * cw[2];
         gmax = 1.0;
     } else if (A.mean_kind == 2) {
         mu_min = (double)A.mean_const;
+        mu_centre = mu_min;
         gmax = 0.0;
     } else {
         double c[3];
@@ -125,10 +199,15 @@ __global__ void majorant_kernel(MajArgs A, float* __restrict__ out) {
         double best = INFINITY;
         for (int i = 0; i < A.n_prims; ++i) best = fmin(best, sdf_prim_d(A.prims[2 * i], A.prims[2 * i + 1], c));
         mu_min = best - hdiag;
+        mu_centre = best;
         gmax = 1.0;
     }
     mu_min += off_min;
     gmax += off_g;
+    if (A.n_obs > 0) {   // conditioned GP (no offset grid, scalar variance)
+        out[cell] = (float)quantize_majorant(cond_bound(A, k, cw, hdiag, mu_min, gmax, mu_centre));
+        return;
+    }
     const double smin = sqrt(vmin), smax = sqrt(vmax);
     const double s_max = smax / (double)A.lengthscale;
     const double zr = mu_min / (mu_min > 0.0 ? smax : smin);
@@ -165,6 +244,9 @@ int launch_majorants(gpss_scene* s, hipStream_t stream) {
     // the largest gradient standard deviation: sigma over the smaller of the two lengthscales
     A.lengthscale = D.lengthscale_n > 0.0f ? fminf(D.lengthscale, D.lengthscale_n) : D.lengthscale;
     A.ggx = D.ndf_kind == GPSS_NDF_GGX;
+    A.n_obs = (int)D.n_obs;
+    A.obs_d = s->d_obs_d;
+    A.obs_noise = D.obs_noise;
     const int n = A.M[0] * A.M[1] * A.M[2];
     hipLaunchKernelGGL(majorant_kernel, dim3((n + 127) / 128), dim3(128), 0, stream, A, s->d_maj);
     return check_hip(hipGetLastError(), "majorant_kernel launch");
@@ -238,12 +320,16 @@ __global__ void debug_trace_kernel(SceneDev S, const uint32_t* __restrict__ ids,
 
 int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* out, int kmax,
                        hipStream_t stream) {
+    if (s->dev.n_obs > 0)
+        return set_error(GPSS_ERR_UNSUPPORTED, "debug traces of a conditioned GP are not available");
     hipLaunchKernelGGL(debug_trace_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, s->dev, ids, n, out, kmax);
     return check_hip(hipGetLastError(), "debug_trace_kernel launch");
 }
 
 int launch_render_paths(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns,
                         hipStream_t stream) {
+    if (s->dev.n_obs > 0 && (s->kernel == GPSS_KERNEL_MEGA || s->kernel == GPSS_KERNEL_WAVEFRONT))
+        return set_error(GPSS_ERR_UNSUPPORTED, "a conditioned GP renders with the persistent kernel only");
     if (s->kernel == GPSS_KERNEL_MEGA) return mega_render(s, paths, counters, s0, ns, stream);
     if (s->kernel == GPSS_KERNEL_WAVEFRONT) return wf_render(s, paths, counters, s0, ns, stream);
     return sched_render(s, paths, counters, s0, ns, stream);
@@ -270,13 +356,15 @@ int launch_reduce(gpss_scene* s, const float* paths, float* image, uint32_t ns, 
 // ---------------------------------------------------------------------------
 // Pointwise medium evaluation.
 // ---------------------------------------------------------------------------
+template <bool COND>
 __global__ void eval_kernel(SceneDev S, const float* __restrict__ pts, const float* __restrict__ dirs,
                             float* __restrict__ out, uint64_t n) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float3 x = f3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
     const float3 d = f3(dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]);
-    const PointQ q = eval_point(S, x);
+    PointQ q = eval_point(S, x);
+    if (COND) condition_point(S, x, q);
     const float r = rho_of(q.mu, q.sigma);
     const float sp = sigma_proj_at(q, d);
     float* o = out + 8 * i;
@@ -291,8 +379,12 @@ __global__ void eval_kernel(SceneDev S, const float* __restrict__ pts, const flo
 }
 
 int launch_eval(gpss_scene* s, const float* pts, const float* dirs, float* out, uint64_t n, hipStream_t stream) {
-    hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, s->dev, pts, dirs,
-                       out, n);
+    if (s->dev.n_obs > 0)
+        hipLaunchKernelGGL(eval_kernel<true>, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, s->dev,
+                           pts, dirs, out, n);
+    else
+        hipLaunchKernelGGL(eval_kernel<false>, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, s->dev,
+                           pts, dirs, out, n);
     return check_hip(hipGetLastError(), "eval_kernel launch");
 }
 

@@ -63,10 +63,12 @@ int sched_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, u
     if (counters) {
         if (med == kMedGgx) GPSS_SCHED_LAUNCH(true, kMedGgx);
         else if (med == kMedAniso) GPSS_SCHED_LAUNCH(true, kMedAniso);
+        else if (med == kMedCond) GPSS_SCHED_LAUNCH(true, kMedCond);
         else GPSS_SCHED_LAUNCH(true, kMedIso);
     } else {
         if (med == kMedGgx) GPSS_SCHED_LAUNCH(false, kMedGgx);
         else if (med == kMedAniso) GPSS_SCHED_LAUNCH(false, kMedAniso);
+        else if (med == kMedCond) GPSS_SCHED_LAUNCH(false, kMedCond);
         else GPSS_SCHED_LAUNCH(false, kMedIso);
     }
 #undef GPSS_SCHED_LAUNCH

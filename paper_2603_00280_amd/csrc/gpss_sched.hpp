@@ -86,10 +86,10 @@ struct AdjointIo {
 // MED: the scene's medium when the kernel is specialized for it (kMedIso generalized with the
 // isotropic kernel, kMedGgx, kMedAniso generalized with the anisotropic kernel), so that
 // the other media's code is not compiled in; kMedAny takes everything from the scene record.
-enum { kMedAny = -1, kMedIso = 0, kMedGgx = 1, kMedAniso = 2 };
+enum { kMedAny = -1, kMedIso = 0, kMedGgx = 1, kMedAniso = 2, kMedCond = 3 };
 
 __host__ __device__ inline int medium_of(const SceneDev& S) {
-    return S.ggx ? kMedGgx : (S.aniso_k != 0.0f ? kMedAniso : kMedIso);
+    return S.n_obs > 0 ? kMedCond : (S.ggx ? kMedGgx : (S.aniso_k != 0.0f ? kMedAniso : kMedIso));
 }
 
 // Cold per-lane state (touched once per segment or vertex) lives in LDS, one column per
@@ -131,6 +131,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
             q.ggx = MED == kMedGgx;
             if (MED != kMedAniso) q.ak = 0.0f;
         }
+        if (MED == kMedCond) condition_point(S, x, q);
         return q;
     };
     auto finish = [&](float L) {   // the path's radiance to its output slot; the lane falls idle

@@ -56,6 +56,7 @@ class gpss_scene_desc(C.Structure):
         ("width", C.c_uint32), ("height", C.c_uint32), ("spp", C.c_uint32), ("max_depth", C.c_uint32),
         ("seed", C.c_uint64), ("scene_id", C.c_uint32), ("lengthscale_n", C.c_float),
         ("ndf_kind", C.c_int32), ("fresnel_eta", C.c_float), ("fresnel_k", C.c_float),
+        ("observations", C.POINTER(C.c_float)), ("n_obs", C.c_uint32), ("obs_noise", C.c_float),
     ]
 
 
@@ -159,6 +160,13 @@ def make_desc(scene):
     d.ndf_kind = int(getattr(scene, "ndf_kind", 0))
     d.fresnel_eta = float(getattr(scene, "fresnel_eta", 0.0))
     d.fresnel_k = float(getattr(scene, "fresnel_k", 0.0))
+    obs = getattr(scene, "observations", None)
+    if obs is not None and len(obs):
+        obs = np.ascontiguousarray(obs, np.float32).reshape(-1, 4)
+        keep.append(obs)
+        d.observations = _fp(obs)
+        d.n_obs = obs.shape[0]
+        d.obs_noise = float(scene.obs_noise)
     return d, keep
 
 

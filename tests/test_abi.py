@@ -96,3 +96,20 @@ def test_null_arguments_are_rejected():
     assert L.gpss_render_paths(None, None, None, 0, 1, None) == gpss.GPSS_ERR_INVALID_ARG
     assert L.gpss_scene_destroy(None) == gpss.GPSS_ERR_INVALID_ARG
     assert L.gpss_scene_get_majorants(None, None, 0) == gpss.GPSS_ERR_INVALID_ARG
+
+
+def test_invalid_observations_are_rejected():
+    s = sc.cond_sphere_scene(n_obs=4, width=8, height=8)
+    rc, msg = _create(s.replace(obs_noise=0.0))
+    assert rc == gpss.GPSS_ERR_INVALID_ARG and "obs_noise" in msg
+    many = np.zeros((sc.MAX_OBSERVATIONS + 1, 4), np.float32)
+    rc, msg = _create(s.replace(observations=many))
+    assert rc == gpss.GPSS_ERR_INVALID_ARG and "n_obs" in msg
+    bad = s.observations.copy()
+    bad[2, 1] = np.inf
+    rc, msg = _create(s.replace(observations=bad))
+    assert rc == gpss.GPSS_ERR_INVALID_ARG and "observations" in msg
+    for kw in (dict(variance_grid=np.full((2, 2, 2), 0.0025, np.float32)), dict(ndf_kind=sc.NDF_GGX),
+               dict(lengthscale_n=0.05), dict(offset_grid=np.zeros((2, 2, 2), np.float32))):
+        rc, msg = _create(s.replace(**kw))
+        assert rc == gpss.GPSS_ERR_UNSUPPORTED and "conditioning" in msg
