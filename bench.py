@@ -33,6 +33,9 @@ WORKLOADS = {
              "directional light 30 deg, ortho 64x64 at 45 deg, 16 spp, max depth 8",
     "mixed": "union SDF of 16 seeded spheres/boxes, 128^3 value-noise variance grid in "
              "[1e-4,1e-2], lengthscale 0.03, 1024x1024, 256 spp, max depth 64",
+    "cond": "unit-sphere SDF prior conditioned on 32 noisy point observations (Fibonacci directions, "
+            "radii jittered +-0.08, value 0, noise 0.05 x variance), variance 0.0025, lengthscale 0.25, "
+            "pinhole 512x512, 64 spp, max depth 32",
 }
 
 
@@ -137,6 +140,8 @@ def make_scenes(name):
         return [sc.plane_scene()]
     if name == "mixed":
         return [sc.mixed_scene()]
+    if name == "cond":
+        return [sc.cond_sphere_scene()]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -159,6 +164,38 @@ def cpu_baseline(scenes, spp: int):
     return {"value": n / dt / 1e6, "unit": "Mpaths/s", "cores": cores, "kind": "oracle",
             "sample": f"all pixels of each scene at {spp} spp ({n} paths, {dt:.1f} s)",
             "cpu": platform.processor() or platform.machine()}
+
+
+def cond_measurement(torch, gpss, steps: int = 2):
+    """The GP conditioned on 32 observations (sphere prior, 512^2, 64 spp): Mpaths/s and the
+    roofline entry of its render kernel (algorithmic FLOPs / launch time on the render stream)."""
+    from gpss_inputs import scenes as sc
+    from paper_2603_00280_amd import flops
+    s = sc.cond_sphere_scene()
+    g = gpss.GpssScene(s)
+    img = torch.empty(s.height, s.width, dtype=torch.float32, device="cuda")
+    _, cnt = g.render_paths(counters=True)
+    torch.cuda.synchronize()
+    fl = flops.flops_from_counters(s, gpss.counters_dict(cnt))
+    g.render(out=img)
+    stream = torch.cuda.current_stream()
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.render(out=img)
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    rate = fl / (ms / 1e3) / 1e12
+    return {"workload": "cond: " + WORKLOADS["cond"], "value": steps * s.n_paths / wall / 1e6,
+            "unit": "Mpaths/s", "avg_launch_ms": ms,
+            "roofline": {"bound": "alu", "achieved": rate, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": rate / FP32_PEAK_TFLOPS, "traffic": None, "flops_per_launch": fl}}
 
 
 def adjoint_measurement(torch, gpss):
@@ -239,6 +276,8 @@ def main():
                     help="skip the adjoint measurement on the offset-sphere workload")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-render measurement on the 64-scene workload")
+    ap.add_argument("--no-cond", action="store_true",
+                    help="skip the measurement of the GP conditioned on point observations")
     ap.add_argument("--tune", action="store_true",
                     help="run the batch autotuner first (its choice is cached on disk)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -353,6 +392,9 @@ def main():
     if not args.no_adjoint:
         print("[bench] adjoint", file=sys.stderr, flush=True)
         result["adjoint"] = adjoint_measurement(torch, gpss)
+    if not args.no_cond and args.workload != "cond":
+        print("[bench] conditioned GP", file=sys.stderr, flush=True)
+        result["conditioned"] = cond_measurement(torch, gpss)
     if not args.no_batch:
         print("[bench] batch", file=sys.stderr, flush=True)
         result["batch"] = batch_measurement(torch, gpss, args.tune)

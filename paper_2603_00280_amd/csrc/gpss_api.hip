@@ -320,13 +320,20 @@ int prepare_observations(gpss_scene* s, const gpss_scene_desc& D) {
     }
     float origin[3];
     for (int a = 0; a < 3; ++a) origin[a] = 0.5f * (D.bounds[a] + D.bounds[3 + a]);
-    std::vector<float> F(4 * gpss::kMaxObs + gpss::kMaxObs * gpss::kMaxObs, 0.0f);
+    // kMaxObs float4 (position - origin, alpha), then the lower triangle of L^-1 row by row as
+    // float4 (L^-1_ij, L^-1_ij (x_j - origin)), formed in double and rounded once
+    std::vector<float> F(4 * gpss::kMaxObs + 4 * (size_t)gpss::kMaxObs * (gpss::kMaxObs + 1) / 2, 0.0f);
     for (int j = 0; j < n; ++j) {
         for (int a = 0; a < 3; ++a) F[4 * j + a] = D.observations[4 * j + a] - origin[a];
         F[4 * j + 3] = (float)alpha[j];
     }
+    size_t e = 4 * gpss::kMaxObs;
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j <= i; ++j) F[4 * gpss::kMaxObs + i * gpss::kMaxObs + j] = (float)Li[(size_t)i * n + j];
+        for (int j = 0; j <= i; ++j, e += 4) {
+            const double v = Li[(size_t)i * n + j];
+            F[e] = (float)v;
+            for (int a = 0; a < 3; ++a) F[e + 1 + a] = (float)(v * ((double)D.observations[4 * j + a] - (double)origin[a]));
+        }
     std::vector<double> Dd;
     Dd.insert(Dd.end(), X.begin(), X.end());
     Dd.insert(Dd.end(), alpha.begin(), alpha.end());
@@ -385,7 +392,7 @@ void fill_dev(gpss_scene* s) {
     V.f_k = D.fresnel_k;
     V.n_obs = (int)D.n_obs;
     V.obs = reinterpret_cast<const float4*>(s->d_obs);
-    V.obs_linv = s->d_obs ? s->d_obs + 4 * gpss::kMaxObs : nullptr;
+    V.obs_tri = s->d_obs ? reinterpret_cast<const float4*>(s->d_obs + 4 * gpss::kMaxObs) : nullptr;
     V.albedo = D.albedo;
     V.albedo_per_prim = D.albedo_per_prim ? 1 : 0;
     for (int a = 0; a < 3; ++a) {

@@ -47,7 +47,8 @@ struct SceneDev {
     float f_eta, f_k;             // conductor IOR eta + i k of the Fresnel term (eta = 0: F = albedo)
     int n_obs;                    // observations conditioning the GP (0: unconditioned)
     const float4* obs;            // per observation: position relative to obs_c, weight alpha
-    const float* obs_linv;        // kMaxObs x kMaxObs: inverse Cholesky factor of kappa(C,C) + noise I
+    const float4* obs_tri;        // lower triangle of L^-1 (L L^T = kappa(C,C) + noise I), row by row:
+                                  // (L^-1_ij, L^-1_ij x_j) for j <= i, positions relative to obs_c
     float obs_c[3];               // origin of the observation positions
     float albedo;
     int albedo_per_prim;
@@ -323,10 +324,11 @@ __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
 //   mu_C = mu + sum_j alpha_j k_j,   grad mu_C = grad mu - (1/l^2) sum_j alpha_j k_j (x - x_j),
 //   with w = L^-1 k and W_a = L^-1 d k / dx_a (L L^T = kappa(C,C) + noise I):
 //   var_C = sigma^2 - |w|^2,  c = cov(grad f, f) = -W^T w,  Sgg = sigma^2/l^2 I - W^T W.
-// W_a is formed as -(1/l^2) (x_a w - P_a), P_a = sum_j (L^-1)_ij k_j x_ja, so that one pass
-// over the lower triangle of L^-1 (uniform across the wave: scalar loads) gives all four
-// right-hand sides while only k_j is kept per lane, in that lane's column of an LDS array
-// (no lane reads another's column: no barrier).  The gradient given f(x) = 0 (the surface)
+// W_a is formed as -(1/l^2) (x_a w - P_a), P_a = sum_j (L^-1_ij x_ja) k_j, so that one pass
+// over the lower triangle of L^-1 gives all four right-hand sides with four FMAs per entry,
+// the entry's (L^-1_ij, L^-1_ij x_j) being one wave-uniform float4 (a scalar load), while only
+// k_j is kept per lane, in that lane's column of an LDS array (no lane reads another's
+// column: no barrier).  The gradient given f(x) = 0 (the surface)
 // then has mean grad mu_C - c mu_C / var_C and covariance Sgg - c c^T / var_C, kept as its
 // Cholesky factor; s (used only by the proposal) is the root of a third of its trace.
 // Workgroups of at most kCondBlock threads.
@@ -354,16 +356,20 @@ __device__ __forceinline__ void condition_point(const SceneDev& S, float3 x, Poi
     float ww = 0.0f;
     float3 c = f3(0.0f, 0.0f, 0.0f);
     float sxx = 0.0f, sxy = 0.0f, sxz = 0.0f, syy = 0.0f, syz = 0.0f, szz = 0.0f;
+    const float4* row = S.obs_tri;
     for (int i = 0; i < n; ++i) {
-        const float* row = S.obs_linv + i * kMaxObs;
         float w = 0.0f;
         float3 P = f3(0.0f, 0.0f, 0.0f);
+#pragma unroll 4
         for (int j = 0; j <= i; ++j) {
-            const float t = row[j] * kl[j][lt];
-            const float4 o = S.obs[j];
-            w += t;
-            P = P + t * f3(o.x, o.y, o.z);
+            const float4 b = row[j];
+            const float kj = kl[j][lt];
+            w = fmaf(b.x, kj, w);
+            P.x = fmaf(b.y, kj, P.x);
+            P.y = fmaf(b.z, kj, P.y);
+            P.z = fmaf(b.w, kj, P.z);
         }
+        row += i + 1;
         const float3 W = (-il2) * (w * xr - P);
         ww += w * w;
         c = c + w * W;

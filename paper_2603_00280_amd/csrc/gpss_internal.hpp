@@ -35,7 +35,7 @@ struct gpss_scene {
     float* d_offset = nullptr;
     float* d_var = nullptr;
     float* d_maj = nullptr;
-    float* d_obs = nullptr;            // conditioned GP: kMaxObs float4 (position, alpha) + kMaxObs^2 L^-1
+    float* d_obs = nullptr;            // conditioned GP: kMaxObs float4 (position, alpha) + packed L^-1 rows
     double* d_obs_d = nullptr;         // the same in double for the majorant: 3n positions, n alpha, n x n L^-1
     float* d_scratch = nullptr;        // per-path radiance of the last render
     size_t scratch_floats = 0;

@@ -18,6 +18,13 @@ Per-event counts:
               inversion (about five Newton steps of 15), slope to normal (15), mixture
               pdf (30), NDF (35), projected area (20), weight (5), reflection (15)
   NEE         light connection: light direction and box clip (32), phase evaluation (70)
+
+A GP conditioned on n observations adds, per point evaluation, the posterior of value and
+gradient: per observation the kernel value, the mean and mean-gradient terms (20) and the
+per-row closing of the triangular solve (29), 8 per entry of the lower triangle of the
+inverse Cholesky factor (n (n + 1) / 2 entries), and the gradient covariance given f = 0
+with its 3x3 Cholesky factor (55); its projected area (+12) and NDF (+30, two 3x3
+triangular solves) cost a little more than the isotropic forms.
 """
 
 # point statistics cost by mean kind: sphere SDF per primitive, box SDF per primitive,
@@ -38,8 +45,23 @@ REAL = 30 + 75 + 15 + 30 + 35 + 20 + 5 + 15
 NEE = 32 + 70
 
 
+COND_PER_OBS = 20 + 29
+COND_PER_PAIR = 8
+COND_BASE = 55
+COND_PROJ = 12
+COND_NDF = 30
+
+
+def n_observations(scene) -> int:
+    obs = getattr(scene, "observations", None)
+    return 0 if obs is None else int(len(obs))
+
+
 def point_flops(scene) -> int:
     f = POINT_BASE
+    n = n_observations(scene)
+    if n:
+        f += COND_BASE + COND_PER_OBS * n + COND_PER_PAIR * n * (n + 1) // 2
     if scene.mean_kind == 1:
         import numpy as np
         kinds = np.asarray(scene.prims)[:, 0]
@@ -53,12 +75,13 @@ def point_flops(scene) -> int:
 
 def per_event(scene) -> dict:
     p = point_flops(scene)
+    cp, cn = (COND_PROJ, COND_NDF) if n_observations(scene) else (0, 0)
     return {
-        "track_steps": TRACK_EXTRA + p + DENSITY + PROJ,
-        "nee_steps": NEE_EXTRA + p + DENSITY + PROJ,
+        "track_steps": TRACK_EXTRA + p + DENSITY + PROJ + cp,
+        "nee_steps": NEE_EXTRA + p + DENSITY + PROJ + cp,
         "cells": CELL,
-        "phase": REAL + p,
-        "nee": NEE,
+        "phase": REAL + p + cp + cn,
+        "nee": NEE + cn,
     }
 
 
