@@ -88,7 +88,7 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
                     vals.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
         return [v for _, v in sorted(vals)]
 
-    kern = "sched_render_kernel<false>"
+    kern = "sched_render_kernel<false, 0>"
     fetch = per_dispatch(fetch_dir, "FETCH_SIZE", kern)
     write = per_dispatch(write_dir, "WRITE_SIZE", kern)
     cf = per_dispatch(copy_fetch_dir, "FETCH_SIZE", "copy")
