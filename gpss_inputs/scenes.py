@@ -213,6 +213,10 @@ def fresnel_rgb_scenes(scene: Scene, metal: str = "gold") -> list:
 # Observation noise is obs_noise_frac x the kernel variance.
 # ---------------------------------------------------------------------------
 MAX_OBSERVATIONS = 32
+# The conditioned majorant is looser per cell than the unconditioned one (it bounds the
+# posterior's mean, spread and gradient over the cell); a finer grid pays for itself because a
+# posterior evaluation costs about a hundred cell crossings.
+COND_MAJORANT_RES = (128, 128, 128)
 
 
 def fibonacci_directions(n: int) -> np.ndarray:
@@ -226,6 +230,7 @@ def fibonacci_directions(n: int) -> np.ndarray:
 def cond_sphere_scene(n_obs: int = 32, jitter: float = 0.08, lengthscale: float = 0.25,
                       variance: float = 0.0025, obs_noise_frac: float = 0.05, obs_seed: int = 6,
                       **kw) -> Scene:
+    kw.setdefault("majorant_res", COND_MAJORANT_RES)
     rng = np.random.default_rng(obs_seed)
     dirs = fibonacci_directions(n_obs)
     rad = 1.0 + rng.uniform(-jitter, jitter, n_obs)
@@ -238,7 +243,7 @@ def cond_sphere_scene(n_obs: int = 32, jitter: float = 0.08, lengthscale: float 
 def cond_blob_scene(n_surface: int = 26, axes=(0.6, 0.45, 0.35), lengthscale: float = 0.3,
                     variance: float = 0.04, obs_noise_frac: float = 0.05, width: int = 512,
                     height: int = 512, spp: int = 64, max_depth: int = 32, seed: int = 7,
-                    majorant_res=(64, 64, 64)) -> Scene:
+                    majorant_res=COND_MAJORANT_RES) -> Scene:
     ax = np.asarray(axes, np.float64)
     surf = fibonacci_directions(n_surface) * ax
     inner = np.concatenate([np.diag(0.5 * ax), -np.diag(0.5 * ax)])

@@ -773,6 +773,7 @@ void build_majorants(Scene& S) {
     double cwv[3];
     for (int a = 0; a < 3; ++a) cwv[a] = S.ext[a] / S.M[a];
     const double hdiag = 0.5 * std::sqrt(cwv[0] * cwv[0] + cwv[1] * cwv[1] + cwv[2] * cwv[2]);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int kz = 0; kz < S.M[2]; ++kz)
         for (int ky = 0; ky < S.M[1]; ++ky)
             for (int kx = 0; kx < S.M[0]; ++kx) {

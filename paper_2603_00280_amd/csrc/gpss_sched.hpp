@@ -33,6 +33,10 @@ enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBe
 #ifndef GPSS_SCHED_EVAL_MIN
 #define GPSS_SCHED_EVAL_MIN 16
 #endif
+// the conditioned GP's evaluation costs about thirty times the others': it waits for fuller waves
+#ifndef GPSS_SCHED_EVAL_MIN_COND
+#define GPSS_SCHED_EVAL_MIN_COND 48
+#endif
 #ifndef GPSS_SCHED_SCATTER_MIN
 #define GPSS_SCHED_SCATTER_MIN 16
 #endif
@@ -299,7 +303,8 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
 
         // ---- medium evaluation at tentative collisions ----
         bool nee_done = false;
-        if (nEval > 0 && (nEval >= GPSS_SCHED_EVAL_MIN || nWalk == 0)) {
+        constexpr int kEvalMin = MED == kMedCond ? GPSS_SCHED_EVAL_MIN_COND : GPSS_SCHED_EVAL_MIN;
+        if (nEval > 0 && (nEval >= kEvalMin || nWalk == 0)) {
             if (op == kOpEval) {
                 sg.advance();
                 // the generator's key and address words are recomputed here rather than kept

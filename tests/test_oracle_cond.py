@@ -107,7 +107,8 @@ def test_full_cov_projected_area_monte_carlo():
 # Posterior (Eq. condition_gp)
 # ---------------------------------------------------------------------------
 def _sphere_with(obs, noise_frac=0.05, variance=0.0025, lengthscale=0.25):
-    return sc.sphere_scene(lengthscale=lengthscale, variance=variance, width=16, height=16, spp=1).replace(
+    return sc.sphere_scene(lengthscale=lengthscale, variance=variance, width=16, height=16, spp=1,
+                           majorant_res=(16, 16, 16)).replace(
         observations=np.asarray(obs, np.float32), obs_noise=float(noise_frac * variance))
 
 
@@ -212,8 +213,8 @@ def test_posterior_importance_sampling_brute_force():
 def test_posterior_derivative_identities(which):
     """grad mu_C is the derivative of the posterior mean, and c = cov(grad f, f) is half the
     derivative of the posterior variance kappa_C(x, x)."""
-    s = sc.cond_sphere_scene(width=16, height=16, spp=1) if which == "sphere" else \
-        sc.cond_blob_scene(width=16, height=16, spp=1)
+    s = sc.cond_sphere_scene(width=16, height=16, spp=1, majorant_res=(16, 16, 16)) if which == "sphere" else \
+        sc.cond_blob_scene(width=16, height=16, spp=1, majorant_res=(16, 16, 16))
     o = orc.OracleScene(s)
     rng = np.random.default_rng(68)
     obs = s.observations[:, :3].astype(float)
@@ -230,7 +231,7 @@ def test_posterior_derivative_identities(which):
 
 
 def test_posterior_covariance_is_psd_and_below_prior():
-    s = sc.cond_sphere_scene(width=16, height=16, spp=1)
+    s = sc.cond_sphere_scene(width=16, height=16, spp=1, majorant_res=(16, 16, 16))
     o = orc.OracleScene(s)
     s2, l = orc.f32(s.variance), orc.f32(s.lengthscale)
     prior = np.diag([s2, s2 / l ** 2, s2 / l ** 2, s2 / l ** 2])
@@ -265,7 +266,7 @@ def test_far_observations_leave_the_prior():
 
 
 def test_posterior_mean_is_linear_in_the_observed_values():
-    base = sc.cond_sphere_scene(n_obs=8, width=16, height=16, spp=1)
+    base = sc.cond_sphere_scene(n_obs=8, width=16, height=16, spp=1, majorant_res=(16, 16, 16))
     rng = np.random.default_rng(71)
     m1, m2 = rng.normal(scale=0.03, size=8), rng.normal(scale=0.03, size=8)
 
@@ -308,7 +309,7 @@ def test_conditioned_majorant_bounds_sigma_t(which):
 
 
 def test_conditioned_scene_rules():
-    s = sc.cond_sphere_scene(n_obs=4, width=16, height=16, spp=1)
+    s = sc.cond_sphere_scene(n_obs=4, width=16, height=16, spp=1, majorant_res=(16, 16, 16))
     orc.OracleScene(s)
     for bad in (dict(obs_noise=0.0), dict(lengthscale_n=0.05), dict(ndf_kind=sc.NDF_GGX),
                 dict(variance_grid=np.full((2, 2, 2), 0.0025, np.float32))):
