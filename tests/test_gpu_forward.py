@@ -152,3 +152,60 @@ def test_white_furnace_gpu(G):
     ref = orc.OracleScene(s).render()
     tot = img.mean() + ref["trunc"].mean()
     assert abs(tot - 1.0) < 5 * math.sqrt(ref["var"].mean() / (s.spp * s.n_pixels)) + 1e-3
+
+
+def _sphere_small(**kw):
+    return sc.sphere_scene(0.1, width=40, height=40, spp=4, max_depth=8).replace(**kw)
+
+
+def _box_union():
+    s = sc.mixed_scene(width=40, height=40, spp=2, max_depth=16, n_prims=6, var_res=16)
+    p = s.prims.copy()
+    sph = p[:, 0] == sc.PRIM_SPHERE
+    p[sph, 0] = sc.PRIM_BOX
+    p[sph, 5] = p[sph, 4]
+    p[sph, 6] = p[sph, 4]
+    return s.replace(prims=p, name="box_union")
+
+
+DEGENERATE = {
+    # no real scattering allowed: paths end at their first real collision (only escapes count)
+    "depth0": lambda: _sphere_small(max_depth=0),
+    # black medium: light arrives only along paths that escape without a real collision
+    "albedo0": lambda: _sphere_small(albedo=0.0),
+    # camera inside the medium's box and inside the surface (dense interior)
+    "camera_inside": lambda: _sphere_small(cam_eye=(0.0, 0.1, 0.3), cam_target=(0.0, 0.0, -1.0)),
+    # boxes only, per-primitive albedo, variance grid
+    "box_union": _box_union,
+}
+
+
+@pytest.mark.parametrize("name", sorted(DEGENERATE))
+def test_degenerate_scenes_parity(G, name):
+    s = DEGENERATE[name]()
+    _parity(G, s, name)
+
+
+def test_no_light_gives_exact_zero(G):
+    s = _sphere_small(point_light=np.zeros(4, np.float32), env_radiance=0.0)
+    _, img = _render(G, s)
+    assert np.count_nonzero(img) == 0
+
+
+def test_empty_medium_gives_exact_environment(G):
+    """A constant mean far above the shell: every majorant cell rounds to 0 (skipped), so every
+    path escapes at once and sees the environment exactly."""
+    s = _sphere_small().replace(mean_kind=sc.MEAN_CONST, mean_const=50.0, prims=np.zeros((0, 8), np.float32))
+    g, img = _render(G, s)
+    assert np.count_nonzero(g.majorants()) == 0
+    assert np.all(img == np.float32(s.env_radiance))
+    ref = orc.OracleScene(s).render()
+    assert np.all(ref["mean"] == np.float32(s.env_radiance))
+
+
+def test_depth0_equals_albedo0_bitwise(G):
+    """Depth 0 ends each path at its first real collision; albedo 0 zeroes the throughput and
+    every light term there: the same path radiances."""
+    a = G.GpssScene(DEGENERATE["depth0"]()).render().cpu().numpy()
+    b = G.GpssScene(DEGENERATE["albedo0"]()).render().cpu().numpy()
+    assert np.array_equal(a, b)
