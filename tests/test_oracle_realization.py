@@ -1,0 +1,121 @@
+"""Brute-force realization check of the oracle's medium (the GPIS the macrofacet medium
+stands for, Sec. 3.1 and Sec. 4.2.1; Fig. tr).
+
+Realizations of the planar GPSS f = mu + GP(0, kappa) are drawn along one ray by a
+Cholesky factor of the squared-exponential covariance at 1/25-lengthscale steps, and their
+zero crossings are counted.  Exact by Rice's formula: the expected number of down-crossings
+per unit length is p_f(0) E[max(0, -f') | f = 0] = phi(mu; 0, sigma^2) sigma_proj(w) for the
+unconditioned GP (value and gradient independent at a point), i.e. the oracle's
+sigma_t(x, w) Phi(mu / sigma), and the slope -f' at a crossing has density proportional to
+v N(v; -w.grad mu, s^2) for v > 0.  Approximate: the first-crossing transmittance equals the
+medium's exp(-int sigma_t) only at short optical depth (the paper's independence assumption
+across the ray, Sec. 4.2.1, leaves a gap further in); it is compared at depth 3.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import special, stats
+
+from gpss_inputs import scenes as sc
+from oracle import oracle as orc
+
+
+SIGMA = 1.0
+ELL = 1.0
+STEP = ELL / 25.0
+N_REAL = 20000
+Z0 = 4.0 * SIGMA
+
+
+@pytest.fixture(scope="module")
+def realizations():
+    """(N_REAL, n) samples of f along the ray x(t) = (0, 0, Z0) + t w, w at 45 deg downward."""
+    w = np.array([math.sqrt(0.5), 0.0, -math.sqrt(0.5)])
+    t = np.arange(0.0, 8.0 + STEP / 2, STEP)
+    d = t[:, None] - t[None, :]
+    K = SIGMA ** 2 * np.exp(-d * d / (2 * ELL * ELL)) + 1e-9 * np.eye(t.size)
+    L = np.linalg.cholesky(K)
+    rng = np.random.default_rng(81)
+    f = (rng.standard_normal((N_REAL, t.size)) @ L.T) + (Z0 + t * w[2])[None, :]
+    return t, w, f
+
+
+def _scene():
+    # the planar GPSS mu = z with sigma = l = 1 (an unbounded slab for point queries)
+    s = sc.plane_scene(variance=SIGMA ** 2, lengthscale=ELL, half_thickness=8.0, majorant_res=(1, 1, 128))
+    return orc.OracleScene(s.replace(bounds=np.array([-10.0, -10.0, -8.0, 10.0, 10.0, 8.0], np.float32)))
+
+
+def test_rice_down_crossing_rate(realizations):
+    t, w, f = realizations
+    o = _scene()
+    down = (f[:, :-1] > 0) & (f[:, 1:] <= 0)
+    # crossing positions by linear interpolation inside each step
+    frac = f[:, :-1] / (f[:, :-1] - f[:, 1:])
+    tc = (t[:-1][None, :] + frac * STEP)[down]
+    edges = np.arange(2.0, 7.01, 0.5)
+    counts, _ = np.histogram(tc, edges)
+    for k in range(edges.size - 1):
+        a, b = edges[k], edges[k + 1]
+        # expected crossings per realization in [a, b): integral of the oracle's phi * sigma_proj
+        ts = np.linspace(a, b, 41)
+        rate = []
+        for tt in ts:
+            x = np.array([0.0, 0.0, Z0]) + tt * w
+            mu = x[2]
+            rate.append(o.sigma_t(x, w) * special.ndtr(mu / SIGMA))
+        expect = np.trapezoid(rate, ts) * N_REAL
+        assert abs(counts[k] - expect) < 4.0 * math.sqrt(expect) + 2.0, (a, counts[k], expect)
+
+
+def test_slope_at_crossings_is_rice_weighted(realizations):
+    """-f' at down-crossings has density v N(v; m, s^2) / E[max(0, N(m, s^2))] on v > 0, where
+    m = -w.grad mu and s^2 = w^T Sigma w = (sigma/l)^2: the along-ray marginal of the visible
+    normals that the NDF and sigma_proj describe."""
+    t, w, f = realizations
+    down = (f[:, :-1] > 0) & (f[:, 1:] <= 0)
+    v = (-(f[:, 1:] - f[:, :-1]) / STEP)[down]
+    m, s = -w[2] * 1.0, SIGMA / ELL
+    norm = m * special.ndtr(m / s) + s * stats.norm.pdf(m / s)
+    edges = np.quantile(v, np.linspace(0, 1, 21))
+    edges[0], edges[-1] = 0.0, np.inf
+    obs, _ = np.histogram(v, edges)
+
+    def cdf(x):   # integral of y N(y; m, s^2) from 0 to x
+        x = np.minimum(x, 60.0)
+        return (m * (special.ndtr((x - m) / s) - special.ndtr(-m / s))
+                - s * (stats.norm.pdf((x - m) / s) - stats.norm.pdf(-m / s)))
+    p = np.diff([cdf(e) for e in edges]) / norm
+    exp = p * v.size
+    chi2 = float(np.sum((obs - exp) ** 2 / exp))
+    # finite-difference slopes add O(step^2) bias; 19 degrees of freedom
+    assert chi2 < stats.chi2.ppf(0.999, 19), chi2
+
+
+def test_first_crossing_transmittance_short_depth(realizations):
+    t, w, f = realizations
+    o = _scene()
+    k = int(round(3.0 / STEP))
+    alive = np.all(f[:, : k + 1] > 0, axis=1).mean()
+    est = o.ratio_tracking([0.0, 0.0, Z0], w, 3.0, 20000).mean()
+    se = math.sqrt(alive * (1 - alive) / N_REAL)
+    assert abs(alive - est) < 4 * se + 2e-3, (alive, est)
+
+
+def test_first_crossing_transmittance_deep_gap(realizations):
+    """Deeper in, the realizations cross earlier than the medium predicts: the medium treats
+    the next crossing as independent of the segment already travelled (Sec. 4.2.1), while a
+    realization that stayed positive along the ray is correlated with it.  The gap has the
+    documented sign and grows with depth."""
+    t, w, f = realizations
+    o = _scene()
+    gaps = []
+    for depth in (5.0, 7.0):
+        k = int(round(depth / STEP))
+        alive = np.all(f[:, : k + 1] > 0, axis=1).mean()
+        est = o.ratio_tracking([0.0, 0.0, Z0], w, depth, 40000).mean()
+        se = math.sqrt(alive * (1 - alive) / N_REAL) + math.sqrt(est * (1 - est) / 40000)
+        assert alive < est - 3 * se, (depth, alive, est)
+        gaps.append((est - alive) / est)
+    assert gaps[1] > gaps[0]
