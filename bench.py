@@ -161,9 +161,41 @@ def cpu_baseline(scenes, spp: int):
         OracleScene(s).render(0, spp, nthreads=cores)
         n += s.n_pixels * spp
     dt = time.perf_counter() - t0
+    # one core on a smaller sample of the same scenes (one sample per pixel of each)
+    n1 = 0
+    t1 = time.perf_counter()
+    for s in scenes:
+        OracleScene(s).render(0, 1, nthreads=1)
+        n1 += s.n_pixels
+    dt1 = time.perf_counter() - t1
     return {"value": n / dt / 1e6, "unit": "Mpaths/s", "cores": cores, "kind": "oracle",
             "sample": f"all pixels of each scene at {spp} spp ({n} paths, {dt:.1f} s)",
-            "cpu": platform.processor() or platform.machine()}
+            "single_core_mpaths_s": n1 / dt1 / 1e6,
+            "single_core_sample": f"all pixels of each scene at 1 spp ({n1} paths, {dt1:.1f} s)",
+            "cpu": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def image_mse(torch, gs, scenes, imgs, factor: int = 16):
+    """MSE of each timed image (samples [0, spp)) against an independent reference of the same
+    scene at factor x spp (samples [spp, (1 + factor) spp)).  The GPU matches the oracle path by
+    path, so the reference stands in for a high-spp oracle image; every form (persistent,
+    wavefront, one thread per path, batch) gives the same image and hence the same MSE."""
+    out = []
+    for g, s, im in zip(gs, scenes, imgs):
+        ref = g.render(s.spp, (1 + factor) * s.spp)
+        torch.cuda.synchronize()
+        out.append(float(((im - ref) ** 2).mean()))
+    return {"reference": f"same scene, samples [spp, {1 + factor} spp)", "per_scene": out}
 
 
 def cond_measurement(torch, gpss, steps: int = 2):
@@ -276,6 +308,8 @@ def main():
                     help="skip the adjoint measurement on the offset-sphere workload")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-render measurement on the 64-scene workload")
+    ap.add_argument("--no-mse", action="store_true",
+                    help="skip the image MSE against a 16x-spp reference of each scene")
     ap.add_argument("--no-cond", action="store_true",
                     help="skip the measurement of the GP conditioned on point observations")
     ap.add_argument("--tune", action="store_true",
@@ -374,6 +408,8 @@ def main():
                      "flops_per_launch": [w[0] for w in work]},
         "per_scene_mpaths_s": [s.n_paths / (ms / 1e3) / 1e6 for s, ms in zip(scenes, per_scene_ms)],
     }
+    if not args.no_mse:
+        result["image_mse"] = image_mse(torch, gs, scenes, imgs)
     if args.compare:
         result["compare"] = {}
         for other in ("persistent", "wavefront", "mega"):
