@@ -101,7 +101,8 @@ typedef struct {
      * F = albedo x Fresnel reflectance at the half vector.  eta = 0: F = albedo. */
     float fresnel_eta, fresnel_k;
     /* GP conditioned on point observations (Sec. 3.1, Eq. condition_gp): n_obs (0..32) rows of
-     * (x, y, z, observed value) taken with independent Gaussian noise of variance obs_noise > 0,
+     * (x, y, z, observed value) taken with independent Gaussian noise of variance obs_noise
+     * (at least 1e-4 x variance, so that single precision resolves the posterior variance),
      * which adds obs_noise I to kappa(C, C) (a zero noise, the equation as printed, would let
      * the posterior variance vanish at the observations and the density become singular).
      * The medium is then the conditioned GP's: f(x) ~ N(mu_C, kappa_C(x, x)), and the gradient

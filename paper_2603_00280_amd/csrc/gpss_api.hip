@@ -234,6 +234,10 @@ int validate_desc(const gpss_scene_desc* D) {
         if (!finite3(D->observations, 4 * (int)D->n_obs)) return set_error(GPSS_ERR_INVALID_ARG, "observations not finite");
         if (!(D->obs_noise > 0.0f) || !std::isfinite(D->obs_noise))
             return set_error(GPSS_ERR_INVALID_ARG, "obs_noise must be > 0");
+        // below this the single-precision posterior variance sigma^2 - |L^-1 k|^2 at an
+        // observation (about obs_noise) would be lost in the cancellation
+        if (!D->variance_grid && D->obs_noise < 1e-4f * D->variance)
+            return set_error(GPSS_ERR_INVALID_ARG, "obs_noise must be >= 1e-4 x variance");
         if (D->variance_grid || D->mean_offset || D->ndf_kind != GPSS_NDF_GENERALIZED ||
             (D->lengthscale_n > 0.0f && D->lengthscale_n != D->lengthscale))
             return set_error(GPSS_ERR_UNSUPPORTED, "conditioning takes a scalar variance, no mean offset grid, the "

@@ -376,7 +376,7 @@ __device__ __forceinline__ void condition_point(const SceneDev& S, float3 x, Poi
         sxx += W.x * W.x; sxy += W.x * W.y; sxz += W.x * W.z;
         syy += W.y * W.y; syz += W.y * W.z; szz += W.z * W.z;
     }
-    const float vc = var - ww;
+    const float vc = fmaxf(var - ww, 1e-6f * var);   // positive whatever the rounding
     const float iv = 1.0f / vc;
     c = -c;
     const float sg = var * il2;

@@ -100,8 +100,9 @@ def test_null_arguments_are_rejected():
 
 def test_invalid_observations_are_rejected():
     s = sc.cond_sphere_scene(n_obs=4, width=8, height=8)
-    rc, msg = _create(s.replace(obs_noise=0.0))
-    assert rc == gpss.GPSS_ERR_INVALID_ARG and "obs_noise" in msg
+    for noise in (0.0, 1e-5 * s.variance):
+        rc, msg = _create(s.replace(obs_noise=noise))
+        assert rc == gpss.GPSS_ERR_INVALID_ARG and "obs_noise" in msg
     many = np.zeros((sc.MAX_OBSERVATIONS + 1, 4), np.float32)
     rc, msg = _create(s.replace(observations=many))
     assert rc == gpss.GPSS_ERR_INVALID_ARG and "n_obs" in msg
