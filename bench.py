@@ -198,36 +198,53 @@ def image_mse(torch, gs, scenes, imgs, factor: int = 16):
     return {"reference": f"same scene, samples [spp, {1 + factor} spp)", "per_scene": out}
 
 
-def cond_measurement(torch, gpss, steps: int = 2):
-    """The GP conditioned on 32 observations (sphere prior, 512^2, 64 spp): Mpaths/s and the
-    roofline entry of its render kernel (algorithmic FLOPs / launch time on the render stream)."""
+def next_row_scenes():
+    """Workloads of the rows built beyond the plain method, each at the sphere workload's
+    launch (512^2, 64 spp, depth 32)."""
     from gpss_inputs import scenes as sc
+    return {
+        "anisotropic": ("sphere, alpha 0.8 across the normal and 0.01 along it (l_n = sqrt(2) sigma / 0.01)",
+                        [sc.aniso_sphere_scene(0.01)]),
+        "ggx": ("sphere, variance 1e-4, GGX macrofacet with alpha 0.1 / 0.5 / 1.0",
+                [sc.ggx_sphere_scene(a) for a in sc.GGX_ALPHAS]),
+        "fresnel": ("sphere l = 0.1 as three colour channels, gold conductor IOR per channel",
+                    sc.fresnel_rgb_scenes(sc.sphere_scene(0.1), "gold")),
+        "conditioned": ("cond: " + WORKLOADS["cond"], [sc.cond_sphere_scene()]),
+    }
+
+
+def row_measurement(torch, gpss, label: str, scenes, steps: int = 2):
+    """Mpaths/s of one row's workload and the roofline entry of its render kernel (algorithmic
+    FLOPs / launch time on the render stream, summed over the row's scenes)."""
     from paper_2603_00280_amd import flops
-    s = sc.cond_sphere_scene()
-    g = gpss.GpssScene(s)
-    img = torch.empty(s.height, s.width, dtype=torch.float32, device="cuda")
-    _, cnt = g.render_paths(counters=True)
-    torch.cuda.synchronize()
-    fl = flops.flops_from_counters(s, gpss.counters_dict(cnt))
-    g.render(out=img)
+    gs = [gpss.GpssScene(s) for s in scenes]
+    imgs = [torch.empty(s.height, s.width, dtype=torch.float32, device="cuda") for s in scenes]
+    fl = 0.0
+    for s, g in zip(scenes, gs):
+        _, cnt = g.render_paths(counters=True)
+        torch.cuda.synchronize()
+        fl += flops.flops_from_counters(s, gpss.counters_dict(cnt))
+    for g, im in zip(gs, imgs):
+        g.render(out=im)
     stream = torch.cuda.current_stream()
     evs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        g.render(out=img)
-        e1.record(stream)
-        evs.append((e0, e1))
+        for g, im in zip(gs, imgs):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g.render(out=im)
+            e1.record(stream)
+            evs.append((e0, e1))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = sum(a.elapsed_time(b) for a, b in evs) / steps
     rate = fl / (ms / 1e3) / 1e12
-    return {"workload": "cond: " + WORKLOADS["cond"], "value": steps * s.n_paths / wall / 1e6,
-            "unit": "Mpaths/s", "avg_launch_ms": ms,
+    n = sum(s.n_paths for s in scenes)
+    return {"workload": label, "value": steps * n / wall / 1e6, "unit": "Mpaths/s", "ms_per_pass": ms,
             "roofline": {"bound": "alu", "achieved": rate, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": rate / FP32_PEAK_TFLOPS, "traffic": None, "flops_per_launch": fl}}
+                         "frac": rate / FP32_PEAK_TFLOPS, "traffic": None, "flops_per_pass": fl}}
 
 
 def adjoint_measurement(torch, gpss):
@@ -310,8 +327,8 @@ def main():
                     help="skip the batched-render measurement on the 64-scene workload")
     ap.add_argument("--no-mse", action="store_true",
                     help="skip the image MSE against a 16x-spp reference of each scene")
-    ap.add_argument("--no-cond", action="store_true",
-                    help="skip the measurement of the GP conditioned on point observations")
+    ap.add_argument("--no-cond", "--no-next", dest="no_next", action="store_true",
+                    help="skip the measurements of the anisotropic, GGX, Fresnel and conditioned rows")
     ap.add_argument("--tune", action="store_true",
                     help="run the batch autotuner first (its choice is cached on disk)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -428,9 +445,12 @@ def main():
     if not args.no_adjoint:
         print("[bench] adjoint", file=sys.stderr, flush=True)
         result["adjoint"] = adjoint_measurement(torch, gpss)
-    if not args.no_cond and args.workload != "cond":
-        print("[bench] conditioned GP", file=sys.stderr, flush=True)
-        result["conditioned"] = cond_measurement(torch, gpss)
+    if not args.no_next and args.workload == "sphere":
+        result["next_rows"] = {}
+        for name, (label, row_scenes) in next_row_scenes().items():
+            print(f"[bench] {name}", file=sys.stderr, flush=True)
+            result["next_rows"][name] = row_measurement(torch, gpss, label, row_scenes)
+            del row_scenes
     if not args.no_batch:
         print("[bench] batch", file=sys.stderr, flush=True)
         result["batch"] = batch_measurement(torch, gpss, args.tune)

@@ -19,6 +19,13 @@ Per-event counts:
               pdf (30), NDF (35), projected area (20), weight (5), reflection (15)
   NEE         light connection: light direction and box clip (32), phase evaluation (70)
 
+Medium variants change the projected area, NDF and proposal terms:
+  anisotropic kernel   projected area +12 (cosine to the normal, scaled spread), NDF +20
+  GGX macrofacet       projected area +5, NDF -20, phase sampling -35 (closed-form GGX
+                       visible normals instead of the Newton slope inversion), mixture pdf -10
+  conductor Fresnel    +30 per phase evaluation and per sampling weight (two square roots,
+                       two divisions)
+
 A GP conditioned on n observations adds, per point evaluation, the posterior of value and
 gradient: per observation the kernel value, the mean and mean-gradient terms (20) and the
 per-row closing of the triangular solve (29), 8 per entry of the lower triangle of the
@@ -73,15 +80,27 @@ def point_flops(scene) -> int:
     return f
 
 
+ANISO_PROJ, ANISO_NDF = 12, 20
+GGX_PROJ, GGX_NDF, GGX_SAMPLE, GGX_PDF = 5, -20, -35, -10
+FRESNEL = 30
+
+
 def per_event(scene) -> dict:
     p = point_flops(scene)
     cp, cn = (COND_PROJ, COND_NDF) if n_observations(scene) else (0, 0)
+    ln = float(getattr(scene, "lengthscale_n", 0.0))
+    if ln > 0.0 and ln != float(scene.lengthscale):
+        cp, cn = cp + ANISO_PROJ, cn + ANISO_NDF
+    sample = 0
+    if int(getattr(scene, "ndf_kind", 0)) == 1:
+        cp, cn, sample = cp + GGX_PROJ, cn + GGX_NDF, GGX_SAMPLE + GGX_PDF
+    fr = FRESNEL if float(getattr(scene, "fresnel_eta", 0.0)) > 0.0 else 0
     return {
         "track_steps": TRACK_EXTRA + p + DENSITY + PROJ + cp,
         "nee_steps": NEE_EXTRA + p + DENSITY + PROJ + cp,
         "cells": CELL,
-        "phase": REAL + p + cp + cn,
-        "nee": NEE + cn,
+        "phase": REAL + p + cp + cn + sample + fr,
+        "nee": NEE + cn + fr,
     }
 
 
