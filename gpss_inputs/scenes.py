@@ -178,6 +178,9 @@ GGX_ALPHAS = (0.1, 0.5, 1.0)
 
 
 def ggx_sphere_scene(alpha: float = 0.5, variance: float = 1e-4, **kw) -> Scene:
+    # the thin shell (sigma = 0.01) wants cells near its thickness: 128^3 halves the tentative
+    # collisions of 64^3 for twice the cell crossings
+    kw.setdefault("majorant_res", (128, 128, 128))
     sigma = float(np.sqrt(np.float32(variance)))
     s = sphere_scene(lengthscale=float(np.sqrt(2.0) * sigma / alpha), variance=variance, **kw)
     return s.replace(name=f"ggx_sphere_a{alpha:g}", ndf_kind=NDF_GGX)
