@@ -345,8 +345,8 @@ def main():
         copy_calibration(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the renderer shards by sample range across GPUs only by design, not in this build)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the renderer's paths would shard across GPUs by sample range; only one GPU is implemented)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -5,7 +5,7 @@ import math
 
 import numpy as np
 
-# spec bar: per-pixel relative error <= 1e-4; at most 0.1 % of pixels may differ
+# parity bar: per-pixel relative error <= 1e-4; at most 0.1 % of pixels may differ
 # through branch flips, and those must stay within 3 sigma of the Monte Carlo noise
 REL_TOL = 1e-4
 FLIP_FRACTION = 1e-3
