@@ -137,7 +137,8 @@ int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n);
 
 /* Forward render (Sec. 5, null-scattering path tracing) of samples [s0, s1) of every
  * pixel into image_dev (device, width*height floats, overwritten with the mean radiance
- * over those samples).  0 <= s0 < s1. */
+ * over those samples).  0 <= s0 < s1, and width*height*(s1-s0) < 2^31 paths per call (as for
+ * every rendering call; split larger ranges, the chunks reproduce the same paths). */
 int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1,
                 gpss_stream_t stream);
 

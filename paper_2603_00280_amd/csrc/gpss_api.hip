@@ -460,6 +460,17 @@ void fill_dev(gpss_scene* s) {
     V.key1 = (uint32_t)(D.seed >> 32) ^ D.scene_id;
 }
 
+// One call renders at most 2^31 - 1 paths (32-bit path slots in the kernels); checked before
+// any allocation so that an oversized range fails fast with a clear message.
+int check_path_count(const gpss_scene* s, uint32_t s0, uint32_t s1) {
+    if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
+    const uint64_t n = s->n_pixels() * (uint64_t)(s1 - s0);
+    if (n > 0x7FFFFFFFull)
+        return set_error(GPSS_ERR_INVALID_ARG, "%llu paths in one call: at most 2^31 - 1 (split [s0, s1))",
+                         (unsigned long long)n);
+    return GPSS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -553,14 +564,14 @@ int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n) {
 int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_dev, uint32_t s0, uint32_t s1,
                       gpss_stream_t stream) {
     if (!scene || !paths_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
-    if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
+    if (int rc = check_path_count(scene, s0, s1)) return rc;
     return gpss::launch_render_paths(scene, paths_dev, counters_dev, s0, s1 - s0,
                                      reinterpret_cast<hipStream_t>(stream));
 }
 
 int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream) {
     if (!scene || !image_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
-    if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
+    if (int rc = check_path_count(scene, s0, s1)) return rc;
     const uint32_t ns = s1 - s0;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int rc = gpss::ensure_scratch(scene, (size_t)scene->n_pixels() * ns);
@@ -604,7 +615,7 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
 int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float* grad_offset_dev,
                         float* grad_scalars_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream) {
     if (!scene || !dloss_dimage_dev || !grad_scalars_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
-    if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
+    if (int rc = check_path_count(scene, s0, s1)) return rc;
     if (scene->d_offset && !grad_offset_dev)
         return set_error(GPSS_ERR_INVALID_ARG, "scene has a mean-offset grid: grad_offset_dev is required");
     if (scene->dev.aniso_k != 0.0f || scene->dev.ggx || scene->dev.n_obs > 0)

@@ -209,3 +209,17 @@ def test_depth0_equals_albedo0_bitwise(G):
     a = G.GpssScene(DEGENERATE["depth0"]()).render().cpu().numpy()
     b = G.GpssScene(DEGENERATE["albedo0"]()).render().cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_oversized_sample_range_is_rejected_before_allocation(G):
+    """16384^2 pixels x 8 samples = 2^31 paths: one more than a call may render."""
+    s = sc.sphere_scene(0.1, width=16384, height=16384, spp=8, max_depth=1)
+    g = G.GpssScene(s)
+    img = torch.empty(s.height, s.width, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    with pytest.raises(G.GpssError, match="at most 2"):
+        g.render(0, 8, out=img)
+    # no 8 GiB per-path buffer was allocated for the rejected call
+    assert torch.cuda.mem_get_info()[0] >= free0 - (64 << 20)
+    del img
