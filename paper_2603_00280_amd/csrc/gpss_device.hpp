@@ -643,7 +643,18 @@ __device__ __forceinline__ float mixture_pdf(const Proposal& p, float3 v, float3
 }
 
 // Slope along the incidence plane at unit roughness: solve F(x) = u F(a) on [-8, a],
-// F(x) = erfc(-x)/2 + exp(-x^2)/(2 a sqrt(pi)), by bracketed Newton iterations.
+// F(x) = erfc(-x)/2 + exp(-x^2)/(2 a sqrt(pi)), by bracketed Newton iterations.  The start
+// blends the two regimes of the visible-slope density (1 - x/a) e^{-x^2}: the Gaussian quantile
+// erfinv(2u - 1) for large a (near normal incidence) and, for small a, the quantile
+// -sqrt(-ln u) of the tail |x| e^{-x^2} that dominates there; weight min(a, 1).  The start only
+// shortens the iteration; the bracket and the tolerance fix the root.
+__device__ __forceinline__ float slope_start(float a, float u) {
+    const float g = u > 0.0f ? erfinvf(2.0f * u - 1.0f) : 0.0f;
+    const float t = -sqrtf(-logf(fmaxf(u, 1e-30f)));
+    if (isinf(a)) return g;
+    const float w = fminf(a, 1.0f);
+    return fminf(w * g + (1.0f - w) * t, a);
+}
 __device__ __forceinline__ float sample_slope_x(float a, float u) {
     const bool fin = !isinf(a);
     const float c2 = fin ? 0.5f * kInvSqrtPi / a : 0.0f;
@@ -652,7 +663,7 @@ __device__ __forceinline__ float sample_slope_x(float a, float u) {
     const float target = u * Fa;
     float lo = -8.0f, hi = fin ? fminf(a, 8.0f) : 8.0f;
     if (target <= 0.5f * erfcf(8.0f) + expf(-64.0f) * c2) return lo;
-    float x = fminf(fmaxf(0.0f, lo), hi);
+    float x = fminf(fmaxf(slope_start(a, u), lo), hi);
     for (int it = 0; it < 48; ++it) {
         const float e = expf(-x * x);
         const float fx = 0.5f * erfcf(-x) + e * c2 - target;
