@@ -647,8 +647,9 @@ __device__ __forceinline__ float mixture_pdf(const Proposal& p, float3 v, float3
 // blends the two regimes of the visible-slope density (1 - x/a) e^{-x^2}: the Gaussian quantile
 // erfinv(2u - 1) for large a (near normal incidence) and, for small a, the quantile
 // -sqrt(-ln u) of the tail |x| e^{-x^2} that dominates there; weight min(a, 1).  The start only
-// shortens the iteration; the bracket and the tolerance fix the root.
-__device__ __forceinline__ float slope_start(float a, float u) {
+// shortens the iteration; the bracket and the tolerance fix the root.  Kept out of line: inlined
+// into every kernel, its code slowed the conditioned-GP specialization by a fifth.
+__device__ __noinline__ float slope_start(float a, float u) {
     const float g = u > 0.0f ? erfinvf(2.0f * u - 1.0f) : 0.0f;
     const float t = -sqrtf(-logf(fmaxf(u, 1e-30f)));
     if (isinf(a)) return g;

@@ -85,3 +85,18 @@ def test_fresnel_adjoint_matches_oracle(G):
     for sl in (slice(0, 3), slice(3, None)):
         a, b = g_gpu[sl], g_orc[sl]
         assert np.abs(a - b).max() <= 1e-3 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("channel", [0, 2])
+def test_fresnel_full_size_sampled(G, channel):
+    """The measured Fresnel workload (sphere l = 0.1 at 512^2, 64 spp, depth 32, gold, one
+    channel scene): the GPU image at 300 oracle-traced pixels."""
+    s = sc.fresnel_rgb_scenes(sc.sphere_scene(0.1), "gold")[channel]
+    rng = np.random.default_rng(20 + channel)
+    px = np.sort(rng.choice(s.n_pixels, 300, replace=False)).astype(np.int64)
+    print(f"[fresnel] full size {s.name} {s.width}x{s.height} spp {s.spp}", flush=True)
+    img = G.GpssScene(s).render().cpu().numpy().ravel()
+    ref = orc.OracleScene(s).render_pixels(px)
+    st = gh.compare_sampled(img[px], ref, s.spp, s.name)
+    print("   ", st, flush=True)
+    gh.assert_sampled_parity(st)
