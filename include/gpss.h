@@ -192,7 +192,9 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
 
 /* Evaluate the medium at n points for n directions (diagnostics and tests).
  * points_dev, dirs_dev: device, n x 3 floats.  out_dev: device, n x 8 floats:
- * mu, sigma (std), s = sigma/l, rho, sigma_proj(dir), sigma_t, ndf(dir as normal), albedo. */
+ * mu, sigma (std), s = sigma/l, rho, sigma_proj(dir), sigma_t, ndf(dir as normal), albedo.
+ * For a conditioned GP, mu and sigma are the posterior's and s is the isotropic spread the
+ * proposal uses (root of a third of the trace of the gradient covariance given f = 0). */
 int gpss_eval_medium(gpss_scene_t scene, const float* points_dev, const float* dirs_dev,
                      float* out_dev, uint64_t n, gpss_stream_t stream);
 
