@@ -156,3 +156,44 @@ def test_gradient_descent_reduces_loss(G):
         losses.append(float(loss.detach()))
     print("   losses", [f"{l:.3e}" for l in losses], flush=True)
     assert losses[-1] < losses[0]
+
+
+def test_adjoint_matches_central_differences(G):
+    """The default adjoint on 32 parameters (variance, lengthscale, albedo and 29 offset-grid
+    nodes near the surface) against FP64 central differences (h = 1e-4 relative for the
+    scalars, 1e-5 for the nodes) of the oracle's frozen-sampling estimator at theta0."""
+    from tests.test_oracle_pins import _unrounded
+    s0 = _small(False)
+    s0.offset_grid = np.random.default_rng(9).normal(0, 0.01, s0.offset_grid.shape).astype(np.float32)
+    dl = _dloss(s0, _small(True))
+    ids = [-1, -2, -3] + [int(i) for i in sc.grad_param_indices(s0)]
+    assert len(ids) == 32
+    base = orc.OracleScene(s0)
+    h = 1e-4
+    fd = []
+    for pid in ids:
+        imgs = []
+        for sgn in (+1, -1):
+            if pid in (-1, -2, -3):
+                field = {-1: "variance", -2: "lengthscale", -3: "albedo"}[pid]
+                v = float(orc.f32(getattr(s0, field)))
+                pert = s0.replace(**{field: v * (1 + sgn * h)})
+                scale = v * h
+            else:
+                off = s0.offset_grid.astype(np.float64).copy()
+                off.ravel()[pid] += sgn * 1e-5
+                pert = s0.replace(offset_grid=off.astype(np.float32))
+                scale = abs(float(np.float32(off.ravel()[pid])) - float(s0.offset_grid.ravel()[pid]))
+            imgs.append(base.render_frozen(_unrounded(pert)))
+        fd.append(float(np.sum(dl * (imgs[0] - imgs[1]))) / (2 * scale))
+    fd = np.array(fd)
+    print(f"[adjoint] central differences, {len(ids)} parameters", flush=True)
+    g = G.GpssScene(s0)
+    g_off, g_sc = g.render_adjoint(torch.as_tensor(dl, dtype=torch.float32))
+    torch.cuda.synchronize()
+    g_off = g_off.cpu().numpy().ravel()
+    g_sc = g_sc.cpu().numpy()
+    g_gpu = np.array([g_sc[0], g_sc[1], g_sc[2]] + [g_off[i] for i in ids[3:]], np.float64)
+    for name, a, b in zip(["var", "len", "alb"] + [f"n{i}" for i in ids[3:]], g_gpu, fd):
+        print(f"   {name:>8s} gpu {a:+.6e} fd {b:+.6e}", flush=True)
+    _check_groups(g_gpu, fd)
