@@ -46,7 +46,7 @@ __device__ void ratio_track_grad(const SceneDev& S, D3 o, D3 d, float3 df, doubl
         const PointQ q = eval_point(S, x);
         const float sig = sigma_t_of(q, df);
         add_dlog_sigma_t(S, x, q, df, -coef * sig / (sg.maj - sig), grad_off, acc);
-        Tr *= 1.0f - sig / sg.maj;
+        Tr *= null_ratio(sig, sg.maj);
         if (!roulette(Tr, rng)) return;
         sg.redraw(rng);
     }

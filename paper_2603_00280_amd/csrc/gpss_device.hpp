@@ -424,6 +424,11 @@ __device__ __forceinline__ float erfcx_pos(float y) {
     p = fmaf(p, s, -6.717940849e-01f);
     return t * __expf(p);
 }
+// Ratio-tracking factor 1 - sigma_t / majorant with a single reciprocal instruction (about
+// one ulp) instead of a correctly rounded division; every tracer form and the adjoint replay
+// use this one function, so their transmittances and roulette decisions stay identical.
+__device__ __forceinline__ float null_ratio(float sig, float maj) { return 1.0f - sig * __builtin_amdgcn_rcpf(maj); }
+
 __device__ __forceinline__ float erfcx_any(float y) {
     const float r = erfcx_pos(fabsf(y));
     return y >= 0.0f ? r : 2.0f * expf(y * y) - r;
@@ -431,8 +436,9 @@ __device__ __forceinline__ float erfcx_any(float y) {
 
 // Density rho = phi(mu; 0, sigma^2) / Phi(mu; 0, sigma^2) = sqrt(2/pi) / (sigma erfcx(-mu/(sigma sqrt2))).
 __device__ __forceinline__ float rho_of(float mu, float sigma) {
-    const float z = mu / sigma;
-    return kSqrt2OverPi / (sigma * erfcx_any(-z * kInvSqrt2));
+    const float is = __builtin_amdgcn_rcpf(sigma);
+    const float z = mu * is;
+    return kSqrt2OverPi * is * __builtin_amdgcn_rcpf(erfcx_any(-z * kInvSqrt2));
 }
 
 // Cosine between a unit direction and the local mean-gradient direction (z where G = 0).
@@ -455,7 +461,7 @@ __device__ __forceinline__ float sigma_proj(float3 G, float s, float ak, float3 
         const float c = cos_to_normal(G, d);
         sd = s * sqrtf(1.0f + ak * (c * c));
     }
-    const float z = m / sd;
+    const float z = m * __builtin_amdgcn_rcpf(sd);
     const float az = fabsf(z);
     const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
     return fmaxf(-m, 0.0f) + sd * ph * (1.0f - az * kSqrtHalfPi * erfcx_pos(az * kInvSqrt2));
@@ -533,7 +539,7 @@ __device__ __forceinline__ float sigma_proj_chol(float3 G, const float* L, float
     const float3 u = f3(L[0] * d.x + L[1] * d.y + L[3] * d.z, L[2] * d.y + L[4] * d.z, L[5] * d.z);
     const float sd = sqrtf(dot(u, u));
     const float m = dot(d, G);
-    const float z = m / sd;
+    const float z = m * __builtin_amdgcn_rcpf(sd);
     const float az = fabsf(z);
     const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
     return fmaxf(-m, 0.0f) + sd * ph * (1.0f - az * kSqrtHalfPi * erfcx_pos(az * kInvSqrt2));

@@ -358,7 +358,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     } else {
                         if (ADJ && (flags & kGradPass))   // shadow-ray factor of this connection
                             add_dlog_sigma_t(S, xf, q, df, -coef * sig / (sg.maj - sig), io.grad_off, acc);
-                        Tr *= 1.0f - sig / sg.maj;
+                        Tr *= null_ratio(sig, sg.maj);
                         if (!roulette(Tr, rng)) {
                             Tr = 0.0f;
                             nee_done = true;

@@ -124,7 +124,7 @@ __device__ __forceinline__ float ratio_track(const SceneDev& S, D3 o, D3 d, D3 i
         const PointQ q = eval_point(S, sg.pos());
         const float sig = sigma_t_of(q, df);
         if (STATS && sig > sg.maj) st.violations++;
-        Tr *= 1.0f - sig / sg.maj;
+        Tr *= null_ratio(sig, sg.maj);
         if (!roulette(Tr, rng)) return 0.0f;
         sg.redraw(rng);
     }

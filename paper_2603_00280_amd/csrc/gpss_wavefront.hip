@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256, GPSS_WF_NEE_MIN_WAVES) void wf_nee_kernel(Scen
                     const PointQ q = eval_point(S, sg.pos());
                     const float sig = sigma_t_of(q, wf);
                     if (STATS && sig > sg.maj) st.violations++;
-                    Tr *= 1.0f - sig / sg.maj;
+                    Tr *= null_ratio(sig, sg.maj);
                     if (!roulette(Tr, rng)) {
                         Tr = 0.0f;
                         done = true;
