@@ -390,6 +390,8 @@ void fill_dev(gpss_scene* s) {
     V.var_grid = s->d_var;
     V.variance = D.variance;
     V.lengthscale = D.lengthscale;
+    V.sigma0 = std::sqrt(D.variance);
+    V.s0 = V.sigma0 / D.lengthscale;
     V.aniso_k = aniso_k(D);
     V.ggx = D.ndf_kind == GPSS_NDF_GGX;
     V.f_eta = D.fresnel_eta;
@@ -605,6 +607,8 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
     scene->desc.albedo = albedo;
     scene->dev.variance = variance;
     scene->dev.lengthscale = lengthscale;
+    scene->dev.sigma0 = std::sqrt(variance);
+    scene->dev.s0 = scene->dev.sigma0 / lengthscale;
     scene->dev.aniso_k = aniso_k(scene->desc);
     scene->dev.albedo = albedo;
     scene->dev_version++;

@@ -42,6 +42,7 @@ struct SceneDev {
     int var_res[3];
     float var_scale[3];
     float lengthscale;
+    float sigma0, s0;             // sqrt(variance) and sqrt(variance) / lengthscale (scalar variance)
     float aniso_k;                // (l / l_n)^2 - 1 for lengthscale l_n along the mean gradient; 0: isotropic
     int ggx;                      // GGX height-field macrofacet instead of the generalized one
     float f_eta, f_k;             // conductor IOR eta + i k of the Fresnel term (eta = 0: F = albedo)
@@ -191,10 +192,11 @@ struct Rng {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float sdf_prim(float4 a, float4 b, float3 x, float3& g) {
     const float3 v = f3(x.x - a.y, x.y - a.z, x.z - a.w);
-    if (a.x < 0.5f) {  // sphere
-        const float r = sqrtf(dot(v, v));
-        g = r > 0.0f ? (1.0f / r) * v : f3(0.0f, 0.0f, 1.0f);
-        return r - b.x;
+    if (a.x < 0.5f) {  // sphere: one reciprocal square root gives the distance and the normal
+        const float d2 = dot(v, v);
+        const float ir = __builtin_amdgcn_rsqf(d2);
+        g = d2 > 0.0f ? ir * v : f3(0.0f, 0.0f, 1.0f);
+        return d2 * ir - b.x;
     }
     const float sx = v.x < 0.0f ? -1.0f : 1.0f, sy = v.y < 0.0f ? -1.0f : 1.0f,
                 sz = v.z < 0.0f ? -1.0f : 1.0f;
@@ -302,13 +304,14 @@ __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
         q.mu += tri_eval(S.offset, S.off_res, S.off_scale, c, &go);
         q.G = q.G + go;
     }
-    float var = S.variance;
     if (S.var_grid) {
         const TriCell c = tri_cell(S.var_res, S.var_scale, S.lo, x);
-        var = tri_eval(S.var_grid, S.var_res, S.var_scale, c, nullptr);
+        q.sigma = sqrtf(tri_eval(S.var_grid, S.var_res, S.var_scale, c, nullptr));
+        q.s = q.sigma / S.lengthscale;
+    } else {   // the same correctly rounded values, formed once per scene
+        q.sigma = S.sigma0;
+        q.s = S.s0;
     }
-    q.sigma = sqrtf(var);
-    q.s = q.sigma / S.lengthscale;
     q.ak = S.aniso_k;
     q.ggx = S.ggx;
     q.feta = S.f_eta;
