@@ -379,6 +379,18 @@ float aniso_k(const gpss_scene_desc& D) {
     return r * r - 1.0f;
 }
 
+// Scheduling policy from the largest gradient spread sigma / l of the scene (the variance
+// grid's largest node, the shorter of the two lengthscales).
+void set_policy(gpss_scene* s) {
+    const gpss_scene_desc& D = s->desc;
+    float vmax = D.variance;
+    if (!s->var_h.empty()) vmax = *std::max_element(s->var_h.begin(), s->var_h.end());
+    const float l = D.lengthscale_n > 0.0f ? std::min(D.lengthscale, D.lengthscale_n) : D.lengthscale;
+    const gpss::SchedPolicy p = gpss::sched_policy(std::sqrt(vmax) / l);
+    s->dev.walk_steps = p.walk_steps;
+    s->dev.scatter_min = p.scatter_min;
+}
+
 void fill_dev(gpss_scene* s) {
     const gpss_scene_desc& D = s->desc;
     gpss::SceneDev& V = s->dev;
@@ -392,6 +404,7 @@ void fill_dev(gpss_scene* s) {
     V.lengthscale = D.lengthscale;
     V.sigma0 = std::sqrt(D.variance);
     V.s0 = V.sigma0 / D.lengthscale;
+    set_policy(s);
     V.aniso_k = aniso_k(D);
     V.ggx = D.ndf_kind == GPSS_NDF_GGX;
     V.f_eta = D.fresnel_eta;
@@ -609,6 +622,7 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
     scene->dev.lengthscale = lengthscale;
     scene->dev.sigma0 = std::sqrt(variance);
     scene->dev.s0 = scene->dev.sigma0 / lengthscale;
+    set_policy(scene);
     scene->dev.aniso_k = aniso_k(scene->desc);
     scene->dev.albedo = albedo;
     scene->dev_version++;

@@ -21,6 +21,19 @@ constexpr float kSqrt2 = 1.41421356237309504880f;
 
 constexpr int kMaxPrims = 64;
 constexpr int kMaxObs = 32;                 // observations of a conditioned GP
+
+// Scheduling policy of the persistent tracer for one scene: cell steps per walk operation and
+// the lanes a scatter operation waits for.  Rough media (largest gradient spread
+// s = sigma / l of at least sqrt(2), roughness alpha >= 2) scatter at most tentative
+// collisions and run faster with short walks and fuller scatter operations (4, 24); smooth
+// ones with longer walks (6, 16).  Measured on the sphere workloads; the choice reorders work
+// across lanes only, never within a path, so images do not depend on it.
+struct SchedPolicy {
+    int walk_steps, scatter_min;
+};
+inline SchedPolicy sched_policy(float s_max) {
+    return s_max >= 1.41421356f ? SchedPolicy{4, 24} : SchedPolicy{6, 16};
+}
 constexpr int kStepCap = 1 << 16;           // tentative collisions per segment
 constexpr float kRRThreshold = 0.0625f;     // shadow-ray Russian roulette below this transmittance
 
@@ -43,6 +56,7 @@ struct SceneDev {
     float var_scale[3];
     float lengthscale;
     float sigma0, s0;             // sqrt(variance) and sqrt(variance) / lengthscale (scalar variance)
+    int walk_steps, scatter_min;  // scheduling of the persistent tracer (sched_policy)
     float aniso_k;                // (l / l_n)^2 - 1 for lengthscale l_n along the mean gradient; 0: isotropic
     int ggx;                      // GGX height-field macrofacet instead of the generalized one
     float f_eta, f_k;             // conductor IOR eta + i k of the Fresnel term (eta = 0: F = albedo)

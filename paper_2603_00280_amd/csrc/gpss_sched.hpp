@@ -37,18 +37,14 @@ enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBe
 #ifndef GPSS_SCHED_EVAL_MIN_COND
 #define GPSS_SCHED_EVAL_MIN_COND 48
 #endif
-#ifndef GPSS_SCHED_SCATTER_MIN
-#define GPSS_SCHED_SCATTER_MIN 16
-#endif
 #ifndef GPSS_SCHED_BEGIN_MIN
 #define GPSS_SCHED_BEGIN_MIN 16
 #endif
 #ifndef GPSS_SCHED_REFILL_MIN
 #define GPSS_SCHED_REFILL_MIN 8
 #endif
-#ifndef GPSS_SCHED_WALK_STEPS
-#define GPSS_SCHED_WALK_STEPS 6
-#endif
+// The scatter threshold and the cell steps per walk come from the scene record (walk_steps,
+// scatter_min): see sched_policy in gpss_device.hpp.
 #ifndef GPSS_SCHED_MIN_WAVES
 #define GPSS_SCHED_MIN_WAVES 3
 #endif
@@ -192,7 +188,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
         if (nBusy == 0) break;  // every lane idle and no paths left
 
         // ---- phase sampling and light-connection set-up at real collisions ----
-        if (nScat > 0 && (nScat >= GPSS_SCHED_SCATTER_MIN || nWalk + nEval + nBegin == 0)) {
+        if (nScat > 0 && (nScat >= S.scatter_min || nWalk + nEval + nBegin == 0)) {
             if (op == kOpScatter) {
                 ++b;
                 const D3 x = sg.o + sg.t * sg.d;
@@ -370,9 +366,9 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 }
             }
         } else if (op == kOpWalk) {
-            // ---- cell walk: up to GPSS_SCHED_WALK_STEPS events per lane ----
+            // ---- cell walk: up to S.walk_steps events per lane ----
 #pragma unroll 1
-            for (int k = 0; k < GPSS_SCHED_WALK_STEPS; ++k) {
+            for (int k = 0; k < S.walk_steps; ++k) {
                 const int ev = sg.step<STATS>(S, st);
                 if (ev == kCell) continue;
                 if (ev == kTentative) {
