@@ -167,6 +167,8 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
 
 // Replay of every path (pixel p / ns, sample s0 + p % ns) whose radiance paths[p] the
 // forward tracer has just computed.
+static_assert(kSchedBlock == kGradCacheLanes, "the gradient cache has one column per thread of a block");
+
 __global__ __launch_bounds__(256, GPSS_ADJ_MIN_WAVES) void adjoint_kernel(SceneDev S, const float* __restrict__ dloss,
                                                                          const float* __restrict__ paths,
                                                                          float* __restrict__ grad_off,
@@ -179,6 +181,7 @@ __global__ __launch_bounds__(256, GPSS_ADJ_MIN_WAVES) void adjoint_kernel(SceneD
         const float wpix = dloss[pixel] / (float)ns;
         if (wpix != 0.0f) replay_path(S, pixel, sample, paths[p], wpix, grad_off, acc);
     }
+    flush_grad_cell(S, grad_off, acc);
     float v[3] = {acc.var, acc.len, acc.alb};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -214,6 +217,7 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_adjoint_kerne
     GradAcc acc{0.0f, 0.0f, 0.0f};
     __shared__ SchedLds<true> lds;
     run_scheduled<false, true, kMedIso>(S, src, nullptr, st, io, acc, lds);
+    flush_grad_cell(S, io.grad_off, acc);
     float v[3] = {acc.var, acc.len, acc.alb};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {

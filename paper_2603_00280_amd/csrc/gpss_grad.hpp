@@ -9,7 +9,36 @@ namespace gpss {
 
 struct GradAcc {
     float var, len, alb;   // d loss / d (variance, lengthscale, albedo), this thread's share
+    int cell = -1;         // offset-grid cell whose corner sums the thread's cache column holds
 };
+
+// Block size the per-thread offset-grid cache is laid out for (one LDS column per thread).
+constexpr int kGradCacheLanes = 256;
+
+// Per-thread cache of the eight corner contributions of one offset-grid cell.  Successive
+// tentative collisions of a track or shadow ray mostly fall in the same cell, so their
+// contributions are summed here and reach the grid with one atomic per corner when the
+// thread moves to another cell (and once at the end), instead of eight atomics per event.
+// Indexed [corner][threadIdx.x]: consecutive threads hit consecutive banks.
+__device__ __forceinline__ float (&grad_cache())[8][kGradCacheLanes] {
+    __shared__ float cache[8][kGradCacheLanes];
+    return cache;
+}
+
+// Add the cached corner sums of the thread's current cell to the grid; empties the cache.
+__device__ __forceinline__ void flush_grad_cell(const SceneDev& S, float* __restrict__ grad_off, GradAcc& acc) {
+    if (acc.cell < 0) return;
+    float (&cache)[8][kGradCacheLanes] = grad_cache();
+    const int t = threadIdx.x;
+    const int sy = S.off_res[0], sz = S.off_res[0] * S.off_res[1];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const int dx = n & 1, dy = (n >> 1) & 1, dz = n >> 2;
+        const float v = cache[n][t];
+        if (v != 0.0f) atomicAdd(&grad_off[acc.cell + dx + dy * sy + dz * sz], v);
+    }
+    acc.cell = -1;
+}
 
 // d log rho = dmu * dmu_coef + dsigma * dsig_coef,  rho = phi(z)/(sigma Phi(z)), z = mu/sigma
 __device__ __forceinline__ void dlog_rho(float mu, float sigma, float& dmu, float& dsig) {
@@ -72,7 +101,11 @@ __device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const 
                                              float csig, float cs, float* __restrict__ grad_off, GradAcc& acc) {
     if (S.offset && grad_off) {
         const TriCell c = tri_cell(S.off_res, S.off_scale, S.lo, x);
-        const int sy = S.off_res[0], sz = S.off_res[0] * S.off_res[1];
+        const bool same = c.base == acc.cell;
+        if (!same) flush_grad_cell(S, grad_off, acc);
+        acc.cell = c.base;
+        float (&cache)[8][kGradCacheLanes] = grad_cache();
+        const int t = threadIdx.x;
         const float fx = c.fx, fy = c.fy, fz = c.fz;
         const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
         const float ax = cG.x * S.off_scale[0], ay = cG.y * S.off_scale[1], az = cG.z * S.off_scale[2];
@@ -82,7 +115,7 @@ __device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const 
             const float wx = dx ? fx : gx, wy = dy ? fy : gy, wz = dz ? fz : gz;
             const float sxg = dx ? 1.0f : -1.0f, syg = dy ? 1.0f : -1.0f, szg = dz ? 1.0f : -1.0f;
             const float v = cmu * (wx * wy * wz) + ax * (sxg * wy * wz) + ay * (syg * wx * wz) + az * (szg * wx * wy);
-            if (v != 0.0f) atomicAdd(&grad_off[c.base + dx + dy * sy + dz * sz], v);
+            cache[n][t] = same ? cache[n][t] + v : v;
         }
     }
     if (!S.var_grid) {

@@ -72,7 +72,7 @@ struct LaunchSource {
 struct AdjointIo {
     const float* dloss;        // d loss / d pixel
     const float* radiance;     // each path's radiance (forward pass), by output slot
-    float* grad_off;           // offset-grid gradient (nullable), accumulated atomically
+    float* grad_off;           // offset-grid gradient (nullable), accumulated atomically per cell
     float inv_ns;              // 1 / samples per pixel of the launch
 };
 
@@ -81,8 +81,9 @@ struct AdjointIo {
 // each path's radiance to paths[slot].  Adjoint form: replay each path with weight
 // dloss[pixel] / ns against its forward radiance and accumulate the parameter gradient
 // (frozen-sampling estimator; the terms are those of the one-thread replay in
-// gpss_adjoint.hip) into io.grad_off and acc.  Must be called by whole waves; returns when
-// the source is exhausted and every lane's path has ended.
+// gpss_adjoint.hip) into io.grad_off and acc; the caller adds the lane's cached offset-grid
+// cell with flush_grad_cell afterwards.  Must be called by whole waves; returns when the
+// source is exhausted and every lane's path has ended.
 // MED: the scene's medium when the kernel is specialized for it (kMedIso generalized with the
 // isotropic kernel, kMedGgx, kMedAniso generalized with the anisotropic kernel), so that
 // the other media's code is not compiled in; kMedAny takes everything from the scene record.
