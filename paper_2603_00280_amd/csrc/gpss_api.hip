@@ -404,6 +404,7 @@ void fill_dev(gpss_scene* s) {
     V.lengthscale = D.lengthscale;
     V.sigma0 = std::sqrt(D.variance);
     V.s0 = V.sigma0 / D.lengthscale;
+    V.inv_l = 1.0f / D.lengthscale;
     set_policy(s);
     V.aniso_k = aniso_k(D);
     V.ggx = D.ndf_kind == GPSS_NDF_GGX;
@@ -622,6 +623,7 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
     scene->dev.lengthscale = lengthscale;
     scene->dev.sigma0 = std::sqrt(variance);
     scene->dev.s0 = scene->dev.sigma0 / lengthscale;
+    scene->dev.inv_l = 1.0f / lengthscale;
     set_policy(scene);
     scene->dev.aniso_k = aniso_k(scene->desc);
     scene->dev.albedo = albedo;

@@ -56,6 +56,7 @@ struct SceneDev {
     float var_scale[3];
     float lengthscale;
     float sigma0, s0;             // sqrt(variance) and sqrt(variance) / lengthscale (scalar variance)
+    float inv_l;                  // 1 / lengthscale (gradient terms)
     int walk_steps, scatter_min;  // scheduling of the persistent tracer (sched_policy)
     float aniso_k;                // (l / l_n)^2 - 1 for lengthscale l_n along the mean gradient; 0: isotropic
     int ggx;                      // GGX height-field macrofacet instead of the generalized one

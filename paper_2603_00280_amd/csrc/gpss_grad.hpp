@@ -40,31 +40,39 @@ __device__ __forceinline__ void flush_grad_cell(const SceneDev& S, float* __rest
     acc.cell = -1;
 }
 
-// d log rho = dmu * dmu_coef + dsigma * dsig_coef,  rho = phi(z)/(sigma Phi(z)), z = mu/sigma
+// d log rho = dmu * dmu_coef + dsigma * dsig_coef,  rho = phi(z)/(sigma Phi(z)), z = mu/sigma:
+//   d log rho / d mu = -(z + r) / sigma,  d log rho / d sigma = (z^2 - 1 + z r) / sigma,
+// with r = phi(z)/Phi(z) = sqrt(2/pi) / erfcx(-z/sqrt2) taken from the same fitted erfcx
+// and reciprocals as the density itself (rho_of).
 __device__ __forceinline__ void dlog_rho(float mu, float sigma, float& dmu, float& dsig) {
-    const float z = mu / sigma;
-    const float r = kSqrt2OverPi / erfcxf(-z * kInvSqrt2);   // phi(z) / Phi(z)
-    dmu = -(z + r) / sigma;
-    dsig = (z * z - 1.0f + z * r) / sigma;
+    const float is = __builtin_amdgcn_rcpf(sigma);
+    const float z = mu * is;
+    const float r = kSqrt2OverPi * __builtin_amdgcn_rcpf(erfcx_any(-z * kInvSqrt2));
+    dmu = -(z + r) * is;
+    dsig = (z * z - 1.0f + z * r) * is;
 }
 
 // d log sigma_proj: sigma_proj = s phi(z) - m Phi(-z), m = d . G, z = m / s;
-// d/dm = -Phi(-z), d/ds = phi(z).  Written with the Mills ratio for z > 0.
+// d/dm = -Phi(-z), d/ds = phi(z).  With R = Phi(-|z|) / phi(z) = sqrt(pi/2) erfcx(|z|/sqrt2)
+// and q = 1 - |z| R (the form of sigma_proj):
+//   z > 0:  sigma_proj = s phi q, so d/dm = -R / (s q) and d/ds = 1 / (s q) (phi cancels,
+//           which keeps large z free of underflow);
+//   z <= 0: sigma_proj = s phi q - m, Phi(-z) = 1 - R phi.
 __device__ __forceinline__ void dlog_proj(float3 G, float s, float3 d, float3& dG, float& ds) {
     const float m = dot(d, G);
-    const float z = m / s;
+    const float z = m * __builtin_amdgcn_rcpf(s);
+    const float az = fabsf(z);
+    const float R = kSqrtHalfPi * erfcx_pos(az * kInvSqrt2);
+    const float q = fmaxf(1.0f - az * R, 1e-30f);
     float a, b;
-    if (z <= 0.0f) {
-        const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
-        const float Phm = 1.0f - 0.5f * erfcf(-z * kInvSqrt2);
-        const float proj = s * ph - m * Phm;
-        a = Phm / proj;
-        b = ph / proj;
+    if (z > 0.0f) {
+        b = __builtin_amdgcn_rcpf(s * q);
+        a = R * b;
     } else {
-        const float R = kSqrtHalfPi * erfcxf(z * kInvSqrt2);   // Phi(-z) / phi(z)
-        const float q = fmaxf(1.0f - z * R, 1e-30f);            // sigma_proj = s phi(z) q
-        a = R / (s * q);
-        b = 1.0f / (s * q);
+        const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
+        const float ip = __builtin_amdgcn_rcpf(fmaf(s * ph, q, -m));
+        a = (1.0f - R * ph) * ip;
+        b = ph * ip;
     }
     dG = (-a) * d;
     ds = b;
@@ -120,10 +128,10 @@ __device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const 
     }
     if (!S.var_grid) {
         // sigma = sqrt(variance), s = sigma / l
-        const float inv2sig = 0.5f / q.sigma;
-        acc.var += csig * inv2sig + cs * inv2sig / S.lengthscale;
+        const float inv2sig = 0.5f * __builtin_amdgcn_rcpf(q.sigma);
+        acc.var += inv2sig * fmaf(cs, S.inv_l, csig);
     }
-    acc.len -= cs * q.s / S.lengthscale;
+    acc.len -= cs * q.s * S.inv_l;
 }
 
 // coefficient c on d log sigma_t(x, d) = d log rho + d log sigma_proj(d)
