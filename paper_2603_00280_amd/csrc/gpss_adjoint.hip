@@ -126,7 +126,7 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
                 float ds;
                 if (hn >= 1e-7f && dlog_ndf(q.G, q.s, (1.0f / hn) * h, dG, ds)) {
                     const float c = wpix * nv.E[li];
-                    scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc);
+                    scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc, true);
                 }
             }
         }
@@ -135,7 +135,7 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
             float dmu, dsig;
             dlog_rho(q.mu, q.sigma, dmu, dsig);
             const float c = wpix * Lrem;
-            scatter_grad(S, xf, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, grad_off, acc);
+            scatter_grad(S, xf, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, grad_off, acc, true);
             if (!S.albedo_per_prim && S.albedo > 0.0f) acc.alb += c / S.albedo;
         }
         // phase sampling (same draws as the forward pass)
@@ -150,7 +150,7 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
             float ds;
             if (dlog_ndf(q.G, q.s, wm, dG, ds)) {
                 const float c = wpix * Lafter;
-                scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc);
+                scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc, true);
             }
         }
         if (!ok) break;

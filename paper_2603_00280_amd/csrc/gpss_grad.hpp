@@ -9,35 +9,48 @@ namespace gpss {
 
 struct GradAcc {
     float var, len, alb;   // d loss / d (variance, lengthscale, albedo), this thread's share
-    int cell = -1;         // offset-grid cell whose corner sums the thread's cache column holds
+    // offset-grid cells whose corner sums the thread's two cache slots hold (-1: empty):
+    // slot 0 the cell of the current vertex, slot 1 that of the moving track or shadow ray
+    int cell0 = -1, cell1 = -1;
 };
 
 // Block size the per-thread offset-grid cache is laid out for (one LDS column per thread).
 constexpr int kGradCacheLanes = 256;
 
-// Per-thread cache of the eight corner contributions of one offset-grid cell.  Successive
-// tentative collisions of a track or shadow ray mostly fall in the same cell, so their
-// contributions are summed here and reach the grid with one atomic per corner when the
-// thread moves to another cell (and once at the end), instead of eight atomics per event.
-// Indexed [corner][threadIdx.x]: consecutive threads hit consecutive banks.
-__device__ __forceinline__ float (&grad_cache())[8][kGradCacheLanes] {
-    __shared__ float cache[8][kGradCacheLanes];
+// Per-thread cache of the eight corner contributions of two offset-grid cells.  A vertex
+// adds to its cell several times (density, each light's NDF, the phase sample's NDF) between
+// which its shadow rays walk away, and successive tentative collisions of a track or shadow
+// ray often share a cell.  Contributions are summed here and reach the grid with one atomic
+// per corner when a slot changes cell (and once at the end), instead of eight atomics per
+// event.  Slot 0 follows the vertices, slot 1 the tentative collisions; a cell is held by at
+// most one slot.  Indexed [slot][corner][threadIdx.x]: consecutive threads hit consecutive banks.
+__device__ __forceinline__ float (&grad_cache())[2][8][kGradCacheLanes] {
+    __shared__ float cache[2][8][kGradCacheLanes];
     return cache;
 }
 
-// Add the cached corner sums of the thread's current cell to the grid; empties the cache.
-__device__ __forceinline__ void flush_grad_cell(const SceneDev& S, float* __restrict__ grad_off, GradAcc& acc) {
-    if (acc.cell < 0) return;
-    float (&cache)[8][kGradCacheLanes] = grad_cache();
+// Add the cached corner sums of slot k to the grid and empty the slot.
+__device__ __forceinline__ void flush_grad_slot(const SceneDev& S, float* __restrict__ grad_off, GradAcc& acc,
+                                                int k) {
+    const int cell = k ? acc.cell1 : acc.cell0;
+    if (cell < 0) return;
+    float (&cache)[2][8][kGradCacheLanes] = grad_cache();
     const int t = threadIdx.x;
     const int sy = S.off_res[0], sz = S.off_res[0] * S.off_res[1];
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
         const int dx = n & 1, dy = (n >> 1) & 1, dz = n >> 2;
-        const float v = cache[n][t];
-        if (v != 0.0f) atomicAdd(&grad_off[acc.cell + dx + dy * sy + dz * sz], v);
+        const float v = cache[k][n][t];
+        if (v != 0.0f) atomicAdd(&grad_off[cell + dx + dy * sy + dz * sz], v);
     }
-    acc.cell = -1;
+    if (k) acc.cell1 = -1;
+    else acc.cell0 = -1;
+}
+
+// Add both cached cells to the grid (at the end of the thread's work).
+__device__ __forceinline__ void flush_grad_cell(const SceneDev& S, float* __restrict__ grad_off, GradAcc& acc) {
+    flush_grad_slot(S, grad_off, acc, 0);
+    flush_grad_slot(S, grad_off, acc, 1);
 }
 
 // d log rho = dmu * dmu_coef + dsigma * dsig_coef,  rho = phi(z)/(sigma Phi(z)), z = mu/sigma:
@@ -104,15 +117,21 @@ __device__ __forceinline__ bool dlog_ndf(float3 G, float s, float3 w, float3& dG
     return true;
 }
 
-// Add coefficients (of d mu, d grad mu, d sigma, d s at point x) to the parameter gradient.
+// Add coefficients (of d mu, d grad mu, d sigma, d s at point x) to the parameter gradient;
+// vertex: x is a real-collision vertex (cache slot 0), else a tentative collision (slot 1).
 __device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const PointQ& q, float cmu, float3 cG,
-                                             float csig, float cs, float* __restrict__ grad_off, GradAcc& acc) {
+                                             float csig, float cs, float* __restrict__ grad_off, GradAcc& acc,
+                                             bool vertex) {
     if (S.offset && grad_off) {
         const TriCell c = tri_cell(S.off_res, S.off_scale, S.lo, x);
-        const bool same = c.base == acc.cell;
-        if (!same) flush_grad_cell(S, grad_off, acc);
-        acc.cell = c.base;
-        float (&cache)[8][kGradCacheLanes] = grad_cache();
+        const bool same = c.base == acc.cell0 || c.base == acc.cell1;
+        const int k = c.base == acc.cell0 ? 0 : (c.base == acc.cell1 ? 1 : (vertex ? 0 : 1));
+        if (!same) {
+            flush_grad_slot(S, grad_off, acc, k);
+            if (k) acc.cell1 = c.base;
+            else acc.cell0 = c.base;
+        }
+        float (&cache)[2][8][kGradCacheLanes] = grad_cache();
         const int t = threadIdx.x;
         const float fx = c.fx, fy = c.fy, fz = c.fz;
         const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
@@ -123,7 +142,7 @@ __device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const 
             const float wx = dx ? fx : gx, wy = dy ? fy : gy, wz = dz ? fz : gz;
             const float sxg = dx ? 1.0f : -1.0f, syg = dy ? 1.0f : -1.0f, szg = dz ? 1.0f : -1.0f;
             const float v = cmu * (wx * wy * wz) + ax * (sxg * wy * wz) + ay * (syg * wx * wz) + az * (szg * wx * wy);
-            cache[n][t] = same ? cache[n][t] + v : v;
+            cache[k][n][t] = same ? cache[k][n][t] + v : v;
         }
     }
     if (!S.var_grid) {
@@ -141,7 +160,7 @@ __device__ __forceinline__ void add_dlog_sigma_t(const SceneDev& S, float3 x, co
     float3 dG;
     dlog_rho(q.mu, q.sigma, dmu, dsig);
     dlog_proj(q.G, q.s, d, dG, ds);
-    scatter_grad(S, x, q, c * dmu, c * dG, c * dsig, c * ds, grad_off, acc);
+    scatter_grad(S, x, q, c * dmu, c * dG, c * dsig, c * ds, grad_off, acc, false);
 }
 
 }  // namespace gpss

@@ -216,7 +216,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     float dmu, dsig;
                     dlog_rho(q.mu, q.sigma, dmu, dsig);
                     const float c = cs_f[kWpix][lt] * cs_f[kL][lt];
-                    scatter_grad(S, xf, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, io.grad_off, acc);
+                    scatter_grad(S, xf, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, io.grad_off, acc, true);
                     if (!S.albedo_per_prim && S.albedo > 0.0f) acc.alb += c / S.albedo;
                     cs_f[kEtot][lt] = 0.0f;
                     cs_f[kDin + 0][lt] = df.x;
@@ -266,7 +266,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                             float ds;
                             if (dlog_ndf(q.G, q.s, wm, dG, ds)) {
                                 const float c = cs_f[kWpix][lt] * Lafter;
-                                scatter_grad(S, to_f3(sg.o), q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc);
+                                scatter_grad(S, to_f3(sg.o), q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
                             }
                         }
                         cs_f[kL][lt] = Lafter;
@@ -416,7 +416,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     const PointQ q = point(xf);
                     if (dlog_ndf(q.G, q.s, (1.0f / hn) * h, dG, ds)) {
                         const float c = cs_f[kWpix][lt] * cs_f[kE][lt];
-                        scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc);
+                        scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
                     }
                 }
             }
