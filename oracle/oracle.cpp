@@ -715,28 +715,73 @@ void node_range(int k, int M, int R, int& lo, int& hi) {
     if (hi > R - 1) hi = R - 1;
 }
 
-// Bound for the conditioned GP (scalar prior variance s^2, isotropic kernel) over cell k,
-// given the prior mean's minimum mu_min and gradient bound gmax over the cell.  With d_j the
-// distances from observation j to the cell (nearest dmin_j, farthest dmax_j):
-//   mu_C >= mu_min + sum_j alpha_j kappa(d), kappa(d) = s^2 e^{-d^2/(2l^2)} taken at dmax_j for
-//           alpha_j > 0 and at dmin_j otherwise;
-//   |grad mu_C| <= gmax + sum_j |alpha_j| (s^2/l^2) d e^{-d^2/(2l^2)}, d = clamp(l, dmin_j, dmax_j)
-//           (the maximum of that profile over [dmin_j, dmax_j]);
-//   s_C^2 <= s^2 (conditioning never adds variance) and, writing f(x_j) = r_j f(x) + e_j with
+// Where the prior mean is smooth over cell k (cell centre c, half diagonal h): its gradient
+// at c and a bound H on the norm of its Hessian over the cell.  Plane and constant means
+// have H = 0.  A mean of signed-distance primitives qualifies when one sphere is the
+// minimum over the whole cell (its distance at c plus h stays below every other
+// primitive's minus h, the distances being 1-Lipschitz) and its centre p lies outside the
+// cell: the Hessian of |x - p| - R is (I - n n^T) / |x - p|, of norm 1 / |x - p|.
+bool prior_smooth_on_cell(const Scene& S, const int k[3], const double cwv[3], double h, double g[3], double& H) {
+    g[0] = g[1] = g[2] = 0.0;
+    H = 0.0;
+    if (S.mean_kind == 0) { g[2] = 1.0; return true; }
+    if (S.mean_kind == 2) return true;
+    double c[3];
+    for (int a = 0; a < 3; ++a) c[a] = S.lo[a] + (k[a] + 0.5) * cwv[a];
+    int best = -1;
+    double fb = INFINITY, f2 = INFINITY;
+    for (size_t i = 0; i < S.prims.size(); ++i) {
+        double f, gi[3];
+        sdf_prim(S.prims[i], c, f, gi);
+        if (f < fb) { f2 = fb; fb = f; best = (int)i; g[0] = gi[0]; g[1] = gi[1]; g[2] = gi[2]; }
+        else f2 = std::min(f2, f);
+    }
+    if (best < 0 || S.prims[best].kind != 0 || !(fb + h < f2 - h)) return false;
+    double d2 = 0.0;   // squared distance from the sphere's centre to the cell
+    for (int a = 0; a < 3; ++a) {
+        const double c0 = S.lo[a] + k[a] * cwv[a], c1 = S.lo[a] + (k[a] + 1) * cwv[a];
+        const double p = S.prims[best].c[a];
+        const double d = p < c0 ? c0 - p : (p > c1 ? p - c1 : 0.0);
+        d2 += d * d;
+    }
+    if (!(d2 > 0.0)) return false;
+    H = 1.0 / std::sqrt(d2);
+    return true;
+}
+
+// Bound for the conditioned GP (scalar prior variance s^2, isotropic kernel) over cell k
+// (centre c, half extents e_a = cw_a / 2, half diagonal h), given the prior mean's minimum
+// mu_min and gradient bound gmax over the cell.  With d_j the distances from observation j to
+// the cell (nearest dmin_j, farthest dmax_j), kappa(d) = s^2 e^{-d^2/(2l^2)} and the
+// posterior at c (mean mu_C(c), mean gradient grad mu_C(c), standard deviation s_C(c)):
+//   mean:   mu_C >= mu_min + sum_j alpha_j kappa(d), taken at dmax_j for alpha_j > 0 and at
+//           dmin_j otherwise;
+//   slope:  |grad mu_C| <= G1 = gmax + sum_j |alpha_j| (s^2/l^2) d e^{-d^2/(2l^2)},
+//           d = clamp(l, dmin_j, dmax_j) (the maximum of that profile over [dmin_j, dmax_j]);
+//           where the prior mean is smooth on the cell (prior_smooth_on_cell, Hessian norm
+//           at most H0) also |grad mu_C| <= Gb = |grad mu_C(c)| + h Hb with
+//           Hb = H0 + sum_j |alpha_j| (s^2/l^2) e^{-dmin_j^2/(2l^2)} max(1, dmax_j^2/l^2 - 1)
+//           (the Hessian of kappa(x - x_j) has eigenvalues (s^2/l^2) e^{-r^2/(2l^2)} times
+//           r^2/l^2 - 1 and -1), and by Taylor's theorem
+//           mu_C >= mu_C(c) - sum_a e_a |d mu_C(c) / dx_a| - Hb h^2 / 2;
+//           G is the smaller slope bound, and mu_C >= mu_C(c) - h G in any case;
+//   spread: s_C <= s (conditioning never adds variance); writing f(x_j) = r_j f(x) + e_j with
 //           e_j independent of f(x) and the observation noise at least s_n^2 I,
 //           1/s_C^2 <= 1/s^2 + sum_j r_j^2 / s_n^2, r_j^2 = e^{-d_j^2/l^2} <= e^{-dmin_j^2/l^2};
-//   the conditioned gradient g ~ N(m, Sigma) has Sigma <= (s/l)^2 I and
-//           |m| <= |grad mu_C| + (s/l) |z|, z = mu_C / s_C (Cauchy-Schwarz on the posterior
-//           covariance of f(x) and grad f(x)), so sigma_proj <= |m| + (s/l) / sqrt(2 pi);
-//   rho = r(z) / s_C with r = phi / Phi decreasing, z >= z_lo = mu_lo / (mu_lo > 0 ? s : s_lo),
-//           and r(z) |z| <= max(0.3, r(z_lo) max(0, -z_lo)) (its supremum over z >= 0 is 0.2945).
-// Two more lower bounds from the posterior at the cell centre c and the half diagonal h:
-//   mu_C >= mu_C(c) - h |grad mu_C|max, and s_C >= s_C(c) - h s / l, since grad s_C =
-//   cov(grad f, f) / s_C has length at most s / l (the Cauchy-Schwarz bound above);
-// each of mu_lo and s_lo is the larger of its two bounds.
+//           grad s_C = cov(grad f, f) / s_C has length at most s / l (Cauchy-Schwarz), so
+//           s_C(c) - h s/l <= s_C <= s_C(c) + h s/l;
+//   each of mu_lo, s_lo is the largest of its lower bounds, s_up the smaller upper bound.
+// The gradient given f = 0 is N(m, Sigma) with Sigma <= (s/l)^2 I and |m| <= G + (s/l) |z|,
+// z = mu_C / s_C (Cauchy-Schwarz again), so with sd = s/l and
+// F(M, sd) = sd phi(M/sd) + M Phi(M/sd), increasing in both arguments and 1-Lipschitz in M,
+//   sigma_proj <= F(G + sd |z|, sd),   rho = r(z) / s_C <= r(z) / s_lo,  r = phi/Phi decreasing,
+// and z >= z_lo = mu_lo / (mu_lo > 0 ? s_up : s_lo).  Over z in [z_lo, 0) the product is at
+// most r(z_lo) F(G + sd |z_lo|, sd) / s_lo; over z >= z0 = max(z_lo, 0) at most
+// (r(z0) F(G, sd) + sd sup_{z >= z0} z r(z)) / s_lo, where z r(z) peaks at 0.29453 (z = 0.84)
+// and decreases beyond, so the supremum is z0 r(z0) for z0 >= 0.9 and 0.2946 otherwise.
 double cond_bound(const Scene& S, const int k[3], const double cwv[3], double mu_min, double gmax) {
     const double l = S.l, s2 = S.variance;
-    double mu_c = 0.0, g_c = 0.0, prec = 1.0 / s2;
+    double mu_c = 0.0, g_c = 0.0, prec = 1.0 / s2, hb = 0.0;
     for (int j = 0; j < S.n_obs; ++j) {
         const double* xj = &S.obs_x[3 * (size_t)j];
         double dn2 = 0.0, df2 = 0.0;
@@ -753,18 +798,33 @@ double cond_bound(const Scene& S, const int k[3], const double cwv[3], double mu
         const double dd = std::min(std::max(l, dmin), dmax);
         g_c += std::fabs(al) * (s2 / (l * l)) * dd * std::exp(-dd * dd / (2.0 * l * l));
         prec += std::exp(-dn2 / (l * l)) / S.obs_noise;
+        hb += std::fabs(al) * (s2 / (l * l)) * std::exp(-dn2 / (2.0 * l * l)) * std::max(1.0, df2 / (l * l) - 1.0);
     }
-    const double G1 = gmax + g_c;
     const double s_hi = std::sqrt(s2), sl = s_hi / l;
-    double c[3], g0[3] = {0.0, 0.0, 0.0};
+    double c[3], g0[3], H0;
     for (int a = 0; a < 3; ++a) c[a] = S.lo[a] + (k[a] + 0.5) * cwv[a];
     const double hdiag = 0.5 * std::sqrt(cwv[0] * cwv[0] + cwv[1] * cwv[1] + cwv[2] * cwv[2]);
+    const bool smooth = prior_smooth_on_cell(S, k, cwv, hdiag, g0, H0);
     const Posterior P = posterior_at(S, c, prior_mean(S, c), g0);
-    const double mu_lo = std::max(mu_min + mu_c, P.mu - hdiag * G1);
-    const double s_lo = std::max(1.0 / std::sqrt(prec), std::sqrt(std::max(P.var, 0.0)) - hdiag * sl);
-    const double z_lo = mu_lo / (mu_lo > 0.0 ? s_hi : s_lo);
-    const double R = r_ratio(z_lo);
-    return (R * (G1 + sl / kSqrt2Pi) + sl * std::max(0.3, R * std::max(0.0, -z_lo))) / s_lo;
+    double G = gmax + g_c;
+    double mu_lo = mu_min + mu_c;
+    if (smooth) {
+        const double Hb = H0 + hb;
+        G = std::min(G, std::sqrt(dot3(P.g, P.g)) + hdiag * Hb);
+        double lin = 0.0;
+        for (int a = 0; a < 3; ++a) lin += 0.5 * cwv[a] * std::fabs(P.g[a]);
+        mu_lo = std::max(mu_lo, P.mu - lin - 0.5 * Hb * hdiag * hdiag);
+    }
+    mu_lo = std::max(mu_lo, P.mu - hdiag * G);
+    const double s_c = std::sqrt(std::max(P.var, 0.0));
+    const double s_lo = std::max(1.0 / std::sqrt(prec), s_c - hdiag * sl);
+    const double s_up = std::min(s_hi, s_c + hdiag * sl);
+    const double z_lo = mu_lo / (mu_lo > 0.0 ? s_up : s_lo);
+    auto F = [&](double M) { return sl * phi_d(M / sl) + M * Phi_d(M / sl); };
+    const double neg = r_ratio(z_lo) * F(G + sl * std::max(0.0, -z_lo));
+    const double z0 = std::max(z_lo, 0.0);
+    const double pos = r_ratio(z0) * F(G) + sl * (z0 >= 0.9 ? z0 * r_ratio(z0) : 0.2946);
+    return std::max(neg, pos) / s_lo;
 }
 
 void build_majorants(Scene& S) {

@@ -65,19 +65,70 @@ __device__ __forceinline__ void node_range(int k, int M, int R, int& lo, int& hi
     hi = min(hi, R - 1);
 }
 
+// Prior mean smooth over cell k (centre c, half diagonal h): its gradient g at c and a bound
+// H of its Hessian norm over the cell.  Plane and constant means: H = 0.  Signed-distance
+// primitives: only when one sphere is the minimum on the whole cell (its distance at c plus
+// h below every other primitive's minus h; distances are 1-Lipschitz) and its centre p is
+// outside the cell, where |x - p| - R has Hessian norm 1 / |x - p|.  Returns false otherwise.
+__device__ bool prior_smooth(const MajArgs& A, const int k[3], const double cw[3], const double c[3], double h,
+                             double g[3], double& H) {
+    g[0] = g[1] = g[2] = 0.0;
+    H = 0.0;
+    if (A.mean_kind == 0) {
+        g[2] = 1.0;
+        return true;
+    }
+    if (A.mean_kind == 2) return true;
+    int best = -1;
+    double fb = INFINITY, f2 = INFINITY;
+    for (int i = 0; i < A.n_prims; ++i) {
+        const double f = sdf_prim_d(A.prims[2 * i], A.prims[2 * i + 1], c);
+        if (f < fb) {
+            f2 = fb;
+            fb = f;
+            best = i;
+        } else {
+            f2 = fmin(f2, f);
+        }
+    }
+    if (best < 0 || A.prims[2 * best].x >= 0.5f || !(fb + h < f2 - h)) return false;
+    const float4 P = A.prims[2 * best];
+    const double p[3] = {(double)P.y, (double)P.z, (double)P.w};
+    double d2 = 0.0, v2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double c0 = (double)A.lo[a] + k[a] * cw[a], c1 = (double)A.lo[a] + (k[a] + 1) * cw[a];
+        const double d = p[a] < c0 ? c0 - p[a] : (p[a] > c1 ? p[a] - c1 : 0.0);
+        d2 += d * d;
+        v2 += (c[a] - p[a]) * (c[a] - p[a]);
+    }
+    if (!(d2 > 0.0)) return false;
+    const double r = sqrt(v2);
+    for (int a = 0; a < 3; ++a) g[a] = (c[a] - p[a]) / r;
+    H = 1.0 / sqrt(d2);
+    return true;
+}
+
 // Bound for the GP conditioned on point observations (scalar variance s^2, isotropic
-// kernel), from the prior mean's minimum mu_min, gradient bound gmax and value mu_c at the
-// cell centre c.  With dmin_j, dmax_j the nearest and farthest distances from observation j
-// to the cell and kappa(d) = s^2 e^{-d^2/(2 l^2)}:
-//   mu_C >= mu_min + sum_j alpha_j kappa(alpha_j > 0 ? dmax_j : dmin_j), and
-//   mu_C >= mu_C(c) - h |grad mu_C|max (h the half diagonal), where
+// kernel) over cell k (centre c, half extents e_a, half diagonal h), from the prior mean's
+// minimum mu_min, gradient bound gmax and value mu_c at c.  With dmin_j, dmax_j the nearest
+// and farthest distances from observation j to the cell, kappa(d) = s^2 e^{-d^2/(2 l^2)} and
+// the posterior mean, mean gradient and standard deviation at c:
+//   mu_C >= mu_min + sum_j alpha_j kappa(alpha_j > 0 ? dmax_j : dmin_j);
 //   |grad mu_C| <= gmax + sum_j |alpha_j| (s^2/l^2) d e^{-d^2/(2l^2)}, d = clamp(l, dmin_j, dmax_j);
+//   where the prior mean is smooth on the cell (Hessian norm <= H0, prior_smooth), with
+//   Hb = H0 + sum_j |alpha_j| (s^2/l^2) e^{-dmin_j^2/(2l^2)} max(1, dmax_j^2/l^2 - 1) bounding
+//   the Hessian of mu_C: |grad mu_C| <= |grad mu_C(c)| + h Hb and (Taylor)
+//   mu_C >= mu_C(c) - sum_a e_a |d mu_C(c)/dx_a| - Hb h^2 / 2;  G is the smaller slope bound;
+//   mu_C >= mu_C(c) - h G;
 //   s_C <= s;  1/s_C^2 <= 1/s^2 + sum_j e^{-dmin_j^2/l^2} / s_n^2 (f(x_j) = r_j f(x) + e_j with
-//   e_j independent of f(x) and noise >= s_n^2 I), and s_C >= s_C(c) - h s/l (|grad s_C| =
-//   |cov(grad f, f)| / s_C <= s/l by Cauchy-Schwarz);
-//   the conditioned gradient g ~ N(m, Sigma): Sigma <= (s/l)^2 I, |m| <= |grad mu_C| + (s/l)|z|,
-//   so sigma_proj <= |m| + (s/l)/sqrt(2 pi);  rho = r(z)/s_C, r = phi/Phi decreasing,
-//   z >= z_lo = mu_lo / (mu_lo > 0 ? s : s_lo), r(z)|z| <= max(0.3, r(z_lo) max(0, -z_lo)).
+//   e_j independent of f(x) and noise >= s_n^2 I), and |grad s_C| = |cov(grad f, f)| / s_C
+//   <= s/l (Cauchy-Schwarz), so s_C(c) -+ h s/l bound s_C from both sides;
+//   the conditioned gradient g ~ N(m, Sigma): Sigma <= (s/l)^2 I, |m| <= G + (s/l)|z|, so
+//   sigma_proj <= F(G + (s/l)|z|, s/l) with F(M, sd) = sd phi(M/sd) + M Phi(M/sd) (increasing
+//   in both, 1-Lipschitz in M);  rho = r(z)/s_C, r = phi/Phi decreasing,
+//   z >= z_lo = mu_lo / (mu_lo > 0 ? s_up : s_lo).  Over z < 0: r(z_lo) F(G + (s/l)|z_lo|) / s_lo;
+//   over z >= z0 = max(z_lo, 0): (r(z0) F(G) + (s/l) sup_{z >= z0} z r(z)) / s_lo, the supremum
+//   being z0 r(z0) for z0 >= 0.9 (z r(z) peaks at 0.29453 near z = 0.84) and 0.2946 otherwise.
 __device__ double cond_bound(const MajArgs& A, const int k[3], const double cw[3], double hdiag,
                              double mu_min, double gmax, double mu_c) {
     const int n = A.n_obs;
@@ -85,13 +136,17 @@ __device__ double cond_bound(const MajArgs& A, const int k[3], const double cw[3
     const double* al = A.obs_d + 3 * n;
     const double* Li = A.obs_d + 4 * n;
     const double l = (double)A.lengthscale, s2 = (double)A.variance;
+    const double il2 = 1.0 / (l * l);
     double c[3], lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
         lo[a] = (double)A.lo[a] + k[a] * cw[a];
         hi[a] = (double)A.lo[a] + (k[a] + 1) * cw[a];
         c[a] = (double)A.lo[a] + (k[a] + 0.5) * cw[a];
     }
-    double mu_obs = 0.0, g_obs = 0.0, prec = 1.0 / s2, mu_p = mu_c;
+    double g0[3], H0;
+    const bool smooth = prior_smooth(A, k, cw, c, hdiag, g0, H0);
+    double mu_obs = 0.0, g_obs = 0.0, prec = 1.0 / s2, mu_p = mu_c, hb = 0.0;
+    double gp[3] = {g0[0], g0[1], g0[2]};
     double kc[kMaxObs];
 #pragma unroll
     for (int j = 0; j < kMaxObs; ++j) {
@@ -111,8 +166,10 @@ __device__ double cond_bound(const MajArgs& A, const int k[3], const double cw[3
             const double dd = fmin(fmax(l, sqrt(dn2)), sqrt(df2));
             g_obs += fabs(a_j) * (s2 / (l * l)) * dd * exp(-dd * dd / (2.0 * l * l));
             prec += exp(-dn2 / (l * l)) / A.obs_noise;
+            hb += fabs(a_j) * (s2 / (l * l)) * exp(-dn2 / (2.0 * l * l)) * fmax(1.0, df2 / (l * l) - 1.0);
             kc[j] = s2 * exp(-dc2 / (2.0 * l * l));
             mu_p += kc[j] * a_j;
+            for (int a = 0; a < 3; ++a) gp[a] += -kc[j] * (c[a] - X[3 * j + a]) * il2 * a_j;
         }
     }
     double ww = 0.0;
@@ -125,13 +182,33 @@ __device__ double cond_bound(const MajArgs& A, const int k[3], const double cw[3
         }
         ww += w * w;
     }
-    const double G1 = gmax + g_obs;
     const double s_hi = sqrt(s2), sl = s_hi / l;
-    const double mu_lo = fmax(mu_min + mu_obs, mu_p - hdiag * G1);
-    const double s_lo = fmax(1.0 / sqrt(prec), sqrt(fmax(s2 - ww, 0.0)) - hdiag * sl);
-    const double z_lo = mu_lo / (mu_lo > 0.0 ? s_hi : s_lo);
-    const double R = sqrt(2.0 / 3.14159265358979323846) / erfcx(-z_lo / 1.41421356237309504880);
-    return (R * (G1 + sl / 2.50662827463100050242) + sl * fmax(0.3, R * fmax(0.0, -z_lo))) / s_lo;
+    double G = gmax + g_obs;
+    double mu_lo = mu_min + mu_obs;
+    if (smooth) {
+        const double Hb = H0 + hb;
+        G = fmin(G, sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2]) + hdiag * Hb);
+        double lin = 0.0;
+        for (int a = 0; a < 3; ++a) lin += 0.5 * cw[a] * fabs(gp[a]);
+        mu_lo = fmax(mu_lo, mu_p - lin - 0.5 * Hb * hdiag * hdiag);
+    }
+    mu_lo = fmax(mu_lo, mu_p - hdiag * G);
+    const double s_c = sqrt(fmax(s2 - ww, 0.0));
+    const double s_lo = fmax(1.0 / sqrt(prec), s_c - hdiag * sl);
+    const double s_up = fmin(s_hi, s_c + hdiag * sl);
+    const double z_lo = mu_lo / (mu_lo > 0.0 ? s_up : s_lo);
+    const double kR = sqrt(2.0 / 3.14159265358979323846);
+    const double kS2 = 1.41421356237309504880, kS2Pi = 2.50662827463100050242;
+    // F(M, sl) with M >= 0
+    auto F = [&](double M) {
+        const double t = M / sl;
+        return sl * (exp(-0.5 * t * t) / kS2Pi) + M * (0.5 * erfc(-t / kS2));
+    };
+    const double neg = kR / erfcx(-z_lo / kS2) * F(G + sl * fmax(0.0, -z_lo));
+    const double z0 = fmax(z_lo, 0.0);
+    const double r0 = kR / erfcx(-z0 / kS2);
+    const double pos = r0 * F(G) + sl * (z0 >= 0.9 ? z0 * r0 : 0.2946);
+    return fmax(neg, pos) / s_lo;
 }
 
 __global__ void majorant_kernel(MajArgs A, float* __restrict__ out) {
