@@ -176,12 +176,14 @@ __global__ __launch_bounds__(256, GPSS_ADJ_MIN_WAVES) void adjoint_kernel(SceneD
                                                                          uint32_t ns, uint64_t npaths) {
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     GradAcc acc{0.0f, 0.0f, 0.0f};
+    grad_table_init();
     if (p < npaths) {
         const uint32_t pixel = (uint32_t)(p / ns), sample = s0 + (uint32_t)(p % ns);
         const float wpix = dloss[pixel] / (float)ns;
         if (wpix != 0.0f) replay_path(S, pixel, sample, paths[p], wpix, grad_off, acc);
     }
     flush_grad_cell(S, grad_off, acc);
+    grad_table_flush(grad_off);
     float v[3] = {acc.var, acc.len, acc.alb};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -216,8 +218,10 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_adjoint_kerne
     src.ns = ns;
     GradAcc acc{0.0f, 0.0f, 0.0f};
     __shared__ SchedLds<true> lds;
+    grad_table_init();
     run_scheduled<false, true, kMedIso>(S, src, nullptr, st, io, acc, lds);
     flush_grad_cell(S, io.grad_off, acc);
+    grad_table_flush(io.grad_off);
     float v[3] = {acc.var, acc.len, acc.alb};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {

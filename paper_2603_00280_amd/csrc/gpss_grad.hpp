@@ -20,16 +20,81 @@ constexpr int kGradCacheLanes = 256;
 // Per-thread cache of the eight corner contributions of two offset-grid cells.  A vertex
 // adds to its cell several times (density, each light's NDF, the phase sample's NDF) between
 // which its shadow rays walk away, and successive tentative collisions of a track or shadow
-// ray often share a cell.  Contributions are summed here and reach the grid with one atomic
-// per corner when a slot changes cell (and once at the end), instead of eight atomics per
-// event.  Slot 0 follows the vertices, slot 1 the tentative collisions; a cell is held by at
-// most one slot.  Indexed [slot][corner][threadIdx.x]: consecutive threads hit consecutive banks.
+// ray often share a cell.  Contributions are summed here and move on (eight corner values)
+// only when a slot changes cell, and once at the end, into the workgroup table below.  Slot
+// 0 follows the vertices, slot 1 the tentative collisions; a cell is held by at most one
+// slot.  Indexed [slot][corner][threadIdx.x]: consecutive threads hit consecutive banks.
 __device__ __forceinline__ float (&grad_cache())[2][8][kGradCacheLanes] {
     __shared__ float cache[2][8][kGradCacheLanes];
     return cache;
 }
 
-// Add the cached corner sums of slot k to the grid and empty the slot.
+// Second level: a workgroup-shared, direct-mapped table of offset-grid nodes in LDS.  The
+// workgroup's 256 lanes trace neighbouring paths, whose cells recur across lanes and over
+// time; a thread's cache evictions are summed into the table and reach the grid when a
+// table entry is taken by another node, or at the end of the kernel.  An entry packs
+// (node + 1, float bits of its sum) in 64 bits (0: empty) and changes by compare-and-swap
+// only, so every value is added exactly once: either into the entry, or by the lane whose
+// swap evicted it, or (after kGradTableTries failed swaps under contention) directly.
+constexpr int kGradTableLog2 = 10;
+constexpr int kGradTable = 1 << kGradTableLog2;   // 8 KiB of LDS per workgroup
+constexpr int kGradTableTries = 4;
+
+__device__ __forceinline__ unsigned long long* grad_table() {
+    __shared__ unsigned long long table[kGradTable];
+    return table;
+}
+
+// Empty the table; every thread of the workgroup calls this before any gradient term.
+__device__ __forceinline__ void grad_table_init() {
+    unsigned long long* T = grad_table();
+    for (int e = threadIdx.x; e < kGradTable; e += blockDim.x) T[e] = 0ull;
+    __syncthreads();
+}
+
+// Add what the table holds to the grid; every thread of the workgroup calls this after its
+// last gradient term.
+__device__ __forceinline__ void grad_table_flush(float* __restrict__ grad_off) {
+    __syncthreads();
+    if (!grad_off) return;
+    const unsigned long long* T = grad_table();
+    for (int e = threadIdx.x; e < kGradTable; e += blockDim.x) {
+        const unsigned long long v = T[e];
+        const uint32_t key = (uint32_t)(v >> 32);
+        if (key) atomicAdd(&grad_off[key - 1u], __uint_as_float((uint32_t)v));
+    }
+}
+
+// Add val[n] to grid node node[n] (n < 8) through the table.  The eight swaps of a round are
+// independent, so their LDS round trips overlap.
+__device__ __forceinline__ void grad_table_add8(float* __restrict__ grad_off, const int node[8], const float val[8]) {
+    unsigned long long* T = grad_table();
+    unsigned pending = 0u;
+#pragma unroll
+    for (int n = 0; n < 8; ++n)
+        if (val[n] != 0.0f) pending |= 1u << n;
+    for (int round = 0; round < kGradTableTries && pending; ++round) {
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            if (!((pending >> n) & 1u)) continue;
+            const uint32_t mine = (uint32_t)node[n] + 1u;
+            const uint32_t e = ((uint32_t)node[n] * 2654435761u) >> (32 - kGradTableLog2);   // Fibonacci hashing
+            const unsigned long long old = T[e];
+            const uint32_t key = (uint32_t)(old >> 32);
+            const float sum = key == mine ? __uint_as_float((uint32_t)old) + val[n] : val[n];
+            const unsigned long long next = ((unsigned long long)mine << 32) | (unsigned long long)__float_as_uint(sum);
+            if (atomicCAS(&T[e], old, next) == old) {
+                if (key != mine && key != 0u) atomicAdd(&grad_off[key - 1u], __uint_as_float((uint32_t)old));
+                pending &= ~(1u << n);
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < 8; ++n)
+        if ((pending >> n) & 1u) atomicAdd(&grad_off[node[n]], val[n]);
+}
+
+// Move the cached corner sums of slot k into the workgroup table and empty the slot.
 __device__ __forceinline__ void flush_grad_slot(const SceneDev& S, float* __restrict__ grad_off, GradAcc& acc,
                                                 int k) {
     const int cell = k ? acc.cell1 : acc.cell0;
@@ -37,17 +102,20 @@ __device__ __forceinline__ void flush_grad_slot(const SceneDev& S, float* __rest
     float (&cache)[2][8][kGradCacheLanes] = grad_cache();
     const int t = threadIdx.x;
     const int sy = S.off_res[0], sz = S.off_res[0] * S.off_res[1];
+    int node[8];
+    float val[8];
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
         const int dx = n & 1, dy = (n >> 1) & 1, dz = n >> 2;
-        const float v = cache[k][n][t];
-        if (v != 0.0f) atomicAdd(&grad_off[cell + dx + dy * sy + dz * sz], v);
+        node[n] = cell + dx + dy * sy + dz * sz;
+        val[n] = cache[k][n][t];
     }
+    grad_table_add8(grad_off, node, val);
     if (k) acc.cell1 = -1;
     else acc.cell0 = -1;
 }
 
-// Add both cached cells to the grid (at the end of the thread's work).
+// Move both cached cells into the workgroup table (at the end of the thread's work).
 __device__ __forceinline__ void flush_grad_cell(const SceneDev& S, float* __restrict__ grad_off, GradAcc& acc) {
     flush_grad_slot(S, grad_off, acc, 0);
     flush_grad_slot(S, grad_off, acc, 1);

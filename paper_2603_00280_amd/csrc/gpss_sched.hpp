@@ -81,9 +81,10 @@ struct AdjointIo {
 // each path's radiance to paths[slot].  Adjoint form: replay each path with weight
 // dloss[pixel] / ns against its forward radiance and accumulate the parameter gradient
 // (frozen-sampling estimator; the terms are those of the one-thread replay in
-// gpss_adjoint.hip) into io.grad_off and acc; the caller adds the lane's cached offset-grid
-// cell with flush_grad_cell afterwards.  Must be called by whole waves; returns when the
-// source is exhausted and every lane's path has ended.
+// gpss_adjoint.hip) into io.grad_off and acc; the caller empties the workgroup's gradient
+// table before (grad_table_init) and adds the lane's cached cells and the table to the grid
+// after (flush_grad_cell, grad_table_flush).  Must be called by whole waves; returns when
+// the source is exhausted and every lane's path has ended.
 // MED: the scene's medium when the kernel is specialized for it (kMedIso generalized with the
 // isotropic kernel, kMedGgx, kMedAniso generalized with the anisotropic kernel), so that
 // the other media's code is not compiled in; kMedAny takes everything from the scene record.
