@@ -57,6 +57,27 @@ def test_adjoint_matches_oracle_dual_gradient(G, perturbed, kernel):
     _check_groups(g_gpu, g_orc)
 
 
+@pytest.mark.parametrize("kernel", ["persistent", "mega"])
+def test_adjoint_coarse_grid_contention(G, kernel):
+    """A 3^3 offset grid: every gradient term of every lane lands on the same 27 nodes, so the
+    workgroup table's entries are contended (its bounded swaps fall back to direct atomics)
+    and evicted all the time; the gradient still equals the oracle's, all nodes compared."""
+    s0 = sc.offset_sphere_scene(False, width=48, height=48, spp=8, max_depth=8, grid_res=3)
+    s0.offset_grid = np.random.default_rng(11).normal(0, 0.01, s0.offset_grid.shape).astype(np.float32)
+    tgt = sc.offset_sphere_scene(True, width=48, height=48, spp=8, max_depth=8, grid_res=3)
+    dl = _dloss(s0, tgt)
+    ids = [-1, -2, -3] + list(range(27))
+    print(f"[adjoint] coarse grid {kernel} 48x48 spp 8, params {len(ids)}", flush=True)
+    g_orc, _ = orc.OracleScene(s0).render_grad(dl, ids)
+    g = G.GpssScene(s0, kernel=kernel)
+    g_off, g_sc = g.render_adjoint(torch.as_tensor(dl, dtype=torch.float32))
+    torch.cuda.synchronize()
+    g_off = g_off.cpu().numpy().ravel()
+    g_sc = g_sc.cpu().numpy()
+    g_gpu = np.array([g_sc[0], g_sc[1], g_sc[2]] + [g_off[i] for i in ids[3:]], np.float64)
+    _check_groups(g_gpu, g_orc)
+
+
 def _check_groups(g_gpu, g_orc):
     """Scalars and grid nodes separately: each within 1e-3 of its group's largest entry."""
     assert np.isfinite(g_gpu).all()
