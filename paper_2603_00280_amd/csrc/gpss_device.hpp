@@ -83,6 +83,27 @@ struct SceneDev {
     uint32_t key0, key1;
 };
 
+// Load from a scene array through the global address space.  The arrays are reached through
+// pointers held in the scene record, whose address space the compiler cannot infer; plain
+// loads would be flat loads, which also count on the LDS counter and so delay every LDS wait
+// of the scheduled loop behind a memory access.
+__device__ __forceinline__ float ld_global(const float* p) {
+    return *(const __attribute__((address_space(1))) float*)p;
+}
+__device__ __forceinline__ float4 ld_global(const float4* p) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *(const __attribute__((address_space(1))) v4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+// The same for arrays that no kernel writes while it reads them (primitives, observations):
+// through the constant address space, a load whose address is the same for the whole wave
+// becomes one scalar load.
+__device__ __forceinline__ float4 ld_const(const float4* p) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *(const __attribute__((address_space(4))) v4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // ---------------------------------------------------------------------------
 // float3 helpers
 // ---------------------------------------------------------------------------
@@ -239,7 +260,7 @@ __device__ __forceinline__ void mean_geom(const SceneDev& S, float3 x, float& f,
     float3 bg = f3(0.0f, 0.0f, 1.0f);
     for (int i = 0; i < S.n_prims; ++i) {
         float3 gi;
-        const float fi = sdf_prim(S.prims[2 * i], S.prims[2 * i + 1], x, gi);
+        const float fi = sdf_prim(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
         if (fi < best) { best = fi; bg = gi; which = i; }
     }
     f = best;
@@ -274,9 +295,10 @@ __device__ __forceinline__ TriCell tri_cell(const int res[3], const float scale[
 __device__ __forceinline__ float tri_eval(const float* __restrict__ g, const int res[3], const float scale[3],
                                           const TriCell& c, float3* grad) {
     const int sx = 1, sy = res[0], sz = res[0] * res[1];
-    const float v000 = g[c.base], v100 = g[c.base + sx], v010 = g[c.base + sy], v110 = g[c.base + sx + sy];
-    const float v001 = g[c.base + sz], v101 = g[c.base + sx + sz], v011 = g[c.base + sy + sz],
-                v111 = g[c.base + sx + sy + sz];
+    const float v000 = ld_global(g + c.base), v100 = ld_global(g + c.base + sx), v010 = ld_global(g + c.base + sy),
+                v110 = ld_global(g + c.base + sx + sy);
+    const float v001 = ld_global(g + c.base + sz), v101 = ld_global(g + c.base + sx + sz),
+                v011 = ld_global(g + c.base + sy + sz), v111 = ld_global(g + c.base + sx + sy + sz);
     const float fx = c.fx, fy = c.fy, fz = c.fz;
     const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
     const float x00 = gx * v000 + fx * v100, x10 = gx * v010 + fx * v110;
@@ -331,7 +353,7 @@ __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
     q.ggx = S.ggx;
     q.feta = S.f_eta;
     q.fk = S.f_k;
-    q.albedo = (S.albedo_per_prim && which >= 0) ? S.prims[2 * which + 1].w : S.albedo;
+    q.albedo = (S.albedo_per_prim && which >= 0) ? ld_const(S.prims + 2 * which + 1).w : S.albedo;
     q.cond = 0;
     return q;
 }
@@ -361,7 +383,7 @@ __device__ __forceinline__ void condition_point(const SceneDev& S, float3 x, Poi
     float am = 0.0f;
     float3 amx = f3(0.0f, 0.0f, 0.0f);
     for (int j = 0; j < n; ++j) {
-        const float4 o = S.obs[j];
+        const float4 o = ld_const(S.obs + j);
         const float3 d = xr - f3(o.x, o.y, o.z);
         const float kj = var * expf(-0.5f * il2 * dot(d, d));
         kl[j][lt] = kj;
@@ -380,7 +402,7 @@ __device__ __forceinline__ void condition_point(const SceneDev& S, float3 x, Poi
         float3 P = f3(0.0f, 0.0f, 0.0f);
 #pragma unroll 4
         for (int j = 0; j <= i; ++j) {
-            const float4 b = row[j];
+            const float4 b = ld_const(row + j);
             const float kj = kl[j][lt];
             w = fmaf(b.x, kj, w);
             P.x = fmaf(b.y, kj, P.x);
@@ -851,7 +873,7 @@ struct Walker {
             s = 0;
         }
     }
-    __device__ __forceinline__ float majorant(const SceneDev& S) const { return S.maj[idx]; }
+    __device__ __forceinline__ float majorant(const SceneDev& S) const { return ld_global(S.maj + idx); }
     // distance along the ray to the exit of the current cell and the axis crossed (ties go
     // to the lower axis)
     __device__ __forceinline__ double exit(int& ax) const {
