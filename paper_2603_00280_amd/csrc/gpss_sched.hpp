@@ -35,7 +35,7 @@ enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBe
 #endif
 // the conditioned GP's evaluation costs about thirty times the others': it waits for fuller waves
 #ifndef GPSS_SCHED_EVAL_MIN_COND
-#define GPSS_SCHED_EVAL_MIN_COND 40
+#define GPSS_SCHED_EVAL_MIN_COND 32
 #endif
 #ifndef GPSS_SCHED_BEGIN_MIN
 #define GPSS_SCHED_BEGIN_MIN 16
