@@ -324,16 +324,18 @@ int prepare_observations(gpss_scene* s, const gpss_scene_desc& D) {
     }
     float origin[3];
     for (int a = 0; a < 3; ++a) origin[a] = 0.5f * (D.bounds[a] + D.bounds[3 + a]);
-    // kMaxObs float4 (position - origin, alpha), then the lower triangle of L^-1 row by row as
-    // float4 (L^-1_ij, L^-1_ij (x_j - origin)), formed in double and rounded once
-    std::vector<float> F(4 * gpss::kMaxObs + 4 * (size_t)gpss::kMaxObs * (gpss::kMaxObs + 1) / 2, 0.0f);
+    // kMaxObs float4 (position - origin, alpha; zeros beyond n), then the lower triangle of
+    // L^-1 row by row as float4 (L^-1_ij, L^-1_ij (x_j - origin)), formed in double and
+    // rounded once, each row zero-padded to 4 cond_row_blocks(i) entries
+    std::vector<float> F(4 * gpss::kMaxObs + 4 * (size_t)gpss::kCondTriEntries, 0.0f);
     for (int j = 0; j < n; ++j) {
         for (int a = 0; a < 3; ++a) F[4 * j + a] = D.observations[4 * j + a] - origin[a];
         F[4 * j + 3] = (float)alpha[j];
     }
     size_t e = 4 * gpss::kMaxObs;
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j <= i; ++j, e += 4) {
+        for (int j = 0; j < 4 * gpss::cond_row_blocks(i); ++j, e += 4) {
+            if (j > i) continue;   // padding stays zero
             const double v = Li[(size_t)i * n + j];
             F[e] = (float)v;
             for (int a = 0; a < 3; ++a) F[e + 1 + a] = (float)(v * ((double)D.observations[4 * j + a] - (double)origin[a]));

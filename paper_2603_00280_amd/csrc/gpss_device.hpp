@@ -20,7 +20,17 @@ constexpr float kInv2PiPow1p5 = 0.06349363593424096978f;   // (2 pi)^(-3/2)
 constexpr float kSqrt2 = 1.41421356237309504880f;
 
 constexpr int kMaxPrims = 64;
-constexpr int kMaxObs = 32;                 // observations of a conditioned GP
+constexpr int kMaxObs = 32;                 // observations of a conditioned GP (a multiple of 4)
+// Stored lower triangle of L^-1: row i zero-padded to cond_row_blocks(i) blocks of four
+// entries, each block one 64-byte scalar load against four k_j of one LDS read.
+constexpr int cond_row_blocks(int i) { return (i >> 2) + 1; }
+constexpr int cond_tri_entries(int n) {
+    int t = 0;
+    for (int i = 0; i < n; ++i) t += 4 * cond_row_blocks(i);
+    return t;
+}
+constexpr int kCondTriEntries = cond_tri_entries(kMaxObs);
+static_assert(kMaxObs % 4 == 0, "observations are processed four at a time");
 
 // Scheduling policy of the persistent tracer for one scene: cell steps per walk operation and
 // the lanes a scatter operation waits for.  Rough media (largest gradient spread
@@ -64,7 +74,8 @@ struct SceneDev {
     int n_obs;                    // observations conditioning the GP (0: unconditioned)
     const float4* obs;            // per observation: position relative to obs_c, weight alpha
     const float4* obs_tri;        // lower triangle of L^-1 (L L^T = kappa(C,C) + noise I), row by row:
-                                  // (L^-1_ij, L^-1_ij x_j) for j <= i, positions relative to obs_c
+                                  // (L^-1_ij, L^-1_ij x_j) for j <= i, positions relative to obs_c,
+                                  // each row zero-padded to 4 cond_row_blocks(i) entries
     float obs_c[3];               // origin of the observation positions
     float albedo;
     int albedo_per_prim;
@@ -367,14 +378,16 @@ __device__ __forceinline__ PointQ eval_point(const SceneDev& S, float3 x) {
 // W_a is formed as -(1/l^2) (x_a w - P_a), P_a = sum_j (L^-1_ij x_ja) k_j, so that one pass
 // over the lower triangle of L^-1 gives all four right-hand sides with four FMAs per entry,
 // the entry's (L^-1_ij, L^-1_ij x_j) being one wave-uniform float4 (a scalar load), while only
-// k_j is kept per lane, in that lane's column of an LDS array (no lane reads another's
-// column: no barrier).  The gradient given f(x) = 0 (the surface)
-// then has mean grad mu_C - c mu_C / var_C and covariance Sgg - c c^T / var_C, kept as its
-// Cholesky factor; s (used only by the proposal) is the root of a third of its trace.
+// k_j is kept per lane, four to a float4 in that lane's column of an LDS array (no lane
+// reads another's column: no barrier).  Rows are zero-padded to whole blocks of four
+// entries; a padded entry adds 0 * k_j exactly, so the sums are those of the bare triangle.
+// The gradient given f(x) = 0 (the surface) then has mean grad mu_C - c mu_C / var_C and
+// covariance Sgg - c c^T / var_C, kept as its Cholesky factor; s (used only by the
+// proposal) is the root of a third of its trace.
 // Workgroups of at most kCondBlock threads.
 constexpr int kCondBlock = 256;
 __device__ __forceinline__ void condition_point(const SceneDev& S, float3 x, PointQ& q) {
-    __shared__ float kl[kMaxObs][kCondBlock];
+    __shared__ float4 kl[kMaxObs / 4][kCondBlock];
     const int lt = threadIdx.x;
     const float il2 = 1.0f / (S.lengthscale * S.lengthscale);
     const float var = S.variance;
@@ -382,14 +395,20 @@ __device__ __forceinline__ void condition_point(const SceneDev& S, float3 x, Poi
     const int n = S.n_obs;
     float am = 0.0f;
     float3 amx = f3(0.0f, 0.0f, 0.0f);
-    for (int j = 0; j < n; ++j) {
-        const float4 o = ld_const(S.obs + j);
-        const float3 d = xr - f3(o.x, o.y, o.z);
-        const float kj = var * expf(-0.5f * il2 * dot(d, d));
-        kl[j][lt] = kj;
-        const float ak = o.w * kj;
-        am += ak;
-        amx = amx + ak * f3(o.x, o.y, o.z);
+    for (int g = 0; g < (n + 3) >> 2; ++g) {
+        float kv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * g + e;
+            const float4 o = ld_const(S.obs + j);   // zeros beyond n (the array holds kMaxObs entries)
+            const float3 d = xr - f3(o.x, o.y, o.z);
+            const float kj = j < n ? var * expf(-0.5f * il2 * dot(d, d)) : 0.0f;
+            kv[e] = kj;
+            const float ak = o.w * kj;
+            am += ak;
+            amx = amx + ak * f3(o.x, o.y, o.z);
+        }
+        kl[g][lt] = make_float4(kv[0], kv[1], kv[2], kv[3]);
     }
     const float mu = q.mu + am;
     const float3 gm = q.G - il2 * (am * xr - amx);
@@ -400,16 +419,23 @@ __device__ __forceinline__ void condition_point(const SceneDev& S, float3 x, Poi
     for (int i = 0; i < n; ++i) {
         float w = 0.0f;
         float3 P = f3(0.0f, 0.0f, 0.0f);
-#pragma unroll 4
-        for (int j = 0; j <= i; ++j) {
-            const float4 b = ld_const(row + j);
-            const float kj = kl[j][lt];
-            w = fmaf(b.x, kj, w);
-            P.x = fmaf(b.y, kj, P.x);
-            P.y = fmaf(b.z, kj, P.y);
-            P.z = fmaf(b.w, kj, P.z);
+        const int rb = cond_row_blocks(i);
+        for (int g = 0; g < rb; ++g) {
+            const float4 kv = kl[g][lt];
+            const float4 b0 = ld_const(row + 4 * g), b1 = ld_const(row + 4 * g + 1),
+                         b2 = ld_const(row + 4 * g + 2), b3 = ld_const(row + 4 * g + 3);
+            // entries j = 4g .. 4g + 3 in order (padding adds 0 * k_j exactly)
+            const float4 bs[4] = {b0, b1, b2, b3};
+            const float ks[4] = {kv.x, kv.y, kv.z, kv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                w = fmaf(bs[e].x, ks[e], w);
+                P.x = fmaf(bs[e].y, ks[e], P.x);
+                P.y = fmaf(bs[e].z, ks[e], P.y);
+                P.z = fmaf(bs[e].w, ks[e], P.z);
+            }
         }
-        row += i + 1;
+        row += 4 * rb;
         const float3 W = (-il2) * (w * xr - P);
         ww += w * w;
         c = c + w * W;
