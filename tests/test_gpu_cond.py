@@ -35,11 +35,16 @@ def test_cond_majorants_match_oracle_bitwise(G, which):
     assert np.array_equal(a.view(np.uint32), b.astype(np.float32).view(np.uint32))
 
 
-@pytest.mark.parametrize("which", ["sphere", "blob"])
+@pytest.mark.parametrize("which", ["sphere", "blob", "sphere-1", "sphere-6", "sphere-13", "sphere-31"])
 def test_cond_medium_matches_oracle(G, which):
-    s = _small(which)
+    """Medium evaluation against the oracle; sphere-N conditions on N observations, so that
+    the observation blocks of four end part-filled (N not a multiple of 4)."""
+    if "-" in which:
+        s = sc.cond_sphere_scene(n_obs=int(which.split("-")[1]), width=64, height=64, spp=8)
+    else:
+        s = _small(which)
     rng = np.random.default_rng(11)
-    n = 3000
+    n = 3000 if "-" not in which else 600
     lo, hi = s.bounds[:3].astype(np.float64), s.bounds[3:].astype(np.float64)
     obs = s.observations[:, :3].astype(np.float64)
     pts = np.concatenate([lo + rng.random((n // 2, 3)) * (hi - lo),
