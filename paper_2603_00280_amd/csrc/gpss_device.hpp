@@ -900,6 +900,13 @@ struct Walker {
         }
     }
     __device__ __forceinline__ float majorant(const SceneDev& S) const { return ld_global(S.maj + idx); }
+    // majorant of the cell that step(ax) would enter (of the current cell if it leaves the grid)
+    __device__ __forceinline__ float next_majorant(const SceneDev& S, int ax) const {
+        const int m0 = -(int)(ax == 0), m1 = -(int)(ax == 1), m2 = -(int)(ax == 2);
+        const int left = (nx & m0) | (ny & m1) | (nz & m2);
+        const int n = left > 0 ? idx + ((stx & m0) | (sty & m1) | (stz & m2)) : idx;
+        return ld_global(S.maj + n);
+    }
     // distance along the ray to the exit of the current cell and the axis crossed (ties go
     // to the lower axis)
     __device__ __forceinline__ double exit(int& ax) const {
