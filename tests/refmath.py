@@ -147,3 +147,132 @@ def fresnel_conductor_snell(c, eta, k):
     rs = (c - n * cos_t) / (c + n * cos_t)
     rp = (n * c - cos_t) / (n * c + cos_t)
     return 0.5 * (abs(rs) ** 2 + abs(rp) ** 2)
+
+
+# ---------------------------------------------------------------------------
+# Scene geometry written from definitions (camera, box, signed distances, grids).
+# ---------------------------------------------------------------------------
+def pinhole_direction(eye, target, up, vfov_deg, width, height, x_img, y_img):
+    """Unit direction of the pinhole ray through image position (x_img, y_img) in pixel units
+    (x to the right, y downward from the top-left corner).  The vertical field of view spans
+    the image height; the horizontal extent follows from the aspect ratio width / height.
+    The image plane sits at unit distance along the viewing direction."""
+    eye, target, up = (np.asarray(v, float) for v in (eye, target, up))
+    w = target - eye
+    w /= np.linalg.norm(w)
+    r = np.cross(w, up)
+    r /= np.linalg.norm(r)
+    u = np.cross(r, w)
+    half_h = math.tan(math.radians(vfov_deg) / 2.0)
+    half_w = half_h * width / height
+    # image-plane coordinates in [-half_w, half_w] x [-half_h, half_h], top row at +half_h
+    px = (x_img / width * 2.0 - 1.0) * half_w
+    py = (1.0 - y_img / height * 2.0) * half_h
+    d = w + px * r + py * u
+    return d / np.linalg.norm(d)
+
+
+def box_chord(o, d, lo, hi, n_scan=4096, tmax=20.0):
+    """Entry and exit distances of the ray o + t d through the box [lo, hi], found from the
+    inside indicator: a fine scan for the transitions, then bisection to ~1e-13.  Returns
+    None when the ray misses."""
+    o, d, lo, hi = (np.asarray(v, float) for v in (o, d, lo, hi))
+    inside = lambda t: bool(np.all(o + t * d >= lo) and np.all(o + t * d <= hi))
+    ts = np.linspace(0.0, tmax, n_scan)
+    pts = o[None, :] + ts[:, None] * d[None, :]
+    ins = np.all((pts >= lo) & (pts <= hi), axis=1)
+    if not ins.any():
+        return None
+    k0, k1 = int(np.argmax(ins)), len(ins) - 1 - int(np.argmax(ins[::-1]))
+
+    def bisect(a, b, want_inside_at_b):
+        for _ in range(80):
+            m = 0.5 * (a + b)
+            if inside(m) == want_inside_at_b:
+                b = m
+            else:
+                a = m
+        return 0.5 * (a + b)
+
+    t0 = 0.0 if k0 == 0 else bisect(ts[k0 - 1], ts[k0], True)
+    t1 = bisect(ts[k1 + 1], ts[k1], True) if k1 + 1 < len(ts) else tmax
+    return t0, t1
+
+
+def box_exit_distance(x, w, lo, hi):
+    """Distance from a point x inside the box [lo, hi] to the box boundary along unit w:
+    the smallest positive distance to the three planes the ray heads for."""
+    x, w, lo, hi = (np.asarray(v, float) for v in (x, w, lo, hi))
+    best = np.inf
+    for a in range(3):
+        if w[a] > 0:
+            best = min(best, (hi[a] - x[a]) / w[a])
+        elif w[a] < 0:
+            best = min(best, (lo[a] - x[a]) / w[a])
+    return best
+
+
+def sdf_sphere_ref(x, c, r):
+    v = np.asarray(x, float) - np.asarray(c, float)
+    n = np.linalg.norm(v)
+    return n - r, v / n
+
+
+def sdf_box_ref(x, c, h):
+    """Exact signed distance of an axis-aligned box (centre c, half extents h) by closest
+    points: outside, the distance to the clamped point and the unit vector from it; inside,
+    minus the distance to the nearest face and that face's outward normal.  Also returns the
+    set of outward normals of all nearest faces (ties) for interior points."""
+    x, c, h = (np.asarray(v, float) for v in (x, c, h))
+    lo, hi = c - h, c + h
+    p = np.minimum(np.maximum(x, lo), hi)
+    if np.any(p != x):
+        v = x - p
+        n = np.linalg.norm(v)
+        return n, v / n, [v / n]
+    dist = np.concatenate([x - lo, hi - x])      # distances to the six faces
+    m = dist.min()
+    normals = []
+    for k in np.flatnonzero(dist == m):
+        nrm = np.zeros(3)
+        nrm[k % 3] = -1.0 if k < 3 else 1.0
+        normals.append(nrm)
+    return -m, normals[0], normals
+
+
+def union_sdf_ref(prims, x):
+    """min over primitive rows [kind, cx, cy, cz, a, b, c, albedo] of their exact signed
+    distances: value, gradient of the minimizing primitive, its index (lowest on ties), the
+    valid gradients (ties inside boxes) and its albedo."""
+    best = None
+    for i, p in enumerate(np.asarray(prims, float)):
+        if p[0] == 0:
+            f, g = sdf_sphere_ref(x, p[1:4], p[4])
+            gs = [g]
+        else:
+            f, g, gs = sdf_box_ref(x, p[1:4], p[4:7])
+        if best is None or f < best[0]:
+            best = (f, g, i, gs, p[7])
+    return best
+
+
+def trilinear_ref(grid_zyx, lo, hi, x):
+    """Value and gradient of the trilinear interpolant of a node-centred grid (shape
+    (nz, ny, nx), node k at lo + k / (n - 1) (hi - lo) per axis) at x, from SciPy's
+    RegularGridInterpolator; the gradient along an axis is the difference of the
+    interpolant on the two node planes bounding x, over their spacing (the interpolant is
+    linear along each axis inside a cell)."""
+    from scipy.interpolate import RegularGridInterpolator
+    nz, ny, nx = grid_zyx.shape
+    axes = [np.linspace(lo[2], hi[2], nz), np.linspace(lo[1], hi[1], ny), np.linspace(lo[0], hi[0], nx)]
+    f = RegularGridInterpolator(axes, np.asarray(grid_zyx, float), method="linear")
+    xz = np.array([x[2], x[1], x[0]], float)
+    val = float(f(xz[None, :])[0])
+    grad = np.zeros(3)
+    for a_zyx, a_xyz in ((0, 2), (1, 1), (2, 0)):
+        ax = axes[a_zyx]
+        k = min(max(int(np.searchsorted(ax, xz[a_zyx], side="right")) - 1, 0), len(ax) - 2)
+        p0, p1 = xz.copy(), xz.copy()
+        p0[a_zyx], p1[a_zyx] = ax[k], ax[k + 1]
+        grad[a_xyz] = (float(f(p1[None, :])[0]) - float(f(p0[None, :])[0])) / (ax[k + 1] - ax[k])
+    return val, grad
