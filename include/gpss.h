@@ -138,7 +138,13 @@ int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n);
 /* Forward render (Sec. 5, null-scattering path tracing) of samples [s0, s1) of every
  * pixel into image_dev (device, width*height floats, overwritten with the mean radiance
  * over those samples).  0 <= s0 < s1, and width*height*(s1-s0) < 2^31 paths per call (as for
- * every rendering call; split larger ranges, the chunks reproduce the same paths). */
+ * every rendering call; split larger ranges, the chunks reproduce the same paths).
+ * Each pixel's paths are summed exactly in fixed point (path radiance rounded to a multiple of
+ * 2^-32, values from 2^24 on saturate, invalid ones add 0; see GPSS_CNT_NONFINITE), so the
+ * image does not depend on the order in which paths finish and every kernel form gives the
+ * same image.  The persistent form (default) keeps one 16-byte sum per pixel, allocated by
+ * the scene's first render; the wavefront and one-thread forms also keep every path's
+ * radiance (4 bytes per path of the call). */
 int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1,
                 gpss_stream_t stream);
 
@@ -149,6 +155,9 @@ enum {
     GPSS_CNT_TRACK_STEPS = 0, GPSS_CNT_REAL = 1, GPSS_CNT_NEE_STEPS = 2,
     GPSS_CNT_VIOLATIONS = 3, GPSS_CNT_CAPPED = 4, GPSS_CNT_ESCAPED = 5,
     GPSS_CNT_TRUNCATED = 6, GPSS_CNT_CELLS = 7, GPSS_CNT_PHASE = 8, GPSS_CNT_NEE = 9,
+    /* path radiances that are not a valid estimate: NaN, infinite or negative (an image adds
+     * them as 0), and finite ones of at least 2^24 (an image adds them as 2^24) */
+    GPSS_CNT_NONFINITE = 10, GPSS_CNT_SATURATED = 11,
     GPSS_NCOUNTERS = 16
 };
 int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_dev,
@@ -161,20 +170,26 @@ int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_d
  * grid.  grad_scalars_dev: device, 3 floats, overwritten with d loss / d (kernel variance,
  * lengthscale, albedo); the variance entry is 0 when the scene has a variance grid and the
  * albedo entry when albedo is per primitive.  The estimator is the forward one with every
- * sampling decision frozen at the current parameters; each path is traced, then replayed
- * from its random-number streams (no per-path storage).  Gradients are accumulated with
+ * sampling decision frozen at the current parameters; each path is traced (primal pass), then
+ * replayed from its random-number streams by the same lane, which keeps the path's radiance
+ * and its first light connections' contributions in registers and LDS: nothing is stored
+ * per path in device memory, the call allocates nothing.  Gradients are accumulated with
  * floating-point atomics, so their last bits depend on scheduling. */
 int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float* grad_offset_dev,
                         float* grad_scalars_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream);
 
 /* Render n scenes of uneven size and sample count in one persistent launch, each over its
  * full [0, spp) into images_dev[i] (host array of device pointers, width*height floats
- * each).  Images are identical to gpss_render's.  The work table (tiles of one scene's
- * paths) and a hipGraph of [cursor reset, persistent kernel, reduction] are built on the
- * first call for a given scene list and replayed afterwards; tile size and persistent grid
- * come from the tuning cache written by gpss_batch_autotune (file $GPSS_TUNE_CACHE, else
- * ~/.cache/gpss_batch_tuning.txt), else 4096 paths and 12 waves per CU.  The call returns
- * after the batch has completed on `stream`.  All scenes must live on one device. */
+ * each; the array is read during the call only).  Images are identical to gpss_render's.
+ * The work table (tiles of one scene's paths), a 16-byte fixed-point sum per pixel of the
+ * batch and a hipGraph of [cursor reset, sum clear, persistent kernel, image kernel] are
+ * built on the first call for a given scene list (which allocates and synchronizes) and
+ * replayed afterwards; tile size and persistent grid come from the tuning cache written by
+ * gpss_batch_autotune (file $GPSS_TUNE_CACHE, else ~/.cache/gpss_batch_tuning.txt), else 4096
+ * paths and 12 waves per CU.  Later calls are asynchronous and ordered on `stream`: changed
+ * scene records and image pointers are copied on `stream` from pinned staging, which waits
+ * only when four earlier uploads of this list are still queued.  Calls on one scene list
+ * must not overlap on different streams.  All scenes must live on one device. */
 int gpss_render_batch(const gpss_scene_t* scenes, uint32_t n, float* const* images_dev,
                       gpss_stream_t stream);
 

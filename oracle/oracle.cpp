@@ -1389,15 +1389,18 @@ static int render_impl(const oracle_scene* s_dec, const oracle_scene* s_w, bool 
     return 0;
 }
 
-int oracle_render_pixels(const oracle_scene* s, const int64_t* pixels, int64_t n, int32_t s0, int32_t s1,
-                         double* mean, double* var, int64_t* counters, int32_t nthreads) {
-    if (!s || !pixels || !mean || n < 0 || s1 <= s0 || s0 < 0) return -1;
+static int render_pixels_impl(const oracle_scene* s, const oracle_scene* s_w, bool frozen, const int64_t* pixels,
+                              int64_t n, int32_t s0, int32_t s1, double* mean, double* var, int64_t* counters,
+                              int32_t nthreads) {
+    if (!s || !s_w || !pixels || !mean || n < 0 || s1 <= s0 || s0 < 0) return -1;
+    if (s->W != s_w->W || s->H != s_w->H) return -1;
     const int64_t npix = (int64_t)s->W * s->H;
     for (int64_t i = 0; i < n; ++i)
         if (pixels[i] < 0 || pixels[i] >= npix) return -1;
     const int ns = s1 - s0;
     Counters total;
     const Params<double> P = plain_params(s);
+    const Params<double> Pw = plain_params(s_w);
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel
     {
@@ -1406,7 +1409,7 @@ int oracle_render_pixels(const oracle_scene* s, const int64_t* pixels, int64_t n
         for (int64_t i = 0; i < n; ++i) {
             double sum = 0.0, sq = 0.0, tb = 0.0;
             for (int sidx = s0; sidx < s1; ++sidx) {
-                const double L = trace_path<double>(P, P, false, (uint32_t)pixels[i], (uint32_t)sidx, C, tb);
+                const double L = trace_path<double>(P, Pw, frozen, (uint32_t)pixels[i], (uint32_t)sidx, C, tb);
                 sum += L;
                 sq += L * L;
             }
@@ -1418,6 +1421,16 @@ int oracle_render_pixels(const oracle_scene* s, const int64_t* pixels, int64_t n
     }
     if (counters) for (int i = 0; i < ORC_C_COUNT; ++i) counters[i] = total.c[i];
     return 0;
+}
+
+int oracle_render_pixels(const oracle_scene* s, const int64_t* pixels, int64_t n, int32_t s0, int32_t s1,
+                         double* mean, double* var, int64_t* counters, int32_t nthreads) {
+    return render_pixels_impl(s, s, false, pixels, n, s0, s1, mean, var, counters, nthreads);
+}
+
+int oracle_render_frozen_pixels(const oracle_scene* s_dec, const oracle_scene* s_w, const int64_t* pixels,
+                                int64_t n, int32_t s0, int32_t s1, double* mean, int32_t nthreads) {
+    return render_pixels_impl(s_dec, s_w, true, pixels, n, s0, s1, mean, nullptr, nullptr, nthreads);
 }
 
 int oracle_render(const oracle_scene* s, int32_t s0, int32_t s1, double* mean, double* var,

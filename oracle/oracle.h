@@ -107,6 +107,9 @@ int oracle_render_pixels(const oracle_scene* s, const int64_t* pixels, int64_t n
  * s_w == s_dec it equals oracle_render. */
 int oracle_render_frozen(const oracle_scene* s_dec, const oracle_scene* s_w, int32_t s0,
                          int32_t s1, double* mean, int64_t* counters, int32_t nthreads);
+/* The same for listed pixels only (flat indices): mean of n entries. */
+int oracle_render_frozen_pixels(const oracle_scene* s_dec, const oracle_scene* s_w, const int64_t* pixels,
+                                int64_t n, int32_t s0, int32_t s1, double* mean, int32_t nthreads);
 
 /* Gradient of sum_p dloss[p] * I_p w.r.t. the selected parameters, by forward-mode
  * dual numbers through the frozen-sampling estimator at the scene's parameters.

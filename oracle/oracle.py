@@ -62,6 +62,8 @@ def lib():
                                            C.c_int32, dp, dp, C.POINTER(C.c_int64), C.c_int32]
         L.oracle_render_frozen.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, dp,
                                            C.POINTER(C.c_int64), C.c_int32]
+        L.oracle_render_frozen_pixels.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.c_int64,
+                                                  C.c_int32, C.c_int32, dp, C.c_int32]
         L.oracle_render_grad.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp, C.c_int32,
                                          C.POINTER(C.c_int64), dp, dp, C.c_int32]
         L.oracle_debug_trace.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int32, dp]
@@ -246,6 +248,20 @@ class OracleScene:
                                         nthreads)
         assert rc == 0
         return mean.reshape(s.height, s.width)
+
+    def render_frozen_pixels(self, weights: "OracleScene", pixels, s0: int = 0, s1: Optional[int] = None,
+                             nthreads: int = 0) -> np.ndarray:
+        """Frozen-sampling render (decisions from this scene, weights from `weights`) of the
+        listed pixels (flat indices) over samples [s0, s1)."""
+        s = self.scene
+        s1 = s.spp if s1 is None else s1
+        px = np.ascontiguousarray(np.asarray(pixels, np.int64))
+        mean = np.zeros(px.size)
+        rc = lib().oracle_render_frozen_pixels(self.handle, weights.handle,
+                                               px.ctypes.data_as(C.POINTER(C.c_int64)), px.size, s0, s1,
+                                               _dp(mean), nthreads)
+        assert rc == 0
+        return mean
 
     def render_grad(self, dloss: np.ndarray, param_ids: Sequence[int], s0: int = 0,
                     s1: Optional[int] = None, nthreads: int = 0, want_image: bool = True):

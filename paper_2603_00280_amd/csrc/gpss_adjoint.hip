@@ -11,9 +11,9 @@
 //   light connection      albedo D(w_h) / (4 sigma(d)) * prod (1 - sigma_t / m) * Le
 // (sigma(d) of a real collision cancels against the phase weight and the light
 // connection).  d C_k = C_k sum over its factors of d log(factor), so a factor contributes
-// d log(factor) times the radiance of all contributions that contain it.  Each path's
-// radiance L comes from a forward pass of the scheduled tracer; one thread per path then
-// replays the same random streams while carrying the remaining radiance
+// d log(factor) times the radiance of all contributions that contain it.  Each path is traced
+// twice by the same thread (or lane): a primal pass, the forward tracer's own, gives its
+// radiance L; a replay of the same random streams then carries the remaining radiance
 // L_rem = L - (contributions already passed), and adds
 //   nulls before vertex k:   -sigma_t / (m - sigma_t) d log sigma_t        x L_rem
 //   vertex k:                d log rho + d log albedo                      x L_rem
@@ -21,7 +21,8 @@
 //                            sum over the shadow ray -sigma_t/(m-sigma_t) d log sigma_t  x C_k,light
 //                            d log D(w_m)                                  x (L_rem - C_k)
 // to the gradient, weighted by dloss/dimage of the pixel over the number of samples.
-// Memory is O(pixels): no path is stored.
+// Nothing is stored per path outside the thread: memory is the gradient and the caller's
+// d loss / d image (O(pixels)).
 #include "gpss_internal.hpp"
 #include "gpss_grad.hpp"
 #include "gpss_sched.hpp"
@@ -45,7 +46,7 @@ __device__ void ratio_track_grad(const SceneDev& S, D3 o, D3 d, float3 df, doubl
         const float3 x = sg.pos();
         const PointQ q = eval_point(S, x);
         const float sig = sigma_t_of(q, df);
-        add_dlog_sigma_t(S, x, q, df, -coef * sig / (sg.maj - sig), grad_off, acc);
+        add_dlog_sigma_t(S, sg.o + sg.t * sg.d, q, df, -coef * sig / (sg.maj - sig), grad_off, acc);
         Tr *= null_ratio(sig, sg.maj);
         if (!roulette(Tr, rng)) return;
         sg.redraw(rng);
@@ -58,8 +59,10 @@ struct VertexNee {
     float3 wh[NLIGHT];
 };
 
-// Replay of path (pixel, sample) with radiance L_total; wpix = dloss/dI_pixel / samples.
-__device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, float L_total, float wpix,
+// Replay of path (pixel, sample) with radiance L_total (the sum of its contributions in
+// double, so that the remaining radiance stays accurate after large contributions have been
+// passed); wpix = dloss/dI_pixel / samples.
+__device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, double L_total, float wpix,
                             float* grad_off, GradAcc& acc) {
     PathStats st;
     Rng rng;
@@ -67,7 +70,8 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
     const float ux = rng.uniform(), uy = rng.uniform();
     D3 o, d;
     camera_ray(S, pixel, ux, uy, o, d);
-    float beta = 1.0f, Lrem = L_total;
+    float beta = 1.0f;
+    double Lrem = L_total;
     int b = 0;
     for (;;) {
         double t0, t1;
@@ -91,7 +95,8 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
                 hit = true;
                 break;
             }
-            if (Lrem != 0.0f) add_dlog_sigma_t(S, x, q, df, -wpix * Lrem * sig / (sg.maj - sig), grad_off, acc);
+            if (Lrem != 0.0)
+                add_dlog_sigma_t(S, sg.o + sg.t * sg.d, q, df, -wpix * (float)Lrem * sig / (sg.maj - sig), grad_off, acc);
             sg.redraw(rng);
         }
         if (!hit) break;
@@ -101,7 +106,7 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         const float3 xf = to_f3(x);
         const PointQ q = eval_point(S, xf);
         VertexNee<2> nv;
-        float Etot = 0.0f;
+        double Etot = 0.0;
 #pragma unroll 1
         for (int li = 0; li < 2; ++li) {
             nv.E[li] = 0.0f;
@@ -115,7 +120,7 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
             rn.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
             const float Tr = ratio_track<false>(S, x, wl, inv, wlf, tend, rn, st);
             nv.E[li] = nee_contribution(mul_rn(beta, p), Tr, Le);
-            Etot = add_rn(Etot, nv.E[li]);
+            Etot += (double)nv.E[li];
             if (nv.E[li] != 0.0f) {
                 Rng rn2;
                 rn2.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
@@ -126,7 +131,7 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
                 float ds;
                 if (hn >= 1e-7f && dlog_ndf(q.G, q.s, (1.0f / hn) * h, dG, ds)) {
                     const float c = wpix * nv.E[li];
-                    scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc, true);
+                    scatter_grad(S, x, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc, true);
                 }
             }
         }
@@ -134,8 +139,8 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         {
             float dmu, dsig;
             dlog_rho(q.mu, q.sigma, dmu, dsig);
-            const float c = wpix * Lrem;
-            scatter_grad(S, xf, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, grad_off, acc, true);
+            const float c = wpix * (float)Lrem;
+            scatter_grad(S, x, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, grad_off, acc, true);
             if (!S.albedo_per_prim && S.albedo > 0.0f) acc.alb += c / S.albedo;
         }
         // phase sampling (same draws as the forward pass)
@@ -143,14 +148,14 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         D3 wi;
         float wgt, pdf;
         float3 wm;
-        const bool ok = sample_scatter(S, q, d, df, rng, wi, wgt, wm, pdf);
-        const float Lafter = Lrem - Etot;
-        if (ok && Lafter != 0.0f) {
+        const bool ok = sample_scatter(S, q, scatter_frame(S, q, x, d), d, df, rng, wi, wgt, wm, pdf);
+        const double Lafter = Lrem - Etot;
+        if (ok && Lafter != 0.0) {
             float3 dG;
             float ds;
             if (dlog_ndf(q.G, q.s, wm, dG, ds)) {
-                const float c = wpix * Lafter;
-                scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc, true);
+                const float c = wpix * (float)Lafter;
+                scatter_grad(S, x, q, 0.0f, c * dG, 0.0f, c * ds, grad_off, acc, true);
             }
         }
         if (!ok) break;
@@ -165,12 +170,10 @@ __device__ void replay_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
 #define GPSS_ADJ_MIN_WAVES 4
 #endif
 
-// Replay of every path (pixel p / ns, sample s0 + p % ns) whose radiance paths[p] the
-// forward tracer has just computed.
+// One thread per path (pixel p / ns, sample s0 + p % ns): its primal pass, then its replay.
 static_assert(kSchedBlock == kGradCacheLanes, "the gradient cache has one column per thread of a block");
 
 __global__ __launch_bounds__(256, GPSS_ADJ_MIN_WAVES) void adjoint_kernel(SceneDev S, const float* __restrict__ dloss,
-                                                                         const float* __restrict__ paths,
                                                                          float* __restrict__ grad_off,
                                                                          float* __restrict__ grad_scalars, uint32_t s0,
                                                                          uint32_t ns, uint64_t npaths) {
@@ -180,7 +183,14 @@ __global__ __launch_bounds__(256, GPSS_ADJ_MIN_WAVES) void adjoint_kernel(SceneD
     if (p < npaths) {
         const uint32_t pixel = (uint32_t)(p / ns), sample = s0 + (uint32_t)(p % ns);
         const float wpix = dloss[pixel] / (float)ns;
-        if (wpix != 0.0f) replay_path(S, pixel, sample, paths[p], wpix, grad_off, acc);
+        if (wpix != 0.0f) {
+            PathStats st;
+            st.clear();
+            double Ld = 0.0;
+            const float L = trace_path<false>(S, pixel, sample, st, nullptr, 0, &Ld);
+            // L = 0 (or an invalid estimate) gives no gradient: every contribution is non-negative
+            if (L > 0.0f && L < INFINITY) replay_path(S, pixel, sample, Ld, wpix, grad_off, acc);
+        }
     }
     flush_grad_cell(S, grad_off, acc);
     grad_table_flush(grad_off);
@@ -219,7 +229,8 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_adjoint_kerne
     GradAcc acc{0.0f, 0.0f, 0.0f};
     __shared__ SchedLds<true> lds;
     grad_table_init();
-    run_scheduled<false, true, kMedIso>(S, src, nullptr, st, io, acc, lds);
+    const PathOut out{nullptr, nullptr};
+    run_scheduled<false, true, kMedIso>(S, src, out, st, io, acc, lds);
     flush_grad_cell(S, io.grad_off, acc);
     grad_table_flush(io.grad_off);
     float v[3] = {acc.var, acc.len, acc.alb};
@@ -249,26 +260,23 @@ int launch_adjoint(gpss_scene* s, const float* dloss, float* grad_off, float* gr
     const uint64_t npaths = s->n_pixels() * ns;
     const uint64_t blocks = (npaths + 255) / 256;
     if (blocks > 0x7FFFFFFFull) return set_error(GPSS_ERR_INVALID_ARG, "too many paths in one launch");
-    // primal pass: every path's radiance from the persistent scheduled tracer
-    int rc = ensure_scratch(s, npaths);
-    if (!rc) rc = sched_render(s, s->d_scratch, nullptr, s0, ns, stream);
-    if (rc) return rc;
     float* go = s->d_offset ? grad_off : nullptr;
-    if (s->kernel == GPSS_KERNEL_MEGA) {   // one thread per path replay
-        hipLaunchKernelGGL(adjoint_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, s->dev, dloss,
-                           s->d_scratch, go, grad_scalars, s0, ns, npaths);
+    if (s->kernel == GPSS_KERNEL_MEGA) {   // one thread per path: primal pass and replay
+        hipLaunchKernelGGL(adjoint_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, s->dev, dloss, go,
+                           grad_scalars, s0, ns, npaths);
         return check_hip(hipGetLastError(), "adjoint_kernel launch");
     }
-    // scheduled replay (the path counter was consumed by the primal pass: reset it)
+    // scheduled: each lane traces its path's primal pass, then replays it
+    int rc = ensure_sched(s, stream);
+    if (rc) return rc;
     hipLaunchKernelGGL(adjoint_head_reset_kernel, dim3(1), dim3(64), 0, stream, s->d_head);
     AdjointIo io;
     io.dloss = dloss;
-    io.radiance = s->d_scratch;
     io.grad_off = go;
     io.inv_ns = 1.0f / (float)ns;
     hipLaunchKernelGGL(sched_adjoint_kernel, dim3(s->sched_grid), dim3(kSchedBlock), 0, stream, s->d_dev, io,
                        s->d_head, grad_scalars, s0, ns, (uint32_t)npaths);
-    return check_hip(hipGetLastError(), "adjoint_kernel launch");
+    return check_hip(hipGetLastError(), "sched_adjoint_kernel launch");
 }
 
 }  // namespace gpss

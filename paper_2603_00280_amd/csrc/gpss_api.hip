@@ -92,34 +92,31 @@ int device_cus(int device, int* cus) {
     return GPSS_OK;
 }
 
-// Path counter, device copy of the scene record and grid size of the persistent scheduled
-// kernel: one 256-thread workgroup per compute unit for each wave per SIMD that the kernel's
-// register budget allows.  The record (read through a pointer, which keeps the kernel's
-// scalar registers free) is re-uploaded after every change of `dev`, ordered after the
-// work already queued on `stream`.
+// Device copy of the scene record read by the persistent kernels (through a pointer, which
+// keeps the kernels' scalar registers free): re-uploaded after every change of `dev`, ordered
+// on `stream` after the work already queued there.  The copy goes from a pinned staging
+// record; the staging is rewritten only once its previous copy has completed (an event
+// wait that blocks only when the previous upload is still queued).  The path counter, the
+// record and the staging are allocated with the scene.
 int ensure_sched(gpss_scene* s, hipStream_t stream) {
-    if (!s->d_head) {
-        int rc = check_hip(hipMalloc(&s->d_head, 64), "hipMalloc(path counter)");
-        if (rc) return rc;
-    }
-    if (!s->d_dev) {
-        int rc = check_hip(hipMalloc(&s->d_dev, sizeof(SceneDev)), "hipMalloc(scene record)");
-        if (rc) return rc;
-    }
     if (s->dev_uploaded != s->dev_version) {
-        int rc = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
-        if (!rc) rc = check_hip(hipMemcpy(s->d_dev, &s->dev, sizeof(SceneDev), hipMemcpyHostToDevice),
-                                "hipMemcpy(scene record)");
+        int rc = check_hip(hipEventSynchronize(s->rec_event), "hipEventSynchronize(scene record)");
+        if (rc) return rc;
+        *s->h_rec = s->dev;
+        rc = check_hip(hipMemcpyAsync(s->d_dev, s->h_rec, sizeof(SceneDev), hipMemcpyHostToDevice, stream),
+                       "hipMemcpyAsync(scene record)");
+        if (!rc) rc = check_hip(hipEventRecord(s->rec_event, stream), "hipEventRecord(scene record)");
         if (rc) return rc;
         s->dev_uploaded = s->dev_version;
     }
-    if (!s->sched_grid) {
-        int cus = 0;
-        int rc = device_cus(s->device, &cus);
-        if (rc) return rc;
-        s->sched_grid = (uint32_t)cus * (uint32_t)sched_waves_per_simd();
-    }
     return GPSS_OK;
+}
+
+// Per-pixel fixed-point accumulator of gpss_render (two 64-bit words per pixel), allocated on
+// the scene's first render.
+int ensure_acc(gpss_scene* s) {
+    if (s->d_acc) return GPSS_OK;
+    return check_hip(hipMalloc(&s->d_acc, 2 * s->n_pixels() * sizeof(unsigned long long)), "hipMalloc(accumulator)");
 }
 
 int ensure_scratch(gpss_scene* s, size_t floats) {
@@ -371,6 +368,9 @@ void free_scene(gpss_scene* s) {
     (void)hipFree(s->wf_mem);
     (void)hipFree(s->d_head);
     (void)hipFree(s->d_dev);
+    (void)hipFree(s->d_acc);
+    if (s->h_rec) (void)hipHostFree(s->h_rec);
+    if (s->rec_event) (void)hipEventDestroy(s->rec_event);
     delete s;
 }
 
@@ -432,6 +432,8 @@ void fill_dev(gpss_scene* s) {
         V.off_scale[a] = D.mean_offset || s->d_offset ? (float)((D.off_res[a] - 1) / ext) : 0.0f;
         V.var_res[a] = (int)D.var_res[a];
         V.var_scale[a] = s->d_var ? (float)((D.var_res[a] - 1) / ext) : 0.0f;
+        V.off_scale_d[a] = D.mean_offset || s->d_offset ? (D.off_res[a] - 1) / ext : 0.0;
+        V.var_scale_d[a] = s->d_var ? (D.var_res[a] - 1) / ext : 0.0;
     }
     V.maj = s->d_maj;
     V.R = D.mix_R;
@@ -536,6 +538,20 @@ int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out) {
             rc = check_hip(hipMemcpy(s->maj_h.data(), s->d_maj, nmaj * sizeof(float), hipMemcpyDeviceToHost),
                            "hipMemcpy majorants");
         }
+        // persistent-kernel state: path counter, device record (uploaded here) and its staging
+        if (!rc) rc = check_hip(hipMalloc(&s->d_head, 64), "hipMalloc(path counter)");
+        if (!rc) rc = check_hip(hipMalloc(&s->d_dev, sizeof(gpss::SceneDev)), "hipMalloc(scene record)");
+        if (!rc) rc = check_hip(hipHostMalloc(reinterpret_cast<void**>(&s->h_rec), sizeof(gpss::SceneDev)),
+                                "hipHostMalloc(scene record)");
+        if (!rc) rc = check_hip(hipEventCreateWithFlags(&s->rec_event, hipEventDisableTiming), "hipEventCreate");
+        if (!rc) rc = check_hip(hipMemcpy(s->d_dev, &s->dev, sizeof(gpss::SceneDev), hipMemcpyHostToDevice),
+                                "hipMemcpy(scene record)");
+        if (!rc) {
+            s->dev_uploaded = s->dev_version;
+            int cus = 0;
+            rc = gpss::device_cus(s->device, &cus);
+            s->sched_grid = (uint32_t)cus * (uint32_t)gpss::sched_waves_per_simd();
+        }
         if (rc) {
             free_scene(s);
             return rc;
@@ -592,11 +608,19 @@ int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1, 
     if (int rc = check_path_count(scene, s0, s1)) return rc;
     const uint32_t ns = s1 - s0;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    int rc = gpss::ensure_scratch(scene, (size_t)scene->n_pixels() * ns);
-    if (rc) return rc;
-    rc = gpss::launch_render_paths(scene, scene->d_scratch, nullptr, s0, ns, st);
-    if (rc) return rc;
-    return gpss::launch_reduce(scene, scene->d_scratch, image_dev, ns, st);
+    if (scene->kernel == GPSS_KERNEL_MEGA || scene->kernel == GPSS_KERNEL_WAVEFRONT) {
+        // these forms keep per-path radiances, reduced per pixel afterwards
+        int rc = gpss::ensure_scratch(scene, (size_t)scene->n_pixels() * ns);
+        if (!rc) rc = gpss::launch_render_paths(scene, scene->d_scratch, nullptr, s0, ns, st);
+        if (!rc) rc = gpss::launch_reduce(scene, scene->d_scratch, image_dev, ns, st);
+        return rc;
+    }
+    // persistent form: each path adds to its pixel's fixed-point sum (O(pixels) memory)
+    int rc = gpss::ensure_acc(scene);
+    if (!rc) rc = gpss::launch_acc_clear(scene->d_acc, scene->n_pixels(), st);
+    if (!rc) rc = gpss::sched_render(scene, nullptr, scene->d_acc, nullptr, s0, ns, st);
+    if (!rc) rc = gpss::launch_acc_finalize(scene->d_acc, image_dev, ns, scene->n_pixels(), st);
+    return rc;
 }
 
 int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, float variance, float lengthscale,

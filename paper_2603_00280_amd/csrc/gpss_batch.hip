@@ -1,13 +1,14 @@
 // Batched rendering of many scenes in one persistent launch.
 //
-// A batch plan holds, in device memory, one record per scene (its scene record and the
-// offset of its paths in a shared per-path buffer) and a table of tiles, each a contiguous
-// range of one scene's paths (path p = pixel * spp + sample).  A persistent kernel's waves
-// take tiles from a global cursor (one atomic per tile) and trace each tile's paths with the
-// scheduled loop of the persistent tracer; a second kernel forms every scene's image as the per-pixel mean over its samples,
-// in sample order.  [reset cursor -> persistent kernel -> reduction] is captured once into
-// a hipGraph per plan and replayed on every call.  Path radiances equal those of
-// gpss_render (same per-path routine and random numbers).
+// A batch plan holds, in device memory, one record per scene (a copy of the scene's record
+// and the offset of its pixels in the batch's pixel numbering) and a table of tiles,
+// each a contiguous range of one scene's paths (path p = pixel * spp + sample).  A persistent
+// kernel's waves take tiles from a global cursor (one atomic per tile) and trace each tile's
+// paths with the scheduled loop of the persistent tracer, adding each path's radiance to its
+// pixel's fixed-point accumulator (gpss_accum.hpp); a second kernel turns every scene's sums
+// into its image.  [cursor reset, accumulator clear, persistent kernel, image kernel] is
+// captured once into a hipGraph per plan and replayed on every call.  Images equal
+// gpss_render's (same per-path routine, random numbers and accumulation).
 #include <sys/stat.h>
 
 #include <algorithm>
@@ -25,8 +26,8 @@
 namespace gpss {
 
 struct BatchScene {
-    SceneDev S;
-    uint64_t path_base;    // first slot of this scene in the per-path buffer
+    SceneDev S;            // copy of the scene's record (read through the kernel's const array,
+                           // so that its fields become scalar loads)
     uint64_t pix_base;     // first pixel of this scene in the batch's pixel numbering
     uint32_t spp;
     uint32_t npix;
@@ -43,9 +44,9 @@ __global__ void batch_reset_kernel(uint32_t* cursor) {
 }
 
 // Paths [p0, p0 + count) of one scene's tile, handed to idle lanes in order (the wave owns
-// the tile, so no atomics): pixel p / spp, sample p % spp, slot base + p.
+// the tile, so no atomics): pixel p / spp, sample p % spp.
 struct TileSource {
-    uint64_t next, end, base;
+    uint64_t next, end;
     uint32_t spp;
     __device__ __forceinline__ bool exhausted() const { return next >= end; }
     __device__ __forceinline__ bool take(bool idle, uint32_t& slot, uint32_t& pixel, uint32_t& sample) {
@@ -56,7 +57,7 @@ struct TileSource {
         const uint64_t p = next + rank;
         next += min((uint64_t)__popcll(m), avail);
         if (!got) return false;
-        slot = (uint32_t)(base + p);
+        slot = (uint32_t)p;
         pixel = (uint32_t)(p / spp);
         sample = (uint32_t)(p % spp);
         return true;
@@ -67,7 +68,8 @@ struct TileSource {
 // tile's paths with the scheduled loop; the scene record is wave-uniform.
 __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const BatchScene* __restrict__ scenes,
                                                                          const Tile* __restrict__ tiles, uint32_t ntiles,
-                                                                         uint32_t* cursor, float* __restrict__ paths) {
+                                                                         uint32_t* cursor,
+                                                                         unsigned long long* __restrict__ acc) {
     const uint32_t lane = threadIdx.x & 63;
     PathStats st;
     st.clear();
@@ -79,25 +81,27 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const 
         if (t >= ntiles) break;
         const Tile tl = tiles[t];
         const BatchScene& B = scenes[tl.scene];
+        const SceneDev& S = B.S;
         TileSource src;
         src.next = tl.p0;
         src.end = tl.p0 + tl.count;
-        src.base = B.path_base;
         src.spp = B.spp;
+        const PathOut out{nullptr, acc + 2 * B.pix_base};
         const AdjointIo io{};
-        GradAcc acc{0.0f, 0.0f, 0.0f};
+        GradAcc gacc{0.0f, 0.0f, 0.0f};
         // the same specialization per medium as the single-scene kernel (identical images)
-        const int med = medium_of(B.S);
-        if (med == kMedGgx) run_scheduled<false, false, kMedGgx>(B.S, src, paths, st, io, acc, lds);
-        else if (med == kMedAniso) run_scheduled<false, false, kMedAniso>(B.S, src, paths, st, io, acc, lds);
-        else run_scheduled<false, false, kMedIso>(B.S, src, paths, st, io, acc, lds);
+        const int med = medium_of(S);
+        if (med == kMedGgx) run_scheduled<false, false, kMedGgx>(S, src, out, st, io, gacc, lds);
+        else if (med == kMedAniso) run_scheduled<false, false, kMedAniso>(S, src, out, st, io, gacc, lds);
+        else run_scheduled<false, false, kMedIso>(S, src, out, st, io, gacc, lds);
     }
 }
 
-// One thread per pixel of the batch: image[pixel] = mean of its samples, in sample order.
-__global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchScene* __restrict__ scenes, uint32_t nscenes,
-                                                           float* const* __restrict__ images,
-                                                           const float* __restrict__ paths, uint64_t total_pix) {
+// One thread per pixel of the batch: the scene's image from its fixed-point sums.
+__global__ __launch_bounds__(256) void batch_image_kernel(const BatchScene* __restrict__ scenes, uint32_t nscenes,
+                                                          float* const* __restrict__ images,
+                                                          const unsigned long long* __restrict__ acc,
+                                                          uint64_t total_pix) {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total_pix) return;
     uint32_t lo = 0, hi = nscenes - 1;   // last scene whose pix_base <= g
@@ -107,27 +111,38 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchScene* __r
         else hi = mid - 1;
     }
     const BatchScene& B = scenes[lo];
-    const uint64_t pix = g - B.pix_base;
-    const float* src = paths + B.path_base + pix * B.spp;
-    float acc = 0.0f;
-    for (uint32_t k = 0; k < B.spp; ++k) acc += src[k];
-    images[lo][pix] = acc / (float)B.spp;
+    images[lo][g - B.pix_base] = acc_mean(acc[2 * g], acc[2 * g + 1], B.spp);
+}
+
+__global__ __launch_bounds__(256) void batch_clear_kernel(unsigned long long* __restrict__ acc, uint64_t nwords) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nwords) acc[i] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
 // Plans, graphs and tuning.
 // ---------------------------------------------------------------------------
+// Uploads of scene records and image pointers in flight per plan: each from its own pinned
+// staging slot, reused once that slot's previous copy has completed.
+constexpr int kImageRing = 4;
+
 struct BatchPlan {
     std::vector<gpss_scene*> scenes;
     uint32_t tile = 0, grid = 0;
     BatchScene* d_scenes = nullptr;
-    BatchScene* h_scenes = nullptr;     // pinned staging of the scene records
+    std::vector<uint64_t> versions;     // record version of each scene that d_scenes holds
+    BatchScene* h_scenes[kImageRing] = {};   // pinned staging slots of the record uploads
+    hipEvent_t ev_scenes[kImageRing] = {};
+    int ring_scenes = 0;
     Tile* d_tiles = nullptr;
     uint32_t ntiles = 0;
     uint32_t* d_cursor = nullptr;
-    float** d_images = nullptr;
-    float** h_images = nullptr;         // pinned staging of the image pointers
-    float* d_paths = nullptr;
+    float** d_images = nullptr;         // image pointers read by the graph
+    std::vector<float*> images_set;     // the pointers d_images holds once the queued copies run
+    float** h_images[kImageRing] = {};  // pinned staging slots of those copies
+    hipEvent_t ev_images[kImageRing] = {};
+    int ring = 0;
+    unsigned long long* d_acc = nullptr;   // fixed-point sums, two words per pixel of the batch
     uint64_t total_paths = 0, total_pix = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -142,12 +157,22 @@ void free_plan(BatchPlan* P) {
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     (void)hipFree(P->d_scenes);
-    (void)hipHostFree(P->h_scenes);
     (void)hipFree(P->d_tiles);
     (void)hipFree(P->d_cursor);
     (void)hipFree(P->d_images);
-    (void)hipHostFree(P->h_images);
-    (void)hipFree(P->d_paths);
+    for (int i = 0; i < kImageRing; ++i) {
+        if (P->ev_images[i]) {
+            (void)hipEventSynchronize(P->ev_images[i]);
+            (void)hipEventDestroy(P->ev_images[i]);
+        }
+        if (P->h_images[i]) (void)hipHostFree(P->h_images[i]);
+        if (P->ev_scenes[i]) {
+            (void)hipEventSynchronize(P->ev_scenes[i]);
+            (void)hipEventDestroy(P->ev_scenes[i]);
+        }
+        if (P->h_scenes[i]) (void)hipHostFree(P->h_scenes[i]);
+    }
+    (void)hipFree(P->d_acc);
     delete P;
 }
 
@@ -212,16 +237,14 @@ static int build_plan(gpss_scene* const* scenes, uint32_t n, uint32_t tile, uint
     P->tile = tile;
     P->grid = std::max(1u, (uint32_t)std::max(1, cus) * waves_per_cu / 4u);
     std::vector<Tile> tiles;
+    std::vector<BatchScene> recs(n);
     uint64_t pbase = 0, xbase = 0;
-    if (!rc) rc = check_hip(hipHostMalloc(reinterpret_cast<void**>(&P->h_scenes), n * sizeof(BatchScene)),
-                            "hipHostMalloc");
     for (uint32_t i = 0; i < n && !rc; ++i) {
         const gpss_scene* s = scenes[i];
-        BatchScene& B = P->h_scenes[i];
+        BatchScene& B = recs[i];
         B.S = s->dev;
         B.spp = s->desc.spp;
         B.npix = (uint32_t)s->n_pixels();
-        B.path_base = pbase;
         B.pix_base = xbase;
         const uint64_t np = s->n_pixels() * s->desc.spp;
         for (uint64_t p0 = 0; p0 < np; p0 += tile)
@@ -229,19 +252,33 @@ static int build_plan(gpss_scene* const* scenes, uint32_t n, uint32_t tile, uint
         pbase += np;
         xbase += s->n_pixels();
     }
+    P->versions.resize(n);
+    for (uint32_t i = 0; i < n; ++i) P->versions[i] = scenes[i]->dev_version;
     P->total_paths = pbase;
     P->total_pix = xbase;
     P->ntiles = (uint32_t)tiles.size();
     if (!rc) rc = check_hip(hipMalloc(&P->d_scenes, n * sizeof(BatchScene)), "hipMalloc");
+    if (!rc)
+        rc = check_hip(hipMemcpy(P->d_scenes, recs.data(), n * sizeof(BatchScene), hipMemcpyHostToDevice),
+                       "hipMemcpy batch scenes");
     if (!rc) rc = check_hip(hipMalloc(&P->d_tiles, tiles.size() * sizeof(Tile)), "hipMalloc");
     if (!rc)
         rc = check_hip(hipMemcpy(P->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice),
                        "hipMemcpy tiles");
     if (!rc) rc = check_hip(hipMalloc(&P->d_cursor, 64), "hipMalloc");
     if (!rc) rc = check_hip(hipMalloc(&P->d_images, n * sizeof(float*)), "hipMalloc");
-    if (!rc) rc = check_hip(hipHostMalloc(reinterpret_cast<void**>(&P->h_images), n * sizeof(float*)),
-                            "hipHostMalloc");
-    if (!rc) rc = check_hip(hipMalloc(&P->d_paths, std::max<uint64_t>(1, pbase) * sizeof(float)), "hipMalloc(paths)");
+    for (int i = 0; i < kImageRing && !rc; ++i) {
+        rc = check_hip(hipHostMalloc(reinterpret_cast<void**>(&P->h_images[i]), n * sizeof(float*)), "hipHostMalloc");
+        if (!rc) rc = check_hip(hipEventCreateWithFlags(&P->ev_images[i], hipEventDisableTiming), "hipEventCreate");
+        if (!rc)
+            rc = check_hip(hipHostMalloc(reinterpret_cast<void**>(&P->h_scenes[i]), n * sizeof(BatchScene)),
+                           "hipHostMalloc");
+        if (!rc) rc = check_hip(hipEventCreateWithFlags(&P->ev_scenes[i], hipEventDisableTiming), "hipEventCreate");
+        if (!rc) std::copy(recs.begin(), recs.end(), P->h_scenes[i]);
+    }
+    if (!rc)
+        rc = check_hip(hipMalloc(&P->d_acc, 2 * std::max<uint64_t>(1, xbase) * sizeof(unsigned long long)),
+                       "hipMalloc(batch accumulator)");
     if (rc) {
         free_plan(P);
         return rc;
@@ -250,17 +287,19 @@ static int build_plan(gpss_scene* const* scenes, uint32_t n, uint32_t tile, uint
     return GPSS_OK;
 }
 
-static int capture_graph(BatchPlan* P, hipStream_t stream) {
+static int capture_graph(BatchPlan* P) {
     hipStream_t cs;
     int rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
     if (rc) return rc;
     rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     if (!rc) {
+        const uint64_t nw = 2 * P->total_pix;
         hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, P->d_cursor);
+        hipLaunchKernelGGL(batch_clear_kernel, dim3((uint32_t)((nw + 255) / 256)), dim3(256), 0, cs, P->d_acc, nw);
         hipLaunchKernelGGL(batch_kernel, dim3(P->grid), dim3(256), 0, cs, P->d_scenes, P->d_tiles, P->ntiles,
-                           P->d_cursor, P->d_paths);
-        hipLaunchKernelGGL(batch_reduce_kernel, dim3((uint32_t)((P->total_pix + 255) / 256)), dim3(256), 0, cs,
-                           P->d_scenes, (uint32_t)P->scenes.size(), P->d_images, P->d_paths, P->total_pix);
+                           P->d_cursor, P->d_acc);
+        hipLaunchKernelGGL(batch_image_kernel, dim3((uint32_t)((P->total_pix + 255) / 256)), dim3(256), 0, cs,
+                           P->d_scenes, (uint32_t)P->scenes.size(), P->d_images, P->d_acc, P->total_pix);
         hipGraph_t g = nullptr;
         rc = check_hip(hipStreamEndCapture(cs, &g), "hipStreamEndCapture");
         if (!rc) {
@@ -269,26 +308,46 @@ static int capture_graph(BatchPlan* P, hipStream_t stream) {
         }
     }
     (void)hipStreamDestroy(cs);
-    (void)stream;
     return rc;
 }
 
-// Stage the scene records and image pointers, then launch the plan's graph on `stream`.
+// Upload changed scene records and image pointers, then launch the plan's graph on `stream`.
+// Everything is ordered on `stream`; the call does not wait for the batch.
 static int run_plan(BatchPlan* P, float* const* images, hipStream_t stream) {
     const uint32_t n = (uint32_t)P->scenes.size();
-    for (uint32_t i = 0; i < n; ++i) {
-        P->h_scenes[i].S = P->scenes[i]->dev;
-        P->h_images[i] = images[i];
-    }
-    int rc = check_hip(hipMemcpyAsync(P->d_scenes, P->h_scenes, n * sizeof(BatchScene), hipMemcpyHostToDevice, stream),
+    int rc = GPSS_OK;
+    bool stale = false;   // a scene's parameters changed since its record was copied
+    for (uint32_t i = 0; i < n; ++i) stale |= P->versions[i] != P->scenes[i]->dev_version;
+    if (stale) {
+        const int slot = P->ring_scenes;
+        P->ring_scenes = (P->ring_scenes + 1) % kImageRing;
+        rc = check_hip(hipEventSynchronize(P->ev_scenes[slot]), "hipEventSynchronize(scene records)");
+        if (rc) return rc;
+        for (uint32_t i = 0; i < n; ++i) {
+            P->h_scenes[slot][i].S = P->scenes[i]->dev;
+            P->versions[i] = P->scenes[i]->dev_version;
+        }
+        rc = check_hip(hipMemcpyAsync(P->d_scenes, P->h_scenes[slot], n * sizeof(BatchScene), hipMemcpyHostToDevice,
+                                      stream),
                        "hipMemcpyAsync(batch scenes)");
-    if (!rc)
-        rc = check_hip(hipMemcpyAsync(P->d_images, P->h_images, n * sizeof(float*), hipMemcpyHostToDevice, stream),
+        if (!rc) rc = check_hip(hipEventRecord(P->ev_scenes[slot], stream), "hipEventRecord");
+        if (rc) return rc;
+    }
+    if (P->images_set.size() != n || !std::equal(P->images_set.begin(), P->images_set.end(), images)) {
+        const int slot = P->ring;
+        P->ring = (P->ring + 1) % kImageRing;
+        rc = check_hip(hipEventSynchronize(P->ev_images[slot]), "hipEventSynchronize(image pointers)");
+        if (rc) return rc;
+        std::copy(images, images + n, P->h_images[slot]);
+        rc = check_hip(hipMemcpyAsync(P->d_images, P->h_images[slot], n * sizeof(float*), hipMemcpyHostToDevice,
+                                      stream),
                        "hipMemcpyAsync(batch images)");
-    if (!rc && !P->exec) rc = capture_graph(P, stream);
+        if (!rc) rc = check_hip(hipEventRecord(P->ev_images[slot], stream), "hipEventRecord");
+        if (rc) return rc;
+        P->images_set.assign(images, images + n);
+    }
+    if (!P->exec) rc = capture_graph(P);
     if (!rc) rc = check_hip(hipGraphLaunch(P->exec, stream), "hipGraphLaunch");
-    // the pinned staging buffers are reused by the next call on this plan: wait for the copies
-    if (!rc) rc = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
     return rc;
 }
 

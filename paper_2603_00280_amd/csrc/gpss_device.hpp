@@ -83,6 +83,7 @@ struct SceneDev {
     float cw[3];                  // majorant cell size
     float inv_cw[3];
     double lo_d[3], hi_d[3], cw_d[3], inv_cw_d[3];  // the same box and cells in double
+    double off_scale_d[3], var_scale_d[3];          // the grid scales in double
     int M[3];
     const float* maj;             // majorant grid, x fastest
     float R;
@@ -157,6 +158,17 @@ __device__ __forceinline__ float add_rn(float a, float b) {
 __device__ __forceinline__ float mul_rn(float a, float b) {
 #pragma clang fp contract(off)
     return a * b;
+}
+
+// Running sum kept as an unevaluated pair hi + lo of floats: hi += v with the rounding error
+// of that addition carried in lo (Knuth's two-sum), about 48 significant bits in all.
+__device__ __forceinline__ void ff_add(float& hi, float& lo, float v) {
+#pragma clang fp contract(off)
+    const float s = hi + v;
+    const float bb = s - hi;
+    const float err = (hi - (s - bb)) + (v - bb);
+    hi = s;
+    lo += err;
 }
 
 // Orthonormal basis around unit n (Duff et al., JCGT 2017).
@@ -490,6 +502,29 @@ __device__ __forceinline__ float erfcx_pos(float y) {
     p = fmaf(p, s, -6.717940849e-01f);
     return t * __expf(p);
 }
+// q(y) = 1 - sqrt(pi) y erfcx(y), y >= 0, from its own fit (fit_mills.py): e^{P(2t - 1)} /
+// (1 + 2 y + 2 y^2), t = 1 / (1 + y / 2), about 2.3e-7 relative error in float32.  It is the
+// bracket of the projected area of a ray travelling up the mean gradient and of the density's
+// log-derivative inside the medium; formed from erfcx as 1 - sqrt(pi) y erfcx(y) it cancels to
+// about 1 / (2 y^2) and loses digits in proportion to y^2.
+__device__ __forceinline__ float mills_q(float y) {
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, y, 1.0f));
+    const float s = fmaf(2.0f, t, -1.0f);
+    float p = -1.845568261e-04f;
+    p = fmaf(p, s, -1.230521427e-03f);
+    p = fmaf(p, s, -2.690260467e-03f);
+    p = fmaf(p, s, 7.366559191e-04f);
+    p = fmaf(p, s, 8.175576550e-03f);
+    p = fmaf(p, s, 4.825736499e-03f);
+    p = fmaf(p, s, 7.088512245e-03f);
+    p = fmaf(p, s, 5.314682672e-02f);
+    p = fmaf(p, s, 6.092653941e-02f);
+    p = fmaf(p, s, -1.119519912e-01f);
+    p = fmaf(p, s, -2.806525253e-01f);
+    p = fmaf(p, s, 5.447329695e-02f);
+    p = fmaf(p, s, 2.073366479e-01f);
+    return __expf(p) * __builtin_amdgcn_rcpf(fmaf(2.0f * y, 1.0f + y, 1.0f));
+}
 // Ratio-tracking factor 1 - sigma_t / majorant with a single reciprocal instruction (about
 // one ulp) instead of a correctly rounded division; every tracer form and the adjoint replay
 // use this one function, so their transmittances and roulette decisions stay identical.
@@ -530,7 +565,7 @@ __device__ __forceinline__ float sigma_proj(float3 G, float s, float ak, float3 
     const float z = m * __builtin_amdgcn_rcpf(sd);
     const float az = fabsf(z);
     const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
-    return fmaxf(-m, 0.0f) + sd * ph * (1.0f - az * kSqrtHalfPi * erfcx_pos(az * kInvSqrt2));
+    return fmaxf(-m, 0.0f) + sd * ph * mills_q(az * kInvSqrt2);
 }
 
 // Generalized NDF (Sec. 4.2.2) for g ~ N(G, Sigma): int_0^inf P(t wm) t^3 dt in closed form.
@@ -608,7 +643,7 @@ __device__ __forceinline__ float sigma_proj_chol(float3 G, const float* L, float
     const float z = m * __builtin_amdgcn_rcpf(sd);
     const float az = fabsf(z);
     const float ph = kInvSqrt2Pi * expf(-0.5f * z * z);
-    return fmaxf(-m, 0.0f) + sd * ph * (1.0f - az * kSqrtHalfPi * erfcx_pos(az * kInvSqrt2));
+    return fmaxf(-m, 0.0f) + sd * ph * mills_q(az * kInvSqrt2);
 }
 __device__ __forceinline__ float3 chol_solve3(const float* L, float3 b) {
     const float y0 = b.x / L[0];
@@ -685,36 +720,6 @@ struct Proposal {
     bool ggx;
 };
 
-__device__ __forceinline__ Proposal make_proposal(const PointQ& q, float R, float3 v) {
-    Proposal p;
-    p.beck = false;
-    p.ggx = q.ggx != 0;
-    p.Reff = 0.0f;
-    const float g2 = dot(q.G, q.G);
-    if (g2 > 0.0f) {
-        const float gn = sqrtf(g2);
-        p.N = (1.0f / gn) * q.G;
-        p.cosv = dot(v, p.N);
-        if (p.cosv > 0.0f) {
-            p.beck = true;
-            p.Reff = R;
-            p.alpha = kSqrt2 * q.s / gn;
-            const float3 vt = v - p.cosv * p.N;
-            const float st = sqrtf(dot(vt, vt));
-            if (st > 1e-7f) {
-                p.T = (1.0f / st) * vt;
-                p.a = p.cosv / (p.alpha * st);
-            } else {
-                float3 b;
-                onb(p.N, p.T, b);
-                p.a = INFINITY;
-            }
-            p.B = cross(p.N, p.T);
-        }
-    }
-    return p;
-}
-
 __device__ __forceinline__ float beckmann_lambda(float a) {
     if (isinf(a)) return 0.0f;
     return 0.5f * (expf(-a * a) * kInvSqrtPi / a - erfcf(a));
@@ -784,49 +789,271 @@ __device__ __forceinline__ float sample_slope_x(float a, float u) {
     return x;
 }
 
-__device__ __forceinline__ float3 sample_half_vector(const Proposal& p, float3 v, float usel, uint32_t ua24,
-                                                     uint32_t ub24) {
+// The random-variate part of the half-vector proposal, in single precision: which component
+// (kind) and its coordinates c[0..2]: Beckmann visible slopes (x, y); GGX: (a1, a2, a3), the
+// point on the unit hemisphere of the stretched configuration; uniform hemisphere: (cos theta,
+// cos phi, sin phi).  combine_half_d maps them through the proposal's frame (in double).
+enum { kHalfUniform = 0, kHalfBeckmann = 1, kHalfGgx = 2 };
+struct HalfDraw {
+    int kind;
+    float c[3];
+};
+__device__ __forceinline__ HalfDraw draw_half(const Proposal& p, float usel, uint32_t ua24, uint32_t ub24) {
     const float ua = (float)ua24 * 0x1p-24f, ub = (float)ub24 * 0x1p-24f;
+    HalfDraw h;
     if (usel < p.Reff && p.ggx) {
-        // GGX visible normals (Heitz 2018): stretch v to unit roughness, sample the projected
-        // hemisphere as a disk whose far half is foreshortened, lift and unstretch.
-        const float vx = dot(v, p.T), vy = dot(v, p.B);
-        float3 h = f3(p.alpha * vx, p.alpha * vy, p.cosv);
-        h = normalize(h);
-        const float l2 = h.x * h.x + h.y * h.y;
-        float3 t1 = f3(1.0f, 0.0f, 0.0f);
-        if (l2 > 0.0f) {
-            const float il = rsqrtf(l2);
-            t1 = f3(-h.y * il, h.x * il, 0.0f);
-        }
-        const float3 t2 = cross(h, t1);
+        // GGX visible normals (Heitz 2018): the projected hemisphere of the stretched view as a
+        // disk whose far half is foreshortened; (a1, a2) on the disk, a3 lifts it (h.z of the
+        // stretched view direction enters a2)
+        const float hz = p.cosv / sqrtf(p.alpha * p.alpha * (1.0f - p.cosv * p.cosv) + p.cosv * p.cosv);
         const float r = sqrtf(ua);
         float sp, cp;
         sincosf(2.0f * kPi * ub, &sp, &cp);
         const float a1 = r * cp;
-        const float sh = 0.5f * (1.0f + h.z);
+        const float sh = 0.5f * (1.0f + hz);
         const float a2 = (1.0f - sh) * sqrtf(fmaxf(0.0f, 1.0f - a1 * a1)) + sh * (r * sp);
-        const float a3 = sqrtf(fmaxf(0.0f, 1.0f - a1 * a1 - a2 * a2));
-        const float3 m = a1 * t1 + a2 * t2 + a3 * h;
-        const float3 e = normalize(f3(p.alpha * m.x, p.alpha * m.y, fmaxf(0.0f, m.z)));
-        return e.x * p.T + e.y * p.B + e.z * p.N;
-    }
-    if (usel < p.Reff) {
-        const float xs = sample_slope_x(p.a, ua);
+        h.kind = kHalfGgx;
+        h.c[0] = a1;
+        h.c[1] = a2;
+        h.c[2] = sqrtf(fmaxf(0.0f, 1.0f - a1 * a1 - a2 * a2));
+    } else if (usel < p.Reff) {
+        h.kind = kHalfBeckmann;
+        h.c[0] = sample_slope_x(p.a, ua);
         // (2 k + 1) / 2^24 - 1, exact in float
-        const float ys = erfinvf((float)((int)(2u * ub24 + 1u) - (1 << 24)) * 0x1p-24f);
-        const float x = p.alpha * xs, y = p.alpha * ys;
-        const float in = 1.0f / sqrtf(x * x + y * y + 1.0f);
-        return f3((-x * p.T.x - y * p.B.x + p.N.x) * in, (-x * p.T.y - y * p.B.y + p.N.y) * in,
-                  (-x * p.T.z - y * p.B.z + p.N.z) * in);
+        h.c[1] = erfinvf((float)((int)(2u * ub24 + 1u) - (1 << 24)) * 0x1p-24f);
+        h.c[2] = 0.0f;
+    } else {
+        float sp, cp;
+        sincosf(2.0f * kPi * ub, &sp, &cp);
+        h.kind = kHalfUniform;
+        h.c[0] = 1.0f - ua;
+        h.c[1] = cp;
+        h.c[2] = sp;
     }
-    float3 t, b;
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// The sampled half vector in double precision.
+//
+// A real collision's half vector sets the direction of the next segment. Formed in single
+// precision (errors of about 1e-7 from the frame at the rounded position and from the final
+// combination), that direction moves later cell crossings and collision points enough to
+// change the discrete outcome of a later test (a short cell chord, a real/null choice) on a
+// few paths in ten thousand; on deep scenes with many samples per pixel that reached more
+// than a pixel in a thousand. The frame of the proposal (mean gradient and spread at the
+// vertex) and the combination of the drawn coordinates with it therefore run in double; the
+// inverse-CDF transforms stay in single precision (their relative error of about 1e-7 in the
+// coordinates moved few decisions). It is once per real collision.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ D3 cross(D3 a, D3 b) {
+    return d3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+// 1 / sqrt(x) and 1 / x for x > 0 in double: the hardware estimate refined by two Newton steps
+// (to about one unit in the last place; the frame needs nothing closer, and these use far
+// fewer registers than the correctly rounded sequences)
+__device__ __forceinline__ double rsqrt_d(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    r = r * (1.5 - hx * r * r);
+    r = r * (1.5 - hx * r * r);
+    return r;
+}
+__device__ __forceinline__ double rcp_d(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * (2.0 - x * r);
+    r = r * (2.0 - x * r);
+    return r;
+}
+__device__ __forceinline__ D3 unit_d(D3 a) { return rsqrt_d(dot(a, a)) * a; }
+// Orthonormal basis around unit n (Duff et al., JCGT 2017), double precision.
+__device__ __forceinline__ void onb(D3 n, D3& t, D3& b) {
+    const double sign = copysign(1.0, n.z);
+    const double a = -rcp_d(sign + n.z);
+    const double bb = n.x * n.y * a;
+    t = d3(1.0 + sign * n.x * n.x * a, sign * bb, -sign * n.x);
+    b = d3(bb, sign + n.y * n.y * a, -n.y);
+}
+
+__device__ __forceinline__ double sdf_prim_dd(float4 a, float4 b, D3 x, D3& g) {
+    const D3 v = d3(x.x - (double)a.y, x.y - (double)a.z, x.z - (double)a.w);
+    if (a.x < 0.5f) {
+        const double r2 = dot(v, v);
+        const double ir = r2 > 0.0 ? rsqrt_d(r2) : 0.0;
+        g = r2 > 0.0 ? ir * v : d3(0.0, 0.0, 1.0);
+        return r2 * ir - (double)b.x;
+    }
+    const double sx = v.x < 0.0 ? -1.0 : 1.0, sy = v.y < 0.0 ? -1.0 : 1.0, sz = v.z < 0.0 ? -1.0 : 1.0;
+    const double qx = fabs(v.x) - (double)b.x, qy = fabs(v.y) - (double)b.y, qz = fabs(v.z) - (double)b.z;
+    const double qmax = fmax(qx, fmax(qy, qz));
+    if (qmax > 0.0) {
+        const double px = fmax(qx, 0.0), py = fmax(qy, 0.0), pz = fmax(qz, 0.0);
+        const double n2 = px * px + py * py + pz * pz;
+        const double in = rsqrt_d(n2);
+        g = in * d3(sx * px, sy * py, sz * pz);
+        return n2 * in;
+    }
+    int ax = 0;
+    if (qy > qx) ax = 1;
+    if (qz > fmax(qx, qy)) ax = 2;
+    g = d3(ax == 0 ? sx : 0.0, ax == 1 ? sy : 0.0, ax == 2 ? sz : 0.0);
+    return qmax;
+}
+
+// Trilinear value and gradient of a node-centred grid, double arithmetic on the float nodes.
+__device__ __forceinline__ double tri_eval_d(const float* __restrict__ g, const int res[3], const double sc[3],
+                                             const SceneDev& S, D3 x, D3* grad) {
+    int i[3];
+    double f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double u = fmin(fmax((comp(x, a) - S.lo_d[a]) * sc[a], 0.0), (double)(res[a] - 1));
+        i[a] = min((int)floor(u), res[a] - 2);
+        f[a] = u - (double)i[a];
+    }
+    const int base = (i[2] * res[1] + i[1]) * res[0] + i[0];
+    const int sx = 1, sy = res[0], sz = res[0] * res[1];
+    const double v000 = ld_global(g + base), v100 = ld_global(g + base + sx), v010 = ld_global(g + base + sy),
+                 v110 = ld_global(g + base + sx + sy), v001 = ld_global(g + base + sz),
+                 v101 = ld_global(g + base + sx + sz), v011 = ld_global(g + base + sy + sz),
+                 v111 = ld_global(g + base + sx + sy + sz);
+    const double fx = f[0], fy = f[1], fz = f[2], gx = 1.0 - fx, gy = 1.0 - fy, gz = 1.0 - fz;
+    const double x00 = gx * v000 + fx * v100, x10 = gx * v010 + fx * v110;
+    const double x01 = gx * v001 + fx * v101, x11 = gx * v011 + fx * v111;
+    const double y0 = gy * x00 + fy * x10, y1 = gy * x01 + fy * x11;
+    if (grad) {
+        const double dx = gy * gz * (v100 - v000) + fy * gz * (v110 - v010) + gy * fz * (v101 - v001) +
+                          fy * fz * (v111 - v011);
+        *grad = d3(dx * sc[0], (gz * (x10 - x00) + fz * (x11 - x01)) * sc[1], (y1 - y0) * sc[2]);
+    }
+    return gz * y0 + fz * y1;
+}
+
+// Mean gradient and gradient spread s = sigma / l at x, in double (the frame of the proposal).
+struct GeomD {
+    D3 G;
+    double s;
+};
+__device__ __forceinline__ GeomD eval_geom_d(const SceneDev& S, D3 x) {
+    GeomD q;
+    if (S.mean_kind == 0) {
+        q.G = d3(0.0, 0.0, 1.0);
+    } else if (S.mean_kind == 2) {
+        q.G = d3(0.0, 0.0, 0.0);
+    } else {
+        double best = INFINITY;
+        q.G = d3(0.0, 0.0, 1.0);
+        for (int i = 0; i < S.n_prims; ++i) {
+            D3 gi;
+            const double fi = sdf_prim_dd(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
+            if (fi < best) { best = fi; q.G = gi; }
+        }
+    }
+    if (S.offset) {
+        D3 go;
+        tri_eval_d(S.offset, S.off_res, S.off_scale_d, S, x, &go);
+        q.G = q.G + go;
+    }
+    const double var = S.var_grid ? tri_eval_d(S.var_grid, S.var_res, S.var_scale_d, S, x, nullptr)
+                                  : (double)S.variance;
+    q.s = var * rsqrt_d(var) * rcp_d((double)S.lengthscale);
+    return q;
+}
+
+// The proposal's frame in double: normal N = G / |G| and, when v is above the local horizon,
+// the incidence-plane tangent T and B = N x T, the roughness and cos(theta_v).
+struct FrameD {
+    D3 N, T, B;
+    double alpha, cosv, a;   // a = cot(theta_v) after stretching to unit roughness
+    bool beck;
+};
+__device__ __forceinline__ FrameD make_frame_d(const GeomD& q, D3 v) {
+    FrameD f;
+    f.beck = false;
+    f.N = f.T = f.B = d3(0.0, 0.0, 0.0);
+    f.alpha = f.cosv = f.a = 0.0;
+    const double g2 = dot(q.G, q.G);
+    if (g2 > 0.0) {
+        const double ign = rsqrt_d(g2);
+        f.N = ign * q.G;
+        f.cosv = dot(v, f.N);
+        if (f.cosv > 0.0) {
+            f.beck = true;
+            f.alpha = 1.41421356237309504880 * q.s * ign;
+            const D3 vt = v - f.cosv * f.N;
+            const double st2 = dot(vt, vt);
+            if (st2 > 1e-14) {
+                const double ist = rsqrt_d(st2);
+                f.T = ist * vt;
+                f.a = f.cosv * ist * rcp_d(f.alpha);
+            } else {
+                D3 b;
+                onb(f.N, f.T, b);
+                f.a = INFINITY;
+            }
+            f.B = cross(f.N, f.T);
+        }
+    }
+    return f;
+}
+
+// The single-precision proposal of a double frame: the draws and the mixture pdf use it, so
+// that the choice of component (v above the local horizon) is the double frame's.
+__device__ __forceinline__ Proposal proposal_of(const FrameD& f, float R, int ggx) {
+    Proposal p;
+    p.N = to_f3(f.N);
+    p.T = to_f3(f.T);
+    p.B = to_f3(f.B);
+    p.alpha = (float)f.alpha;
+    p.cosv = (float)f.cosv;
+    p.a = (float)f.a;
+    p.beck = f.beck;
+    p.Reff = f.beck ? R : 0.0f;
+    p.ggx = ggx != 0;
+    return p;
+}
+
+// The half vector from the drawn coordinates (draw_half with proposal_of(f)) and the frame f,
+// in double: visible slopes or the stretched GGX hemisphere point mapped through the frame,
+// or the uniform hemisphere about v.  Only N, alpha and cos(theta_v) of f are read (the
+// tangents are formed again here, so that less of the frame stays live across the draws).
+__device__ __forceinline__ D3 combine_half_d(const HalfDraw& h, FrameD f, D3 v) {
+    if (h.kind != kHalfUniform) {
+        const D3 vt = v - f.cosv * f.N;
+        const double st2 = dot(vt, vt);
+        if (st2 > 1e-14) {
+            f.T = rsqrt_d(st2) * vt;
+        } else {
+            D3 b;
+            onb(f.N, f.T, b);
+        }
+        f.B = cross(f.N, f.T);
+    }
+    if (h.kind == kHalfGgx) {
+        // stretched configuration: local frame of the stretched view direction hs
+        const double vx = dot(v, f.T), vy = dot(v, f.B);
+        const D3 hs = unit_d(d3(f.alpha * vx, f.alpha * vy, f.cosv));
+        const double l2 = hs.x * hs.x + hs.y * hs.y;
+        D3 t1 = d3(1.0, 0.0, 0.0);
+        if (l2 > 0.0) {
+            const double il = rsqrt_d(l2);
+            t1 = d3(-hs.y * il, hs.x * il, 0.0);
+        }
+        const D3 t2 = cross(hs, t1);
+        const D3 m = (double)h.c[0] * t1 + (double)h.c[1] * t2 + (double)h.c[2] * hs;
+        const D3 e = unit_d(d3(f.alpha * m.x, f.alpha * m.y, fmax(0.0, m.z)));
+        return e.x * f.T + e.y * f.B + e.z * f.N;
+    }
+    if (h.kind == kHalfBeckmann) {
+        const double x = f.alpha * (double)h.c[0], y = f.alpha * (double)h.c[1];
+        return rsqrt_d(x * x + y * y + 1.0) * (f.N - x * f.T - y * f.B);
+    }
+    D3 t, b;
     onb(v, t, b);
-    const float ct = 1.0f - ua;
-    const float st = sqrtf(ua * (2.0f - ua));
-    float sp, cp;
-    sincosf(2.0f * kPi * ub, &sp, &cp);
-    return (st * cp) * t + (st * sp) * b + ct * v;
+    const double ct = (double)h.c[0];                  // 1 - u_a, exact
+    const double st2 = (1.0 - ct) * (1.0 + ct);        // u_a (2 - u_a), exact
+    const double st = st2 > 0.0 ? st2 * rsqrt_d(st2) : 0.0;
+    return (st * (double)h.c[1]) * t + (st * (double)h.c[2]) * b + ct * v;
 }
 
 // ---------------------------------------------------------------------------
@@ -936,8 +1163,10 @@ struct Walker {
 // Per-thread event counts (kept in registers, flushed once per path when requested).
 struct PathStats {
     uint32_t track_steps, real, nee_steps, violations, capped, escaped, truncated, cells, phase, nee;
+    uint32_t nonfinite, saturated;   // path radiances not finite or negative (added as 0) / at least 2^24
     __device__ __forceinline__ void clear() {
         track_steps = real = nee_steps = violations = capped = escaped = truncated = cells = phase = nee = 0;
+        nonfinite = saturated = 0;
     }
 };
 

@@ -1,5 +1,6 @@
-// Forward kernels: majorant-grid construction, one-thread-per-path rendering, the ordered
-// per-pixel reduction and pointwise medium evaluation.
+// Forward kernels: majorant-grid construction, one-thread-per-path rendering, the per-pixel
+// reduction and fixed-point accumulator kernels, and pointwise medium evaluation.
+#include "gpss_accum.hpp"
 #include "gpss_internal.hpp"
 #include "gpss_trace.hpp"
 
@@ -339,11 +340,11 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 __device__ __forceinline__ void flush_stats(const PathStats& st, unsigned long long* counters) {
-    const uint32_t vals[10] = {st.track_steps, st.real, st.nee_steps, st.violations, st.capped,
-                               st.escaped, st.truncated, st.cells, st.phase, st.nee};
+    const uint32_t vals[12] = {st.track_steps, st.real, st.nee_steps, st.violations, st.capped,
+                               st.escaped, st.truncated, st.cells, st.phase, st.nee, st.nonfinite, st.saturated};
     const bool lead = (threadIdx.x & 63) == 0;
 #pragma unroll
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < 12; ++i) {
         const uint32_t t = wave_sum(vals[i]);
         if (lead && t) atomicAdd(&counters[i], (unsigned long long)t);
     }
@@ -364,7 +365,13 @@ __global__ __launch_bounds__(256, GPSS_MEGA_MIN_WAVES) void render_paths_kernel(
     if (p < npaths) {
         const uint32_t pixel = (uint32_t)(p / ns);
         const uint32_t sample = s0 + (uint32_t)(p % ns);
-        paths[p] = trace_path<STATS>(S, pixel, sample, st);
+        const float L = trace_path<STATS>(S, pixel, sample, st);
+        if (STATS) {
+            const int c = acc_class(L);
+            st.nonfinite += c == kAccNonFinite;
+            st.saturated += c == kAccSaturated;
+        }
+        paths[p] = L;
     }
     if (STATS) flush_stats(st, counters);
 }
@@ -409,18 +416,23 @@ int launch_render_paths(gpss_scene* s, float* paths, uint64_t* counters, uint32_
         return set_error(GPSS_ERR_UNSUPPORTED, "a conditioned GP renders with the persistent kernel only");
     if (s->kernel == GPSS_KERNEL_MEGA) return mega_render(s, paths, counters, s0, ns, stream);
     if (s->kernel == GPSS_KERNEL_WAVEFRONT) return wf_render(s, paths, counters, s0, ns, stream);
-    return sched_render(s, paths, counters, s0, ns, stream);
+    return sched_render(s, paths, nullptr, counters, s0, ns, stream);
 }
 
-// Per-pixel mean over the sample range, summed in sample order (deterministic).
+// Per-pixel mean over the sample range from per-path radiances: the same fixed-point sums as
+// the accumulating kernels (gpss_accum.hpp), hence the same image.
 __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ paths, float* __restrict__ image,
                                                      uint32_t ns, uint64_t npix) {
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
     const float* src = paths + p * ns;
-    float acc = 0.0f;
-    for (uint32_t k = 0; k < ns; ++k) acc += src[k];
-    image[p] = acc / (float)ns;
+    unsigned long long lo = 0, hi = 0;
+    for (uint32_t k = 0; k < ns; ++k) {
+        const uint64_t v = acc_fixed(src[k]);
+        lo += v & 0xFFFFFFFFull;
+        hi += v >> 32;
+    }
+    image[p] = acc_mean(lo, hi, ns);
 }
 
 int launch_reduce(gpss_scene* s, const float* paths, float* image, uint32_t ns, hipStream_t stream) {
@@ -428,6 +440,33 @@ int launch_reduce(gpss_scene* s, const float* paths, float* image, uint32_t ns, 
     hipLaunchKernelGGL(reduce_kernel, dim3((uint32_t)((npix + 255) / 256)), dim3(256), 0, stream, paths, image,
                        ns, npix);
     return check_hip(hipGetLastError(), "reduce_kernel launch");
+}
+
+// Fixed-point accumulator of npix pixels (two words each): cleared before a launch adds to it,
+// turned into the image after.  Kernels rather than memsets, so that they may be captured.
+__global__ __launch_bounds__(256) void acc_clear_kernel(unsigned long long* __restrict__ acc, uint64_t nwords) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nwords) acc[i] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void acc_finalize_kernel(const unsigned long long* __restrict__ acc,
+                                                           float* __restrict__ image, uint32_t ns, uint64_t npix) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    image[p] = acc_mean(acc[2 * p], acc[2 * p + 1], ns);
+}
+
+int launch_acc_clear(unsigned long long* acc, uint64_t npix, hipStream_t stream) {
+    const uint64_t nw = 2 * npix;
+    hipLaunchKernelGGL(acc_clear_kernel, dim3((uint32_t)((nw + 255) / 256)), dim3(256), 0, stream, acc, nw);
+    return check_hip(hipGetLastError(), "acc_clear_kernel launch");
+}
+
+int launch_acc_finalize(const unsigned long long* acc, float* image, uint32_t ns, uint64_t npix,
+                        hipStream_t stream) {
+    hipLaunchKernelGGL(acc_finalize_kernel, dim3((uint32_t)((npix + 255) / 256)), dim3(256), 0, stream, acc, image,
+                       ns, npix);
+    return check_hip(hipGetLastError(), "acc_finalize_kernel launch");
 }
 
 // ---------------------------------------------------------------------------

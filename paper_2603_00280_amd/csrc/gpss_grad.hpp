@@ -124,13 +124,22 @@ __device__ __forceinline__ void flush_grad_cell(const SceneDev& S, float* __rest
 // d log rho = dmu * dmu_coef + dsigma * dsig_coef,  rho = phi(z)/(sigma Phi(z)), z = mu/sigma:
 //   d log rho / d mu = -(z + r) / sigma,  d log rho / d sigma = (z^2 - 1 + z r) / sigma,
 // with r = phi(z)/Phi(z) = sqrt(2/pi) / erfcx(-z/sqrt2) taken from the same fitted erfcx
-// and reciprocals as the density itself (rho_of).
+// and reciprocals as the density itself (rho_of), and z + r from the fitted bracket mills_q
+// where the two cancel (z < 0).
 __device__ __forceinline__ void dlog_rho(float mu, float sigma, float& dmu, float& dsig) {
     const float is = __builtin_amdgcn_rcpf(sigma);
     const float z = mu * is;
-    const float r = kSqrt2OverPi * __builtin_amdgcn_rcpf(erfcx_any(-z * kInvSqrt2));
-    dmu = -(z + r) * is;
-    dsig = (z * z - 1.0f + z * r) * is;
+    // z + r with r = phi(z) / Phi(z); inside the medium (z < 0) the two cancel to about 1 / |z|,
+    // so the sum is formed as sqrt(2/pi) q(|z| / sqrt2) / erfcx(|z| / sqrt2) (mills_q)
+    float zr;
+    if (z < 0.0f) {
+        const float y = -z * kInvSqrt2;
+        zr = kSqrt2OverPi * mills_q(y) * __builtin_amdgcn_rcpf(erfcx_pos(y));
+    } else {
+        zr = z + kSqrt2OverPi * __builtin_amdgcn_rcpf(erfcx_any(-z * kInvSqrt2));
+    }
+    dmu = -zr * is;
+    dsig = fmaf(z, zr, -1.0f) * is;
 }
 
 // d log sigma_proj: sigma_proj = s phi(z) - m Phi(-z), m = d . G, z = m / s;
@@ -144,7 +153,7 @@ __device__ __forceinline__ void dlog_proj(float3 G, float s, float3 d, float3& d
     const float z = m * __builtin_amdgcn_rcpf(s);
     const float az = fabsf(z);
     const float R = kSqrtHalfPi * erfcx_pos(az * kInvSqrt2);
-    const float q = fmaxf(1.0f - az * R, 1e-30f);
+    const float q = fmaxf(mills_q(az * kInvSqrt2), 1e-30f);   // 1 - az R without its cancellation
     float a, b;
     if (z > 0.0f) {
         b = __builtin_amdgcn_rcpf(s * q);
@@ -163,35 +172,63 @@ __device__ __forceinline__ void dlog_proj(float3 G, float s, float3 d, float3& d
 //   d log D / dG = (w s M4/M3 - G) / s^2,
 //   d log D / ds = (M5/M3 - 2 k M4/M3 + |G|^2/s^2 - 3) / s.
 // M_n by the recurrence M_n = k M_{n-1} + (n-1) M_{n-2}; scaled by exp(k^2/2) for k < 0.
-__device__ __forceinline__ bool dlog_ndf(float3 G, float s, float3 w, float3& dG, float& ds) {
-    const float is = 1.0f / s;
-    const float k = dot(G, w) * is;
-    float m0, m1;
-    if (k >= 0.0f) {
-        m0 = kSqrt2Pi * (1.0f - 0.5f * erfcf(k * kInvSqrt2));
-        m1 = expf(-0.5f * k * k) + k * m0;
+__device__ __noinline__ bool dlog_ndf(float3 G, float s, float3 w, float3& dG, float& ds) {
+    // in double: for k < 0 each step of the moments' recursion cancels (m1 to about 1/k^2, m3
+    // to about 1/|k|^4, ...), which in single precision left relative errors of 1e-5 at k = -3
+    // and 2e-3 at k = -5 in r4 and r5; once per vertex and light connection
+    const double sd = (double)s, is = 1.0 / sd;
+    const double Gx = G.x, Gy = G.y, Gz = G.z, wx = w.x, wy = w.y, wz = w.z;
+    const double k = (Gx * wx + Gy * wy + Gz * wz) * is;
+    constexpr double kS2Pi = 2.50662827463100050242, kSHalfPi = 1.25331413731550025121,
+                     kIS2 = 0.70710678118654752440;
+    double m0, m1;
+    if (k >= 0.0) {
+        m0 = kS2Pi * (1.0 - 0.5 * erfc(k * kIS2));
+        m1 = exp(-0.5 * k * k) + k * m0;
     } else {
-        m0 = kSqrtHalfPi * erfcxf(-k * kInvSqrt2);
-        m1 = 1.0f + k * m0;
+        m0 = kSHalfPi * erfcx(-k * kIS2);
+        m1 = 1.0 + k * m0;
     }
-    const float m2 = k * m1 + m0;
-    const float m3 = k * m2 + 2.0f * m1;
-    const float m4 = k * m3 + 3.0f * m2;
-    const float m5 = k * m4 + 4.0f * m3;
-    if (!(m3 > 0.0f)) return false;
-    const float r4 = m4 / m3, r5 = m5 / m3;
-    dG = (is * is) * ((s * r4) * w - G);
-    ds = (r5 - 2.0f * k * r4 + dot(G, G) * is * is - 3.0f) * is;
+    const double m2 = k * m1 + m0;
+    const double m3 = k * m2 + 2.0 * m1;
+    const double m4 = k * m3 + 3.0 * m2;
+    const double m5 = k * m4 + 4.0 * m3;
+    if (!(m3 > 0.0)) return false;
+    const double r4 = m4 / m3, r5 = m5 / m3;
+    const double c = is * is, sr4 = sd * r4;
+    dG = f3((float)(c * (sr4 * wx - Gx)), (float)(c * (sr4 * wy - Gy)), (float)(c * (sr4 * wz - Gz)));
+    ds = (float)((r5 - 2.0 * k * r4 + (Gx * Gx + Gy * Gy + Gz * Gz) * c - 3.0) * is);
     return true;
 }
 
 // Add coefficients (of d mu, d grad mu, d sigma, d s at point x) to the parameter gradient;
 // vertex: x is a real-collision vertex (cache slot 0), else a tentative collision (slot 1).
-__device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const PointQ& q, float cmu, float3 cG,
+// Offset-grid cell of x with its fractions formed in double: in single precision u = (x - lo)
+// scale reaches the grid resolution and its fraction keeps an absolute error of about 1e-5,
+// which the weights of the nodes it is small for carry as a relative error.
+__device__ __forceinline__ TriCell tri_cell_d(const int res[3], const double scale[3], const double lo[3], D3 x) {
+    TriCell c;
+    int i[3];
+    double f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double ua = fmin(fmax((comp(x, a) - lo[a]) * scale[a], 0.0), (double)(res[a] - 1));
+        const int ia = min((int)floor(ua), res[a] - 2);
+        i[a] = ia;
+        f[a] = ua - (double)ia;
+    }
+    c.base = (i[2] * res[1] + i[1]) * res[0] + i[0];
+    c.fx = (float)f[0];
+    c.fy = (float)f[1];
+    c.fz = (float)f[2];
+    return c;
+}
+
+__device__ __forceinline__ void scatter_grad(const SceneDev& S, D3 x, const PointQ& q, float cmu, float3 cG,
                                              float csig, float cs, float* __restrict__ grad_off, GradAcc& acc,
                                              bool vertex) {
     if (S.offset && grad_off) {
-        const TriCell c = tri_cell(S.off_res, S.off_scale, S.lo, x);
+        const TriCell c = tri_cell_d(S.off_res, S.off_scale_d, S.lo_d, x);
         const bool same = c.base == acc.cell0 || c.base == acc.cell1;
         const int k = c.base == acc.cell0 ? 0 : (c.base == acc.cell1 ? 1 : (vertex ? 0 : 1));
         if (!same) {
@@ -222,7 +259,7 @@ __device__ __forceinline__ void scatter_grad(const SceneDev& S, float3 x, const 
 }
 
 // coefficient c on d log sigma_t(x, d) = d log rho + d log sigma_proj(d)
-__device__ __forceinline__ void add_dlog_sigma_t(const SceneDev& S, float3 x, const PointQ& q, float3 d, float c,
+__device__ __forceinline__ void add_dlog_sigma_t(const SceneDev& S, D3 x, const PointQ& q, float3 d, float c,
                                                  float* grad_off, GradAcc& acc) {
     float dmu, dsig, ds;
     float3 dG;

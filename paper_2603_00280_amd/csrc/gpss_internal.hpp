@@ -37,8 +37,9 @@ struct gpss_scene {
     float* d_maj = nullptr;
     float* d_obs = nullptr;            // conditioned GP: kMaxObs float4 (position, alpha) + packed L^-1 rows
     double* d_obs_d = nullptr;         // the same in double for the majorant: 3n positions, n alpha, n x n L^-1
-    float* d_scratch = nullptr;        // per-path radiance of the last render
+    float* d_scratch = nullptr;        // per-path radiances of the wavefront and one-thread forms
     size_t scratch_floats = 0;
+    unsigned long long* d_acc = nullptr;  // per-pixel fixed-point radiance sums (two words per pixel)
     int device = 0;
     uint32_t spp = 0;
     int kernel = 0;                    // GPSS_KERNEL_*
@@ -48,6 +49,8 @@ struct gpss_scene {
     uint32_t wf_grid = 0;              // persistent workgroups per wavefront launch
     uint32_t* d_head = nullptr;        // path counter of the persistent scheduled kernel
     gpss::SceneDev* d_dev = nullptr;   // device copy of `dev` read by the persistent kernels
+    gpss::SceneDev* h_rec = nullptr;   // pinned staging of the record's asynchronous uploads
+    hipEvent_t rec_event = nullptr;    // completion of the last upload from h_rec
     uint64_t dev_version = 1;          // bumped whenever `dev` changes
     uint64_t dev_uploaded = 0;         // version held by d_dev
     uint32_t sched_grid = 0;           // workgroups of the persistent scheduled kernel
@@ -59,6 +62,7 @@ namespace gpss {
 int set_error(int code, const char* fmt, ...);
 int check_hip(hipError_t e, const char* what);
 int ensure_scratch(gpss_scene* s, size_t floats);
+int ensure_acc(gpss_scene* s);
 
 // kernel launchers (gpss_forward.hip)
 int launch_majorants(gpss_scene* s, hipStream_t stream);
@@ -70,7 +74,12 @@ int wf_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint
 int mega_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
 int ensure_sched(gpss_scene* s, hipStream_t stream);
 int sched_waves_per_simd();
-int sched_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
+// paths (per-path output) or acc (per-pixel accumulator) receives the radiances
+int sched_render(gpss_scene* s, float* paths, unsigned long long* acc, uint64_t* counters, uint32_t s0,
+                 uint32_t ns, hipStream_t stream);
+int launch_acc_clear(unsigned long long* acc, uint64_t npix, hipStream_t stream);
+int launch_acc_finalize(const unsigned long long* acc, float* image, uint32_t ns, uint64_t npix,
+                        hipStream_t stream);
 int device_cus(int device, int* cus);
 int launch_debug_trace(gpss_scene* s, const uint32_t* ids, uint32_t n, float* out, int kmax,
                        hipStream_t stream);

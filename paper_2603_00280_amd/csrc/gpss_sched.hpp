@@ -20,6 +20,7 @@
 // path radiances are bit-identical to it.
 #pragma once
 
+#include "gpss_accum.hpp"
 #include "gpss_grad.hpp"
 #include "gpss_trace.hpp"
 #include "gpss_waves.hpp"
@@ -68,23 +69,37 @@ struct LaunchSource {
     }
 };
 
+// Where the forward form puts each path's radiance: paths[slot] when `paths` is set (per-path
+// output), else its pixel's fixed-point accumulator `acc` (two words per pixel, gpss_accum.hpp).
+struct PathOut {
+    float* paths;
+    unsigned long long* acc;
+};
+
 // Inputs and outputs of the path-replay adjoint form of the loop.
 struct AdjointIo {
     const float* dloss;        // d loss / d pixel
-    const float* radiance;     // each path's radiance (forward pass), by output slot
     float* grad_off;           // offset-grid gradient (nullable), accumulated atomically per cell
     float inv_ns;              // 1 / samples per pixel of the launch
 };
 
+// Light connections per path whose contribution the adjoint's primal pass keeps for the
+// replay (one LDS column each); later connections are walked twice in the replay.
+constexpr int kAdjConn = 4;
+
 // Trace every path of `src` (a wave-collective path source: take(idle, slot, pixel, sample)
-// hands idle lanes new paths, exhausted() is wave-uniform).  Forward form (ADJ false): write
-// each path's radiance to paths[slot].  Adjoint form: replay each path with weight
-// dloss[pixel] / ns against its forward radiance and accumulate the parameter gradient
-// (frozen-sampling estimator; the terms are those of the one-thread replay in
-// gpss_adjoint.hip) into io.grad_off and acc; the caller empties the workgroup's gradient
-// table before (grad_table_init) and adds the lane's cached cells and the table to the grid
-// after (flush_grad_cell, grad_table_flush).  Must be called by whole waves; returns when
-// the source is exhausted and every lane's path has ended.
+// hands idle lanes new paths, exhausted() is wave-uniform).  Forward form (ADJ false): each
+// path's radiance goes to `out`.  Adjoint form: each path with dloss[pixel] != 0 is traced
+// twice by its lane: a primal pass, the forward tracer's own, gives its radiance L and keeps
+// the contributions of its first kAdjConn light connections; a replay of the same random
+// streams then carries L_rem (L less the contributions already passed) and accumulates the
+// parameter gradient with weight dloss[pixel] / ns (frozen-sampling estimator; the terms are
+// those of the one-thread replay in gpss_adjoint.hip) into io.grad_off and acc.  A shadow ray
+// whose contribution was kept is walked once in the replay, for its gradient, and not at all
+// when the contribution is 0.  Nothing is stored per path outside the lane.  The caller
+// empties the workgroup's gradient table before (grad_table_init) and adds the lane's cached
+// cells and the table to the grid after (flush_grad_cell, grad_table_flush).  Must be called
+// by whole waves; returns when the source is exhausted and every lane's path has ended.
 // MED: the scene's medium when the kernel is specialized for it (kMedIso generalized with the
 // isotropic kernel, kMedGgx, kMedAniso generalized with the anisotropic kernel), so that
 // the other media's code is not compiled in; kMedAny takes everything from the scene record.
@@ -99,13 +114,13 @@ __host__ __device__ inline int medium_of(const SceneDev& S) {
 // kernel declares it (__shared__) and hands it to run_scheduled.
 template <bool ADJ>
 struct SchedLds {
-    uint32_t u[3][kSchedBlock];             // output slot, pixel, sample
-    float f[ADJ ? 15 : 6][kSchedBlock];     // beta, L, beta*phase and Le per light (+ adjoint terms)
-    double d[3][kSchedBlock];               // direction of the next track segment
+    uint32_t u[3][kSchedBlock];                     // output slot, pixel, sample
+    float f[ADJ ? 15 + kAdjConn : 6][kSchedBlock];  // beta, L, beta*phase and Le per light (+ adjoint terms)
+    double d[3][kSchedBlock];                       // direction of the next track segment
 };
 
 template <bool STATS, bool ADJ, int MED, class Source>
-__device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, float* __restrict__ paths,
+__device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, const PathOut& out,
                                               PathStats& st, const AdjointIo& io, GradAcc& acc,
                                               SchedLds<ADJ>& lds) {
     auto& cs_u = lds.u;
@@ -113,15 +128,19 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
     auto& cs_d = lds.d;
     const int lt = threadIdx.x;
     enum { kSlot = 0, kPixel = 1, kSample = 2 };
-    // forward: kL = radiance so far; adjoint: kL = remaining radiance L_rem of the replay
+    // forward: kL = radiance so far.  Adjoint: kL + kLlo = radiance so far (primal pass), then
+    // the remaining radiance L_rem (replay), kept as a two-float sum (ff_add) so that L_rem
+    // stays accurate after large contributions have been passed.  kE0 + c: contribution of the
+    // path's light connection c < kAdjConn.
     enum { kBeta = 0, kL = 1, kBp0 = 2, kBp1 = 3, kLe0 = 4, kLe1 = 5,
-           kWpix = 6, kEtot = 7, kE = 8, kWm = 9, kDin = 12 };   // kWm, kDin: 3 columns each
-    enum { kHas0 = 1, kHas1 = 2, kDead = 4, kGradPass = 8, kVertex = 16 };
+           kWpix = 6, kLlo = 7, kE = 8, kWm = 9, kDin = 12, kE0 = 15 };   // kWm, kDin: 3 columns each
+    enum { kHas0 = 1, kHas1 = 2, kDead = 4, kGradPass = 8, kVertex = 16, kReplay = 32 };
 
     int op = kOpIdle;
     int b = 0;                 // real collisions so far
     int mode = 0;              // current segment: 0 track, 1 + li shadow ray toward light li
     int flags = 0;             // kHas0 | kHas1 (lights connected at this vertex) | kDead | ...
+    int conn = 0;              // adjoint: light connections of the path completed so far
     float Tr = 1.0f;
     float coef = 0.0f;         // adjoint: weight of the shadow ray being replayed for its gradient
     Segment sg;
@@ -136,9 +155,61 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
         if (MED == kMedCond) condition_point(S, x, q);
         return q;
     };
-    auto finish = [&](float L) {   // the path's radiance to its output slot; the lane falls idle
-        if (!ADJ) paths[cs_u[kSlot][lt]] = L;
+    auto start = [&]() {   // camera ray of the lane's path (pixel, sample in its columns)
+        const uint32_t pixel = cs_u[kPixel][lt], sample = cs_u[kSample][lt];
+        Rng rc;
+        rc.init(S.key0, S.key1, pixel, sample, 0u, kStreamCam);
+        const float ux = rc.uniform(), uy = rc.uniform();
+        D3 o, d;
+        camera_ray(S, pixel, ux, uy, o, d);
+        cs_d[0][lt] = d.x;
+        cs_d[1][lt] = d.y;
+        cs_d[2][lt] = d.z;
+        cs_f[kBeta][lt] = 1.0f;
+        sg.o = o;
+        b = 0;
+        mode = 0;
+        conn = 0;
+        op = kOpBegin;
+    };
+    auto finish = [&](float L) {   // end of the path (or of the adjoint's primal pass)
+        if (ADJ && !(flags & kReplay)) {
+            // primal pass done (its radiance is kL + kLlo): replay the path against it.  L = 0
+            // makes every gradient term 0 (all contributions are non-negative), so such paths
+            // end here.
+            if (L > 0.0f && L < INFINITY) {
+                flags = kReplay;
+                start();
+                return;
+            }
+        }
+        if (!ADJ) {
+            if (STATS) {
+                const int c = acc_class(L);
+                st.nonfinite += c == kAccNonFinite;
+                st.saturated += c == kAccSaturated;
+            }
+            if (out.paths) out.paths[cs_u[kSlot][lt]] = L;
+            else acc_add(out.acc, cs_u[kPixel][lt], L);
+        }
         op = kOpIdle;
+    };
+    // a track segment left the medium: the environment it sees ends the path
+    auto escape = [&]() {
+        const float c = mul_rn(cs_f[kBeta][lt], S.env);
+        if (ADJ && !(flags & kReplay)) {
+            ff_add(cs_f[kL][lt], cs_f[kLlo][lt], c);
+            finish(cs_f[kL][lt]);
+        } else {
+            finish(add_rn(cs_f[kL][lt], c));
+        }
+    };
+    // after light li's connection: the next light, the next track segment, or the end of a
+    // path whose phase sample was degenerate
+    auto next_connection = [&](int li) {
+        mode = (li == 0 && (flags & kHas1)) ? 2 : 0;
+        if (mode == 0 && (flags & kDead)) finish(cs_f[kL][lt]);
+        else op = kOpBegin;
     };
 
     for (;;) {
@@ -161,29 +232,16 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 got = wpix != 0.0f;   // paths of pixels without loss gradient are skipped
             }
             if (got) {
-                Rng rc;
-                rc.init(S.key0, S.key1, pixel, sample, 0u, kStreamCam);
-                const float ux = rc.uniform(), uy = rc.uniform();
-                D3 o, d;
-                camera_ray(S, pixel, ux, uy, o, d);
                 cs_u[kSlot][lt] = slot;
                 cs_u[kPixel][lt] = pixel;
                 cs_u[kSample][lt] = sample;
-                cs_d[0][lt] = d.x;
-                cs_d[1][lt] = d.y;
-                cs_d[2][lt] = d.z;
-                cs_f[kBeta][lt] = 1.0f;
+                cs_f[kL][lt] = 0.0f;
                 if (ADJ) {
-                    cs_f[kL][lt] = io.radiance[slot];
+                    cs_f[kLlo][lt] = 0.0f;
                     cs_f[kWpix][lt] = wpix;
-                } else {
-                    cs_f[kL][lt] = 0.0f;
                 }
-                sg.o = o;
-                b = 0;
-                mode = 0;
                 flags = 0;
-                op = kOpBegin;
+                start();
             }
             continue;
         }
@@ -197,9 +255,14 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 const D3 d = sg.d;
                 const float3 df = to_f3(d);
                 const float3 xf = to_f3(x);
+                // the double frame before the point statistics: fewer values are live
+                FrameD fr;
+                if (MED != kMedCond) fr = scatter_frame(S, x, d);
                 const PointQ q = point(xf);
+                if (MED == kMedCond) fr = scatter_frame(q, d);
                 const float beta = cs_f[kBeta][lt];
-                flags = 0;
+                const bool replay = ADJ && (flags & kReplay);
+                flags &= kReplay;
 #pragma unroll
                 for (int li = 0; li < 2; ++li) {
                     D3 wl;
@@ -212,14 +275,13 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     cs_f[kBp0 + li][lt] = mul_rn(beta, ph);
                     cs_f[kLe0 + li][lt] = Le;
                 }
-                if (ADJ) {
+                if (replay) {
                     // density and albedo: every contribution from this vertex on (L_rem)
                     float dmu, dsig;
                     dlog_rho(q.mu, q.sigma, dmu, dsig);
-                    const float c = cs_f[kWpix][lt] * cs_f[kL][lt];
-                    scatter_grad(S, xf, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, io.grad_off, acc, true);
+                    const float c = cs_f[kWpix][lt] * (cs_f[kL][lt] + cs_f[kLlo][lt]);
+                    scatter_grad(S, x, q, c * dmu, f3(0.0f, 0.0f, 0.0f), c * dsig, 0.0f, io.grad_off, acc, true);
                     if (!S.albedo_per_prim && S.albedo > 0.0f) acc.alb += c / S.albedo;
-                    cs_f[kEtot][lt] = 0.0f;
                     cs_f[kDin + 0][lt] = df.x;
                     cs_f[kDin + 1][lt] = df.y;
                     cs_f[kDin + 2][lt] = df.z;
@@ -229,12 +291,12 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 float wgt, pdf;
                 float3 wm;
                 if (STATS) st.phase++;
-                if (sample_scatter(S, q, d, df, rng, wi, wgt, wm, pdf)) {
+                if (sample_scatter(S, q, fr, d, df, rng, wi, wgt, wm, pdf)) {
                     cs_f[kBeta][lt] = mul_rn(beta, wgt);
                     cs_d[0][lt] = wi.x;
                     cs_d[1][lt] = wi.y;
                     cs_d[2][lt] = wi.z;
-                    if (ADJ) {
+                    if (replay) {
                         cs_f[kWm + 0][lt] = wm.x;
                         cs_f[kWm + 1][lt] = wm.y;
                         cs_f[kWm + 2][lt] = wm.z;
@@ -258,8 +320,9 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                 if (mode == 0) {
                     if (ADJ && (flags & kVertex)) {
                         // phase sample of the vertex just left: contributions after its lights
+                        // (their contributions have been taken off L_rem)
                         flags &= ~kVertex;
-                        const float Lafter = cs_f[kL][lt] - cs_f[kEtot][lt];
+                        const float Lafter = cs_f[kL][lt] + cs_f[kLlo][lt];
                         if (Lafter != 0.0f) {
                             const PointQ q = point(to_f3(sg.o));
                             const float3 wm = f3(cs_f[kWm][lt], cs_f[kWm + 1][lt], cs_f[kWm + 2][lt]);
@@ -267,17 +330,16 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                             float ds;
                             if (dlog_ndf(q.G, q.s, wm, dG, ds)) {
                                 const float c = cs_f[kWpix][lt] * Lafter;
-                                scatter_grad(S, to_f3(sg.o), q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
+                                scatter_grad(S, sg.o, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
                             }
                         }
-                        cs_f[kL][lt] = Lafter;
                     }
                     const D3 o = sg.o, d = d3(cs_d[0][lt], cs_d[1][lt], cs_d[2][lt]);
                     double t0, t1;
                     D3 inv;
                     if (!clip_box(S, o, d, t0, t1, inv)) {
                         if (STATS) st.escaped++;
-                        finish(add_rn(cs_f[kL][lt], mul_rn(cs_f[kBeta][lt], S.env)));
+                        escape();
                     } else {
                         rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamTrack);
                         sg.begin<STATS>(S, o, d, inv, t0, t1, rng, st);
@@ -285,6 +347,20 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     }
                 } else {
                     const int li = mode - 1;
+                    if (ADJ && (flags & kReplay) && !(flags & kGradPass) && conn < kAdjConn) {
+                        // replay of a connection whose contribution E the primal pass kept:
+                        // no walk when E = 0, else the gradient pass only
+                        const float E = cs_f[kE0 + conn][lt];
+                        ff_add(cs_f[kL][lt], cs_f[kLlo][lt], -E);
+                        if (E == 0.0f) {
+                            ++conn;
+                            next_connection(li);
+                            continue;
+                        }
+                        cs_f[kE][lt] = E;
+                        coef = cs_f[kWpix][lt] * E;
+                        flags |= kGradPass;
+                    }
                     const D3 x = sg.o;
                     D3 wl, inv;
                     double tend;
@@ -344,10 +420,10 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                                 op = kOpScatter;
                             }
                         } else {
-                            if (ADJ) {   // null collision: every remaining contribution
-                                const float Lrem = cs_f[kL][lt];
+                            if (ADJ && (flags & kReplay)) {   // null collision: every remaining contribution
+                                const float Lrem = cs_f[kL][lt] + cs_f[kLlo][lt];
                                 if (Lrem != 0.0f)
-                                    add_dlog_sigma_t(S, xf, q, df, -cs_f[kWpix][lt] * Lrem * sig / (sg.maj - sig),
+                                    add_dlog_sigma_t(S, sg.o + sg.t * sg.d, q, df, -cs_f[kWpix][lt] * Lrem * sig / (sg.maj - sig),
                                                      io.grad_off, acc);
                             }
                             sg.redraw(rng);
@@ -355,7 +431,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                         }
                     } else {
                         if (ADJ && (flags & kGradPass))   // shadow-ray factor of this connection
-                            add_dlog_sigma_t(S, xf, q, df, -coef * sig / (sg.maj - sig), io.grad_off, acc);
+                            add_dlog_sigma_t(S, sg.o + sg.t * sg.d, q, df, -coef * sig / (sg.maj - sig), io.grad_off, acc);
                         Tr *= null_ratio(sig, sg.maj);
                         if (!roulette(Tr, rng)) {
                             Tr = 0.0f;
@@ -377,7 +453,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     op = kOpEval;
                 } else if (mode == 0) {   // track segment left the medium
                     if (STATS) st.escaped++;
-                    finish(add_rn(cs_f[kL][lt], mul_rn(cs_f[kBeta][lt], S.env)));
+                    escape();
                 } else {
                     nee_done = true;
                 }
@@ -390,23 +466,31 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
             const int li = mode - 1;
             bool next = true;
             if (!ADJ) {
-                const float L = add_rn(cs_f[kL][lt], nee_contribution(cs_f[kBp0 + li][lt], Tr, cs_f[kLe0 + li][lt]));
-                cs_f[kL][lt] = L;
-            } else if (!(flags & kGradPass)) {
-                // primal pass of the connection: its contribution E; a second pass over the same
-                // random stream differentiates it when E != 0
+                cs_f[kL][lt] = add_rn(cs_f[kL][lt], nee_contribution(cs_f[kBp0 + li][lt], Tr, cs_f[kLe0 + li][lt]));
+            } else if (!(flags & kReplay)) {
+                // primal pass: add the contribution and keep it for the replay
                 const float E = nee_contribution(cs_f[kBp0 + li][lt], Tr, cs_f[kLe0 + li][lt]);
-                cs_f[kEtot][lt] = add_rn(cs_f[kEtot][lt], E);
+                ff_add(cs_f[kL][lt], cs_f[kLlo][lt], E);
+                if (conn < kAdjConn) cs_f[kE0 + conn][lt] = E;
+                ++conn;
+            } else if (!(flags & kGradPass)) {
+                // replay of a connection beyond the kept ones: this walk gives its contribution
+                // E; a second pass over the same random stream differentiates it when E != 0
+                const float E = nee_contribution(cs_f[kBp0 + li][lt], Tr, cs_f[kLe0 + li][lt]);
+                ff_add(cs_f[kL][lt], cs_f[kLlo][lt], -E);
                 if (E != 0.0f) {
                     cs_f[kE][lt] = E;
                     coef = cs_f[kWpix][lt] * E;
                     flags |= kGradPass;
                     next = false;
                     op = kOpBegin;
+                } else {
+                    ++conn;
                 }
             } else {
                 // gradient pass done: the NDF at the connection's half vector
                 flags &= ~kGradPass;
+                ++conn;
                 const float3 din = f3(cs_f[kDin][lt], cs_f[kDin + 1][lt], cs_f[kDin + 2][lt]);
                 const float3 h = to_f3(sg.d) - din;
                 const float hn = sqrtf(dot(h, h));
@@ -417,15 +501,11 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, fl
                     const PointQ q = point(xf);
                     if (dlog_ndf(q.G, q.s, (1.0f / hn) * h, dG, ds)) {
                         const float c = cs_f[kWpix][lt] * cs_f[kE][lt];
-                        scatter_grad(S, xf, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
+                        scatter_grad(S, sg.o, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
                     }
                 }
             }
-            if (next) {
-                mode = (li == 0 && (flags & kHas1)) ? 2 : 0;
-                if (mode == 0 && (flags & kDead)) finish(cs_f[kL][lt]);
-                else op = kOpBegin;
-            }
+            if (next) next_connection(li);
         }
     }
 }

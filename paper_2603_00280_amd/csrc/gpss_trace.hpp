@@ -180,22 +180,59 @@ __device__ __forceinline__ bool light_sample(const SceneDev& S, int li, D3 x, D3
     return light_sample(S, li, x, wl, tend, Le, inv);
 }
 
-// Phase-function sampling at a real collision (Sec. 4.2.2 proposal): draws (select, a, b)
-// from the PHASE stream, returns the scattered direction and the throughput weight
-// albedo <v, w_m> D(w_m) / (sigma(d) pdf(w_m)); false for a degenerate sample.
-__device__ __forceinline__ bool sample_scatter(const SceneDev& S, const PointQ& q, D3 d, float3 df, Rng& rng,
-                                               D3& wi, float& wgt, float3& wm, float& pdf) {
+// The proposal's frame at real collision x for travel direction d, in double, from the mean
+// gradient and spread there.  Only N, alpha, cos(theta_v) and a are kept (sample_scatter forms
+// the tangents).
+__device__ __forceinline__ FrameD scatter_frame(const SceneDev& S, D3 x, D3 d) {
+    FrameD fr = make_frame_d(eval_geom_d(S, x), -d);
+    fr.T = fr.B = d3(0.0, 0.0, 0.0);
+    return fr;
+}
+// The same from single-precision point statistics (a conditioned GP's posterior).
+__device__ __forceinline__ FrameD scatter_frame(const PointQ& q, D3 d) {
+    GeomD gd;
+    gd.G = d3(q.G);
+    gd.s = (double)q.s;
+    FrameD fr = make_frame_d(gd, -d);
+    fr.T = fr.B = d3(0.0, 0.0, 0.0);
+    return fr;
+}
+// The frame for q at x: the conditioned GP's from q, every other medium's from the scene.
+__device__ __forceinline__ FrameD scatter_frame(const SceneDev& S, const PointQ& q, D3 x, D3 d) {
+    return q.cond ? scatter_frame(q, d) : scatter_frame(S, x, d);
+}
+
+// Phase-function sampling at a real collision (Sec. 4.2.2 proposal) with the frame fr of
+// scatter_frame: draws (select, a, b) from the PHASE stream, returns the scattered direction
+// and the throughput weight albedo <v, w_m> D(w_m) / (sigma(d) pdf(w_m)); false for a
+// degenerate sample.  The half vector is formed in double, since the scattered direction
+// starts the next segment; the inverse-CDF draws, the pdf and the weight are single precision.
+__device__ __forceinline__ bool sample_scatter(const SceneDev& S, const PointQ& q, const FrameD& fr, D3 d, float3 df,
+                                               Rng& rng, D3& wi, float& wgt, float3& wm, float& pdf) {
     const float3 v = -df;
-    const Proposal prop = make_proposal(q, S.R, v);
+    const D3 vd = -d;
+    Proposal prop = proposal_of(fr, S.R, q.ggx);
+    if (fr.beck) {   // the single-precision tangents of the frame
+        const float3 vt = v - prop.cosv * prop.N;
+        const float st = sqrtf(dot(vt, vt));
+        if (st > 1e-7f) {
+            prop.T = (1.0f / st) * vt;
+        } else {
+            float3 bb;
+            onb(prop.N, prop.T, bb);
+        }
+        prop.B = cross(prop.N, prop.T);
+    }
     const float usel = rng.uniform();
     const uint32_t ua = rng.next24(), ub = rng.next24();
-    wm = sample_half_vector(prop, v, usel, ua, ub);
+    const HalfDraw hd = draw_half(prop, usel, ua, ub);
+    const D3 wmd = combine_half_d(hd, fr, vd);
+    wm = to_f3(wmd);
     pdf = mixture_pdf(prop, v, wm);
-    const float vm = dot(v, wm);
-    if (!(pdf > 0.0f) || !(vm > 0.0f)) return false;
-    const D3 wmd = d3(wm);
-    const D3 vd = -d;
-    wi = normalize((2.0 * dot(vd, wmd)) * wmd - vd);
+    const double vmd = dot(vd, wmd);
+    if (!(pdf > 0.0f) || !(vmd > 0.0)) return false;
+    const float vm = fmaxf(dot(v, wm), 0.0f);
+    wi = normalize((2.0 * vmd) * wmd - vd);
     wgt = fresnel_F(q, vm) * vm * ndf_at(q, wm) / (sigma_proj_at(q, df) * pdf);
     return true;
 }
@@ -210,10 +247,11 @@ constexpr int kRecFields = 16;
 
 // One path (pixel, sample): returns its radiance estimate.  With REC, vertex k's record
 // goes to rec[k * kRecFields ...] for k < kmax: x, t_hit, track steps, (phase, Tr) per
-// light, w_m, pdf, weight, beta after the vertex, L after its next-event estimates.
+// light, w_m, pdf, weight, beta after the vertex, L after its next-event estimates.  Lsum
+// (nullable) receives the sum of the same contributions in double.
 template <bool STATS, bool REC = false>
 __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, PathStats& st,
-                            float* rec = nullptr, int kmax = 0) {
+                            float* rec = nullptr, int kmax = 0, double* Lsum = nullptr) {
     Rng rng;
     rng.init(S.key0, S.key1, pixel, sample, 0u, kStreamCam);
     const float ux = rng.uniform(), uy = rng.uniform();
@@ -225,6 +263,7 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         double t0, t1;
         D3 inv;
         if (!clip_box(S, o, d, t0, t1, inv)) {
+            if (Lsum) *Lsum += (double)mul_rn(beta, S.env);
             L = add_rn(L, mul_rn(beta, S.env));
             if (STATS) st.escaped++;
             break;
@@ -237,6 +276,7 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         float* r = (REC && b < kmax) ? rec + b * kRecFields : nullptr;
         if (res == kAbsorbed) break;
         if (res == kEscape) {
+            if (Lsum) *Lsum += (double)mul_rn(beta, S.env);
             L = add_rn(L, mul_rn(beta, S.env));
             if (STATS) st.escaped++;
             break;
@@ -266,7 +306,9 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
             Rng rn;
             rn.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
                         const float Tr = ratio_track<STATS>(S, x, wl, inv, wlf, tend, rn, st);
-            L = add_rn(L, nee_contribution(mul_rn(beta, p), Tr, Le));
+            const float E = nee_contribution(mul_rn(beta, p), Tr, Le);
+            if (Lsum) *Lsum += (double)E;
+            L = add_rn(L, E);
             if (REC && r) { r[5 + 2 * li] = p; r[6 + 2 * li] = Tr; }
         }
         // phase sampling
@@ -275,7 +317,7 @@ __device__ float trace_path(const SceneDev& S, uint32_t pixel, uint32_t sample, 
         float wgt, pdf;
         float3 wm;
         if (STATS) st.phase++;
-        if (!sample_scatter(S, q, d, df, rng, wi, wgt, wm, pdf)) break;  // degenerate: the path ends
+        if (!sample_scatter(S, q, scatter_frame(S, q, x, d), d, df, rng, wi, wgt, wm, pdf)) break;  // degenerate: the path ends
         beta = mul_rn(beta, wgt);
         if (REC && r) {
             r[9] = wm.x; r[10] = wm.y; r[11] = wm.z; r[12] = pdf; r[13] = wgt; r[14] = beta; r[15] = L;

@@ -13,6 +13,7 @@
 // ranks), and appends outputs to the next queue with one atomic per wave (ballot +
 // prefix ranks).  The arithmetic per path is the same, operation for operation, as the
 // one-thread-per-path kernel, so both give bit-identical path radiances.
+#include "gpss_accum.hpp"
 #include "gpss_internal.hpp"
 #include "gpss_trace.hpp"
 #include "gpss_waves.hpp"
@@ -74,15 +75,26 @@ __global__ void wf_next_kernel(WfState W) {
 template <bool STATS>
 __device__ __forceinline__ void flush_stats_wf(const PathStats& st, unsigned long long* counters) {
     if (!STATS) return;
-    const uint32_t vals[10] = {st.track_steps, st.real, st.nee_steps, st.violations, st.capped,
-                               st.escaped, st.truncated, st.cells, st.phase, st.nee};
+    const uint32_t vals[12] = {st.track_steps, st.real, st.nee_steps, st.violations, st.capped,
+                               st.escaped, st.truncated, st.cells, st.phase, st.nee, st.nonfinite, st.saturated};
 #pragma unroll
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < 12; ++i) {
         uint32_t v = vals[i];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if ((threadIdx.x & 63) == 0 && v) atomicAdd(&counters[i], (unsigned long long)v);
     }
+}
+
+// Final radiance of path p (counted when it is not a valid estimate, see gpss_accum.hpp).
+template <bool STATS>
+__device__ __forceinline__ void wf_emit(const WfState& W, uint32_t p, float L, PathStats& st) {
+    if (STATS) {
+        const int c = acc_class(L);
+        st.nonfinite += c == kAccNonFinite;
+        st.saturated += c == kAccSaturated;
+    }
+    W.out[p] = L;
 }
 
 #ifndef GPSS_WF_TRACK_MIN_WAVES
@@ -120,7 +132,7 @@ __global__ __launch_bounds__(256, GPSS_WF_TRACK_MIN_WAVES) void wf_track_kernel(
             L = add_rn(L, W.nee_c[2 * p]);
             L = add_rn(L, W.nee_c[2 * p + 1]);
             if (bf & kDead) {
-                W.out[p] = L;
+                wf_emit<STATS>(W, p, L, st);
             } else {
                 b = bf;
                 beta = W.beta[p];
@@ -131,7 +143,7 @@ __global__ __launch_bounds__(256, GPSS_WF_TRACK_MIN_WAVES) void wf_track_kernel(
                 if (!clip_box(S, o, d, t0, t1, inv)) {
                     L = add_rn(L, mul_rn(beta, S.env));
                     if (STATS) st.escaped++;
-                    W.out[p] = L;
+                    wf_emit<STATS>(W, p, L, st);
                 } else {
                     uint32_t pixel, sample;
                     pixel_sample(W, p, pixel, sample);
@@ -177,14 +189,14 @@ __global__ __launch_bounds__(256, GPSS_WF_TRACK_MIN_WAVES) void wf_track_kernel(
                 if (res == kEscape) {
                     L = add_rn(L, mul_rn(beta, S.env));
                     if (STATS) st.escaped++;
-                    W.out[p] = L;
+                    wf_emit<STATS>(W, p, L, st);
                 } else if (res == kAbsorbed) {
-                    W.out[p] = L;
+                    wf_emit<STATS>(W, p, L, st);
                 } else {
                     if (STATS) st.real++;
                     if ((int)b + 1 > S.max_depth) {
                         if (STATS) st.truncated++;
-                        W.out[p] = L;
+                        wf_emit<STATS>(W, p, L, st);
                     } else {
                         const D3 x = sg.o + sg.t * sg.d;
                         W.ox[p] = x.x; W.oy[p] = x.y; W.oz[p] = x.z;
@@ -246,7 +258,7 @@ __global__ __launch_bounds__(256) void wf_scatter_kernel(SceneDev S, WfState W, 
             float wgt, pdf;
             float3 wm;
             if (STATS) st.phase++;
-            if (sample_scatter(S, q, d, df, rng, wi, wgt, wm, pdf)) {
+            if (sample_scatter(S, q, scatter_frame(S, q, x, d), d, df, rng, wi, wgt, wm, pdf)) {
                 W.dx[p] = wi.x; W.dy[p] = wi.y; W.dz[p] = wi.z;
                 W.beta[p] = mul_rn(beta, wgt);
             } else {

@@ -22,7 +22,7 @@ GPSS_ERR_OOM = -3
 GPSS_ERR_UNSUPPORTED = -4
 GPSS_NCOUNTERS = 16
 COUNTER_NAMES = ["track_steps", "real", "nee_steps", "violations", "capped", "escaped",
-                 "truncated", "cells", "phase", "nee"]
+                 "truncated", "cells", "phase", "nee", "nonfinite", "saturated"]
 
 EXPORTED = ["gpss_scene_create", "gpss_scene_destroy", "gpss_scene_get_majorants", "gpss_render",
             "gpss_render_paths", "gpss_eval_medium", "gpss_debug_trace", "gpss_scene_set_kernel",

@@ -10,6 +10,9 @@ import numpy as np
 REL_TOL = 1e-4
 FLIP_FRACTION = 1e-3
 FLIP_SIGMAS = 3.0
+# pixels sampled at random for the full-size checks (the oracle traces only those): enough that
+# the raw flipped fraction resolves FLIP_FRACTION (at most 20 of them)
+NPIX_SAMPLED = 20000
 
 
 def compare_images(gpu: np.ndarray, ref: dict, spp: int, label: str = ""):
@@ -69,13 +72,6 @@ def isclose_rel(a, b, rel):
 __all__ = ["compare_images", "assert_parity", "compare_paths", "fmt", "math"]
 
 
-def allowed_flips(n: int) -> int:
-    """Flipped pixels allowed among n sampled pixels: the 99th percentile of
-    Binomial(n, FLIP_FRACTION), i.e. what a 0.1 % flip rate produces by chance."""
-    from scipy import stats
-    return int(stats.binom.ppf(0.99, n, FLIP_FRACTION))
-
-
 def compare_sampled(gpu_vals, ref: dict, spp: int, label: str = ""):
     """Sampled-pixel comparison: gpu_vals and ref['mean'/'var'] are 1-D over the samples."""
     o = np.asarray(ref["mean"], np.float64)
@@ -86,13 +82,16 @@ def compare_sampled(gpu_vals, ref: dict, spp: int, label: str = ""):
     se = np.sqrt(np.maximum(ref["var"], 0.0) / spp)
     within = np.abs(g - o) <= FLIP_SIGMAS * se + floor
     return {"label": label, "n_pixels": int(o.size), "n_flipped": int(bad.sum()),
-            "allowed": allowed_flips(o.size),
+            "flip_fraction": float(bad.mean()),
             "max_rel_unflipped": float(rel[~bad].max()) if (~bad).any() else 0.0,
             "flipped_outside_3sigma": int((bad & ~within).sum()), "image_mean": float(o.mean())}
 
 
 def assert_sampled_parity(stats: dict):
+    """The same bar as assert_parity on a sample of the pixels: the raw fraction of sampled
+    pixels above the relative tolerance is at most FLIP_FRACTION (no allowance for the
+    sampling), each within FLIP_SIGMAS standard errors."""
     msg = str(stats)
-    assert stats["n_flipped"] <= stats["allowed"], msg
+    assert stats["flip_fraction"] <= FLIP_FRACTION, msg
     assert stats["flipped_outside_3sigma"] == 0, msg
     assert stats["max_rel_unflipped"] <= REL_TOL, msg

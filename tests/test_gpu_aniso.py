@@ -87,10 +87,10 @@ def test_aniso_plane_parity(G):
 
 def test_aniso_full_size_sampled(G):
     """512^2, 64 spp, depth 32 (the sphere workload's launch) at alpha_z = 0.01: the GPU
-    image at 400 oracle-traced pixels."""
+    image at 20 000 oracle-traced pixels."""
     s = sc.aniso_sphere_scene(0.01)
     rng = np.random.default_rng(7)
-    px = np.sort(rng.choice(s.n_pixels, 400, replace=False)).astype(np.int64)
+    px = np.sort(rng.choice(s.n_pixels, gh.NPIX_SAMPLED, replace=False)).astype(np.int64)
     print(f"[aniso] full size {s.name} {s.width}x{s.height} spp {s.spp}", flush=True)
     img = G.GpssScene(s).render().cpu().numpy().ravel()
     ref = orc.OracleScene(s).render_pixels(px)

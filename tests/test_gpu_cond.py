@@ -101,10 +101,10 @@ def test_cond_image_parity_ragged(G):
 
 def test_cond_full_size_sampled(G):
     """512^2, 64 spp, depth 32 (the sphere workload's launch) with 32 observations: the GPU
-    image at 400 oracle-traced pixels."""
+    image at 20 000 oracle-traced pixels."""
     s = sc.cond_sphere_scene()
     rng = np.random.default_rng(12)
-    px = np.sort(rng.choice(s.n_pixels, 400, replace=False)).astype(np.int64)
+    px = np.sort(rng.choice(s.n_pixels, gh.NPIX_SAMPLED, replace=False)).astype(np.int64)
     print(f"[cond] full size {s.name} {s.width}x{s.height} spp {s.spp}", flush=True)
     img = G.GpssScene(s).render().cpu().numpy().ravel()
     ref = orc.OracleScene(s).render_pixels(px)

@@ -78,14 +78,21 @@ def test_medium_evaluation_matches_oracle(G):
             st = o.sigma_t(pts[i].astype(np.float64), dirs[i].astype(np.float64))
             D = orc.ndf(e["G"], e["s"], dirs[i].astype(np.float64))
             sp = orc.sigma_proj(e["G"], e["s"], dirs[i].astype(np.float64))
+            rho = orc.rho(e["mu"], e["sigma"])
             for name, gv, ov, scale in (("mu", out[i, 0], e["mu"], 1.0), ("sigma", out[i, 1], e["sigma"], 0),
+                                        ("rho", out[i, 3], rho, 1e-3),
                                         ("proj", out[i, 4], sp, 1e-3), ("sigma_t", out[i, 5], st, 1e-3),
                                         ("ndf", out[i, 6], D, 1e-3)):
                 err = abs(gv - ov) / max(abs(ov), scale * 1e-3 if scale else 1e-30)
                 worst[name] = max(worst.get(name, 0.0), err)
+            worst["mu_abs"] = max(worst.get("mu_abs", 0.0), abs(out[i, 0] - e["mu"]))
             assert out[i, 7] == pytest.approx(e["albedo"], rel=1e-6)
         print(s.name, {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+        # mu: single-precision evaluation of distances of order 1, so an absolute error of a few
+        # units in the last place of 1 (2^-23 = 1.2e-7)
+        assert worst["mu_abs"] < 5e-7
         assert worst["sigma"] < 5e-6
+        assert worst["rho"] < 1e-4
         assert worst["proj"] < 1e-4 and worst["sigma_t"] < 1e-4 and worst["ndf"] < 1e-4
 
 

@@ -82,18 +82,17 @@ def test_fresnel_adjoint_matches_oracle(G):
     g_sc = g_sc.cpu().numpy()
     g_gpu = np.array([g_sc[0], g_sc[1], g_sc[2]] + [g_off[i] for i in ids[3:]], np.float64)
     print("[fresnel] adjoint", np.c_[g_gpu, g_orc][:6], flush=True)
-    for sl in (slice(0, 3), slice(3, None)):
-        a, b = g_gpu[sl], g_orc[sl]
-        assert np.abs(a - b).max() <= 1e-3 * np.abs(b).max()
+    from tests.test_gpu_adjoint import _check_groups
+    _check_groups(g_gpu, g_orc)
 
 
 @pytest.mark.parametrize("channel", [0, 2])
 def test_fresnel_full_size_sampled(G, channel):
     """The measured Fresnel workload (sphere l = 0.1 at 512^2, 64 spp, depth 32, gold, one
-    channel scene): the GPU image at 300 oracle-traced pixels."""
+    channel scene): the GPU image at 20 000 oracle-traced pixels."""
     s = sc.fresnel_rgb_scenes(sc.sphere_scene(0.1), "gold")[channel]
     rng = np.random.default_rng(20 + channel)
-    px = np.sort(rng.choice(s.n_pixels, 300, replace=False)).astype(np.int64)
+    px = np.sort(rng.choice(s.n_pixels, gh.NPIX_SAMPLED, replace=False)).astype(np.int64)
     print(f"[fresnel] full size {s.name} {s.width}x{s.height} spp {s.spp}", flush=True)
     img = G.GpssScene(s).render().cpu().numpy().ravel()
     ref = orc.OracleScene(s).render_pixels(px)

@@ -84,10 +84,10 @@ def test_ggx_plane_parity(G):
 
 
 def test_ggx_full_size_sampled(G):
-    """512^2, 64 spp, depth 32 at alpha = 0.5: the GPU image at 400 oracle-traced pixels."""
+    """512^2, 64 spp, depth 32 at alpha = 0.5: the GPU image at 20 000 oracle-traced pixels."""
     s = sc.ggx_sphere_scene(0.5)
     rng = np.random.default_rng(8)
-    px = np.sort(rng.choice(s.n_pixels, 400, replace=False)).astype(np.int64)
+    px = np.sort(rng.choice(s.n_pixels, gh.NPIX_SAMPLED, replace=False)).astype(np.int64)
     print(f"[ggx] full size {s.name} {s.width}x{s.height} spp {s.spp}", flush=True)
     img = G.GpssScene(s).render().cpu().numpy().ravel()
     ref = orc.OracleScene(s).render_pixels(px)
