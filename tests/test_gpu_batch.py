@@ -51,6 +51,31 @@ def test_batch_sees_parameter_updates(G):
     assert np.array_equal(imgs[1].cpu().numpy(), fresh.render().cpu().numpy())
 
 
+def test_batch_calls_are_stream_ordered(G):
+    """Calls return without waiting: several replays into different image buffers and a
+    parameter update between them, queued on one side stream with no host synchronization,
+    each give the image of its own parameters."""
+    scenes = _small_batch()[:4]
+    gs = [G.GpssScene(s) for s in scenes]
+    G.render_batch(gs)                      # plan and graph
+    torch.cuda.synchronize()
+    ref0 = [g.render().cpu().numpy() for g in gs]
+    upd = dict(variance=0.004, lengthscale=0.07, albedo=0.6)
+    ref1 = G.GpssScene(scenes[2].replace(**upd)).render().cpu().numpy()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs = [[torch.empty(g.shape, device="cuda") for g in gs] for _ in range(6)]
+        for k in range(6):
+            if k == 3:   # the record changes between queued replays
+                gs[2].set_params(stream=stream, **upd)
+            G.render_batch(gs, outs[k], stream=stream)
+    stream.synchronize()
+    for k in range(6):
+        for i, (o, r) in enumerate(zip(outs[k], ref0)):
+            want = ref1 if (k >= 3 and i == 2) else r
+            assert np.array_equal(o.cpu().numpy(), want), (k, i)
+
+
 def test_batch_autotune_and_cache(G, tmp_path):
     os.environ["GPSS_TUNE_CACHE"] = str(tmp_path / "tune.txt")
     try:

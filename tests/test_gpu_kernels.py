@@ -45,6 +45,8 @@ def test_kernel_matches_megakernel_bitwise(G, name, kernel):
     diff = np.flatnonzero(pm.view(np.uint32) != pw.view(np.uint32))
     assert diff.size == 0, (diff[:8], pm.ravel()[diff[:8]], pw.ravel()[diff[:8]])
     assert G.counters_dict(cm) == G.counters_dict(cw)
+    # every path radiance is a finite, non-negative estimate below the accumulator's range
+    assert G.counters_dict(cm)["nonfinite"] == 0 and G.counters_dict(cm)["saturated"] == 0
     # the image entry point through both kernels
     im_w = g.render().cpu().numpy()
     g.set_kernel("mega")
