@@ -148,6 +148,18 @@ int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n);
 int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1,
                 gpss_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid allocation): gpss_render by the persistent kernel, with its scratch
+ * memory (the per-pixel fixed-point sums, 16 bytes per pixel, and the path counter) in a
+ * fixed array of the library on each device instead of memory of the scene.  The call
+ * allocates and frees nothing (it reads the scene record uploaded as gpss_render would).
+ * At most 1048576 pixels (1024 x 1024); larger images return GPSS_ERR_INVALID_ARG.  The
+ * array (16 MiB per device) is held until the process ends and is shared by every call on a
+ * device: calls that overlap on one device race (each clears the array on its own stream
+ * before rendering).  The scene's device must be current.  Same image as gpss_render. */
+int gpss_render_noalloc(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1,
+                        gpss_stream_t stream);
+
 /* As gpss_render but writes the per-path radiance to paths_dev (device,
  * width*height*(s1-s0) floats, pixel-major, then sample).  counters_dev (device, nullable)
  * receives GPSS_NCOUNTERS uint64 event counts added to its current contents. */

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpss.so")
 SOURCES = ["gpss_api.hip", "gpss_forward.hip", "gpss_wavefront.hip", "gpss_adjoint.hip", "gpss_batch.hip",
-           "gpss_persistent.hip"]
+           "gpss_persistent.hip", "gpss_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GPSS_OFFLOAD_ARCH", "gfx950")
 

@@ -482,6 +482,9 @@ void fill_dev(gpss_scene* s) {
 
 // One call renders at most 2^31 - 1 paths (32-bit path slots in the kernels); checked before
 // any allocation so that an oversized range fails fast with a clear message.
+}  // namespace
+
+namespace gpss {
 int check_path_count(const gpss_scene* s, uint32_t s0, uint32_t s1) {
     if (s1 <= s0) return set_error(GPSS_ERR_INVALID_ARG, "empty sample range [%u, %u)", s0, s1);
     const uint64_t n = s->n_pixels() * (uint64_t)(s1 - s0);
@@ -490,8 +493,7 @@ int check_path_count(const gpss_scene* s, uint32_t s0, uint32_t s1) {
                          (unsigned long long)n);
     return GPSS_OK;
 }
-
-}  // namespace
+}  // namespace gpss
 
 extern "C" {
 
@@ -598,14 +600,14 @@ int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n) {
 int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_dev, uint32_t s0, uint32_t s1,
                       gpss_stream_t stream) {
     if (!scene || !paths_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
-    if (int rc = check_path_count(scene, s0, s1)) return rc;
+    if (int rc = gpss::check_path_count(scene, s0, s1)) return rc;
     return gpss::launch_render_paths(scene, paths_dev, counters_dev, s0, s1 - s0,
                                      reinterpret_cast<hipStream_t>(stream));
 }
 
 int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream) {
     if (!scene || !image_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
-    if (int rc = check_path_count(scene, s0, s1)) return rc;
+    if (int rc = gpss::check_path_count(scene, s0, s1)) return rc;
     const uint32_t ns = s1 - s0;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (scene->kernel == GPSS_KERNEL_MEGA || scene->kernel == GPSS_KERNEL_WAVEFRONT) {
@@ -661,7 +663,7 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
 int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float* grad_offset_dev,
                         float* grad_scalars_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream) {
     if (!scene || !dloss_dimage_dev || !grad_scalars_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
-    if (int rc = check_path_count(scene, s0, s1)) return rc;
+    if (int rc = gpss::check_path_count(scene, s0, s1)) return rc;
     if (scene->d_offset && !grad_offset_dev)
         return set_error(GPSS_ERR_INVALID_ARG, "scene has a mean-offset grid: grad_offset_dev is required");
     if (scene->dev.aniso_k != 0.0f || scene->dev.ggx || scene->dev.n_obs > 0)

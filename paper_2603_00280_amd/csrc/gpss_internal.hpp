@@ -74,9 +74,11 @@ int wf_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint
 int mega_render(gpss_scene* s, float* paths, uint64_t* counters, uint32_t s0, uint32_t ns, hipStream_t stream);
 int ensure_sched(gpss_scene* s, hipStream_t stream);
 int sched_waves_per_simd();
-// paths (per-path output) or acc (per-pixel accumulator) receives the radiances
+// paths (per-path output) or acc (per-pixel accumulator) receives the radiances; head: the
+// launch's path counter (nullptr: the scene's)
 int sched_render(gpss_scene* s, float* paths, unsigned long long* acc, uint64_t* counters, uint32_t s0,
-                 uint32_t ns, hipStream_t stream);
+                 uint32_t ns, hipStream_t stream, uint32_t* head = nullptr);
+int check_path_count(const gpss_scene* s, uint32_t s0, uint32_t s1);
 int launch_acc_clear(unsigned long long* acc, uint64_t npix, hipStream_t stream);
 int launch_acc_finalize(const unsigned long long* acc, float* image, uint32_t ns, uint64_t npix,
                         hipStream_t stream);

@@ -48,19 +48,20 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_render_kernel
 
 
 int sched_render(gpss_scene* s, float* paths, unsigned long long* acc, uint64_t* counters, uint32_t s0,
-                 uint32_t ns, hipStream_t stream) {
+                 uint32_t ns, hipStream_t stream, uint32_t* head) {
     const PathOut out{paths, acc};
     const uint64_t npaths = s->n_pixels() * ns;
     if (npaths > 0x7FFFFFFFull) return set_error(GPSS_ERR_INVALID_ARG, "persistent launch limited to 2^31 paths");
     int rc = ensure_sched(s, stream);
     if (rc) return rc;
-    hipLaunchKernelGGL(sched_reset_kernel, dim3(1), dim3(64), 0, stream, s->d_head);
+    if (!head) head = s->d_head;
+    hipLaunchKernelGGL(sched_reset_kernel, dim3(1), dim3(64), 0, stream, head);
     const dim3 blk(256);
     const dim3 grid(s->sched_grid);
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters);
     const int med = medium_of(s->dev);
 #define GPSS_SCHED_LAUNCH(ST, M)                                                                                    \
-    hipLaunchKernelGGL((sched_render_kernel<ST, M>), grid, blk, 0, stream, s->d_dev, out, s->d_head,              \
+    hipLaunchKernelGGL((sched_render_kernel<ST, M>), grid, blk, 0, stream, s->d_dev, out, head,                    \
                        ST ? cnt : nullptr, s0, ns, (uint32_t)npaths)
     if (counters) {
         if (med == kMedGgx) GPSS_SCHED_LAUNCH(true, kMedGgx);

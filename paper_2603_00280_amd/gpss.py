@@ -25,6 +25,7 @@ COUNTER_NAMES = ["track_steps", "real", "nee_steps", "violations", "capped", "es
                  "truncated", "cells", "phase", "nee", "nonfinite", "saturated"]
 
 EXPORTED = ["gpss_scene_create", "gpss_scene_destroy", "gpss_scene_get_majorants", "gpss_render",
+            "gpss_render_noalloc",
             "gpss_render_paths", "gpss_eval_medium", "gpss_debug_trace", "gpss_scene_set_kernel",
             "gpss_render_adjoint", "gpss_scene_set_params", "gpss_render_batch", "gpss_batch_autotune",
             "gpss_last_error"]
@@ -76,6 +77,7 @@ def lib():
         L.gpss_scene_destroy.argtypes = [vp]
         L.gpss_scene_get_majorants.argtypes = [vp, fp, C.c_uint64]
         L.gpss_render.argtypes = [vp, vp, C.c_uint32, C.c_uint32, vp]
+        L.gpss_render_noalloc.argtypes = [vp, vp, C.c_uint32, C.c_uint32, vp]
         L.gpss_render_paths.argtypes = [vp, vp, vp, C.c_uint32, C.c_uint32, vp]
         L.gpss_eval_medium.argtypes = [vp, vp, vp, vp, C.c_uint64, vp]
         L.gpss_debug_trace.argtypes = [vp, vp, C.c_uint32, vp, C.c_uint32, vp]
@@ -191,6 +193,10 @@ def gpss_scene_get_majorants(handle: int, n: int) -> np.ndarray:
 
 def gpss_render(handle: int, image_ptr: int, s0: int, s1: int, stream=None) -> None:
     _check(lib().gpss_render(handle, image_ptr, s0, s1, _stream_ptr(stream)))
+
+
+def gpss_render_noalloc(handle: int, image_ptr: int, s0: int, s1: int, stream=None) -> None:
+    _check(lib().gpss_render_noalloc(handle, image_ptr, s0, s1, _stream_ptr(stream)))
 
 
 def gpss_render_paths(handle: int, paths_ptr: int, counters_ptr: Optional[int], s0: int, s1: int,
