@@ -4,7 +4,8 @@
 // persistent kernels finish paths in no fixed order, so a floating-point sum would depend on
 // scheduling.  Each path's radiance L is instead rounded to the integer v = round(L 2^32)
 // (L in [0, 2^24), so v < 2^56) and added to the pixel's two 64-bit words: the low 32 bits of
-// v to word 0, the high bits to word 1.  Integer additions commute, so the sum is exact and
+// v to word 0, the high bits to word 1 (the persistent kernels gather a wave's paths of a pixel
+// in LDS first, gpss_sched.hpp).  Integer additions commute, so the sum is exact and
 // independent of the order; 2^31 additions of either part cannot overflow its word.  The
 // mean is then (word1 2^32 + word0) 2^-32 / samples, formed in double and rounded once to
 // float.  Every form of the tracer (persistent, batch, wavefront, one thread per path) forms
@@ -36,14 +37,6 @@ __device__ __forceinline__ uint64_t acc_fixed(float L) {
     if (c == kAccNonFinite) return 0ull;
     const float v = c == kAccSaturated ? kAccMax : L;
     return (uint64_t)__double2ull_rn((double)v * kAccScale);
-}
-
-// Add one path's radiance to pixel `pixel` of the two-word accumulator.
-__device__ __forceinline__ void acc_add(unsigned long long* __restrict__ acc, uint32_t pixel, float L) {
-    const uint64_t v = acc_fixed(L);
-    unsigned long long* w = acc + 2ull * pixel;
-    if (v & 0xFFFFFFFFull) atomicAdd(w, (unsigned long long)(v & 0xFFFFFFFFull));
-    if (v >> 32) atomicAdd(w + 1, (unsigned long long)(v >> 32));
 }
 
 // Mean of `ns` samples from the two words.

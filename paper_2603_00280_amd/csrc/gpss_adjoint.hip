@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_adjoint_kerne
     PathStats st;
     st.clear();
     LaunchSource src;
-    src.rd.init(npaths);
+    src.init(npaths);
     src.head = head;
     src.s0 = s0;
     src.ns = ns;

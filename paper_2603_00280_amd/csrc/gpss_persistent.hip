@@ -1,5 +1,5 @@
 // Persistent scheduled form of the forward tracer for one scene: a grid sized to the
-// resident waves, each wave taking its paths in 64-path chunks (one atomic per chunk) and
+// resident waves, each wave taking its paths in chunks of 64 or 256 (one atomic per chunk) and
 // tracing them with the scheduled loop of gpss_sched.hpp.  Each path's radiance goes to the
 // per-path output or to its pixel's fixed-point accumulator.
 #include "gpss_internal.hpp"
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void sched_render_kernel
     PathStats st;
     st.clear();
     LaunchSource src;
-    src.rd.init(npaths);
+    src.init(npaths);
     src.head = head;
     src.s0 = s0;
     src.ns = ns;

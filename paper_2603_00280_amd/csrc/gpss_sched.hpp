@@ -27,7 +27,8 @@
 
 namespace gpss {
 
-enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBegin = 4 };
+// kOpOut: the path has ended and its radiance (column kL) waits to be added to its pixel
+enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBegin = 4, kOpOut = 5 };
 
 // Minimum number of waiting lanes (of 64) before an operation runs while other lanes could
 // still walk, and the number of cell steps per walk operation.
@@ -53,9 +54,20 @@ enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBe
 // Threads per workgroup of the kernels that run the scheduled loop (per-lane LDS columns).
 constexpr int kSchedBlock = 256;
 
-// Paths p in [0, npaths) of one launch: pixel p / ns, sample s0 + p % ns, slot p.
+// Paths p in [0, npaths) of one launch: pixel p / ns, sample s0 + p % ns, slot p.  Large
+// launches are claimed 256 consecutive paths at a time (at 256 samples per pixel one pixel,
+// whose sum then leaves the wave's pixel table, below, about once); launches with fewer than
+// kLaunchChunkMinClaims such claims per resident wave take 64, so that no wave runs out of
+// paths early.
+constexpr uint32_t kLaunchChunkBig = 256;
+constexpr uint32_t kLaunchChunkMinClaims = 32;
 struct LaunchSource {
     ChunkReader rd;
+    __device__ __forceinline__ void init(uint32_t npaths) {
+        const uint32_t waves = gridDim.x * (blockDim.x / 64u);
+        const bool big = npaths / waves >= kLaunchChunkMinClaims * kLaunchChunkBig;
+        rd.init(npaths, big ? kLaunchChunkBig : kChunk);
+    }
     uint32_t* head;
     uint32_t s0, ns;
     __device__ __forceinline__ bool exhausted() const { return rd.exhausted; }
@@ -112,11 +124,26 @@ __host__ __device__ inline int medium_of(const SceneDev& S) {
 // Cold per-lane state (touched once per segment or vertex) lives in LDS, one column per
 // lane, so that registers hold what the cell walk and the medium evaluation use.  The
 // kernel declares it (__shared__) and hands it to run_scheduled.
+// Per-wave table of pixel sums (direct-mapped by pixel): a wave takes consecutive paths, which
+// share pixels, so ended paths add to their pixel's entry here and an entry goes to the global
+// accumulator (two integer atomics) only when it changes pixel and at the end.  The device-
+// scope atomics of one add per path reach past the per-XCD L2 and wrote about 100 bytes of
+// memory traffic per path.
+constexpr int kAccTable = 16;
+constexpr int kSchedWaves = kSchedBlock / 64;
+struct AccTable {
+    unsigned long long lo[kSchedWaves][kAccTable], hi[kSchedWaves][kAccTable];
+    uint32_t px[kSchedWaves][kAccTable];   // pixel + 1 of the entry, 0 = empty
+};
+
 template <bool ADJ>
 struct SchedLds {
     uint32_t u[3][kSchedBlock];                     // output slot, pixel, sample
     float f[ADJ ? 15 + kAdjConn : 6][kSchedBlock];  // beta, L, beta*phase and Le per light (+ adjoint terms)
     double d[3][kSchedBlock];                       // direction of the next track segment
+    double o[3][kSchedBlock];                       // origin of the current segment
+    double sd[3][kSchedBlock];                      // direction of the current segment
+    AccTable acc;                                   // forward form with a pixel accumulator
 };
 
 template <bool STATS, bool ADJ, int MED, class Source>
@@ -126,7 +153,12 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
     auto& cs_u = lds.u;
     auto& cs_f = lds.f;
     auto& cs_d = lds.d;
+    auto& cs_o = lds.o;
+    auto& cs_sd = lds.sd;
     const int lt = threadIdx.x;
+    const int lane = lt & 63, wv = lt >> 6;
+    const bool accumulate = !ADJ && !out.paths;   // wave-uniform
+    if (accumulate && lane < kAccTable) lds.acc.px[wv][lane] = 0u;
     enum { kSlot = 0, kPixel = 1, kSample = 2 };
     // forward: kL = radiance so far.  Adjoint: kL + kLlo = radiance so far (primal pass), then
     // the remaining radiance L_rem (replay), kept as a two-float sum (ff_add) so that L_rem
@@ -143,8 +175,22 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
     int conn = 0;              // adjoint: light connections of the path completed so far
     float Tr = 1.0f;
     float coef = 0.0f;         // adjoint: weight of the shadow ray being replayed for its gradient
+    // The segment's origin and direction are read at tentative collisions, vertices and
+    // segment starts only, not by the cell walk: they live in LDS (columns cs_o, cs_sd) rather
+    // than in registers, and sg.o, sg.d are not read.
     Segment sg;
-    sg.o = d3(0.0, 0.0, 0.0);
+    auto origin = [&]() { return d3(cs_o[0][lt], cs_o[1][lt], cs_o[2][lt]); };
+    auto set_origin = [&](D3 o) {
+        cs_o[0][lt] = o.x;
+        cs_o[1][lt] = o.y;
+        cs_o[2][lt] = o.z;
+    };
+    auto seg_dir = [&]() { return d3(cs_sd[0][lt], cs_sd[1][lt], cs_sd[2][lt]); };
+    auto set_seg_dir = [&](D3 d) {
+        cs_sd[0][lt] = d.x;
+        cs_sd[1][lt] = d.y;
+        cs_sd[2][lt] = d.z;
+    };
     Rng rng;
     auto point = [&](float3 x) {   // medium statistics at x, with the specialized NDF kind
         PointQ q = eval_point(S, x);
@@ -166,7 +212,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
         cs_d[1][lt] = d.y;
         cs_d[2][lt] = d.z;
         cs_f[kBeta][lt] = 1.0f;
-        sg.o = o;
+        set_origin(o);
         b = 0;
         mode = 0;
         conn = 0;
@@ -189,10 +235,25 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                 st.nonfinite += c == kAccNonFinite;
                 st.saturated += c == kAccSaturated;
             }
-            if (out.paths) out.paths[cs_u[kSlot][lt]] = L;
-            else acc_add(out.acc, cs_u[kPixel][lt], L);
+            if (out.paths) {
+                out.paths[cs_u[kSlot][lt]] = L;
+            } else {   // added to the pixel's sum at the top of the next iteration
+                cs_f[kL][lt] = L;
+                op = kOpOut;
+                return;
+            }
         }
         op = kOpIdle;
+    };
+    // add one entry of the pixel table to the global accumulator and empty it (lane-local)
+    auto flush_entry = [&](int e) {
+        const uint32_t p1 = lds.acc.px[wv][e];
+        if (p1 == 0u) return;
+        unsigned long long* w = out.acc + 2ull * (p1 - 1u);
+        const unsigned long long lo = lds.acc.lo[wv][e], hi = lds.acc.hi[wv][e];
+        if (lo) atomicAdd(w, lo);
+        if (hi) atomicAdd(w + 1, hi);
+        lds.acc.px[wv][e] = 0u;
     };
     // a track segment left the medium: the environment it sees ends the path
     auto escape = [&]() {
@@ -213,6 +274,29 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
     };
 
     for (;;) {
+        if (accumulate) {
+            // ended paths: one pixel at a time (wave-uniform), its entry taken over by that pixel
+            // if it held another, then every lane of the pixel adds its fixed-point radiance
+            for (uint64_t mOut = __ballot(op == kOpOut); mOut;) {
+                const int leader = __builtin_ctzll(mOut);
+                const uint32_t P = __shfl(cs_u[kPixel][lt], leader, 64);
+                const int e = (int)(P % (uint32_t)kAccTable);
+                if (lane == leader && lds.acc.px[wv][e] != P + 1u) {
+                    flush_entry(e);
+                    lds.acc.lo[wv][e] = 0ull;
+                    lds.acc.hi[wv][e] = 0ull;
+                    lds.acc.px[wv][e] = P + 1u;
+                }
+                const bool mine = op == kOpOut && cs_u[kPixel][lt] == P;
+                if (mine) {
+                    const uint64_t v = acc_fixed(cs_f[kL][lt]);
+                    if (v & 0xFFFFFFFFull) atomicAdd(&lds.acc.lo[wv][e], (unsigned long long)(v & 0xFFFFFFFFull));
+                    if (v >> 32) atomicAdd(&lds.acc.hi[wv][e], (unsigned long long)(v >> 32));
+                    op = kOpIdle;
+                }
+                mOut &= ~__ballot(mine);
+            }
+        }
         const uint64_t mIdle = __ballot(op == kOpIdle);
         const uint64_t mWalk = __ballot(op == kOpWalk);
         const uint64_t mEval = __ballot(op == kOpEval);
@@ -245,14 +329,17 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
             }
             continue;
         }
-        if (nBusy == 0) break;  // every lane idle and no paths left
+        if (nBusy == 0) {   // every lane idle and no paths left
+            if (accumulate && lane < kAccTable) flush_entry(lane);
+            break;
+        }
 
         // ---- phase sampling and light-connection set-up at real collisions ----
         if (nScat > 0 && (nScat >= S.scatter_min || nWalk + nEval + nBegin == 0)) {
             if (op == kOpScatter) {
                 ++b;
-                const D3 x = sg.o + sg.t * sg.d;
-                const D3 d = sg.d;
+                const D3 d = seg_dir();
+                const D3 x = origin() + sg.t * d;
                 const float3 df = to_f3(d);
                 const float3 xf = to_f3(x);
                 // the double frame before the point statistics: fewer values are live
@@ -305,7 +392,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                 } else {
                     flags |= kDead;   // the path ends after this vertex's light connections
                 }
-                sg.o = x;
+                set_origin(x);
                 mode = (flags & kHas0) ? 1 : ((flags & kHas1) ? 2 : 0);
                 if (mode == 0 && (flags & kDead)) finish(cs_f[kL][lt]);
                 else op = kOpBegin;
@@ -324,17 +411,18 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                         flags &= ~kVertex;
                         const float Lafter = cs_f[kL][lt] + cs_f[kLlo][lt];
                         if (Lafter != 0.0f) {
-                            const PointQ q = point(to_f3(sg.o));
+                            const D3 o = origin();
+                            const PointQ q = point(to_f3(o));
                             const float3 wm = f3(cs_f[kWm][lt], cs_f[kWm + 1][lt], cs_f[kWm + 2][lt]);
                             float3 dG;
                             float ds;
                             if (dlog_ndf(q.G, q.s, wm, dG, ds)) {
                                 const float c = cs_f[kWpix][lt] * Lafter;
-                                scatter_grad(S, sg.o, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
+                                scatter_grad(S, o, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
                             }
                         }
                     }
-                    const D3 o = sg.o, d = d3(cs_d[0][lt], cs_d[1][lt], cs_d[2][lt]);
+                    const D3 o = origin(), d = d3(cs_d[0][lt], cs_d[1][lt], cs_d[2][lt]);
                     double t0, t1;
                     D3 inv;
                     if (!clip_box(S, o, d, t0, t1, inv)) {
@@ -343,6 +431,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                     } else {
                         rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamTrack);
                         sg.begin<STATS>(S, o, d, inv, t0, t1, rng, st);
+                        set_seg_dir(d);
                         op = kOpWalk;
                     }
                 } else {
@@ -361,13 +450,14 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                         coef = cs_f[kWpix][lt] * E;
                         flags |= kGradPass;
                     }
-                    const D3 x = sg.o;
+                    const D3 x = origin();
                     D3 wl, inv;
                     double tend;
                     float Le;
                     light_sample(S, li, x, wl, tend, Le, inv);
                     rng.init(S.key0, S.key1, pixel, sample, (uint32_t)b, kStreamNee0 + (uint32_t)li);
                     sg.begin<STATS>(S, x, wl, inv, 0.0, tend, rng, st);
+                    set_seg_dir(wl);
                     Tr = 1.0f;
                     op = kOpWalk;
                 }
@@ -396,8 +486,10 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                 const bool capped = ++sg.steps > kStepCap;
                 float u2 = 0.0f;
                 if (!capped && mode == 0) u2 = rng.uniform();
-                const float3 xf = sg.pos();
-                const float3 df = to_f3(sg.d);   // single-precision travel direction
+                const D3 dd = seg_dir();
+                const D3 xd = origin() + sg.t * dd;
+                const float3 xf = to_f3(xd);
+                const float3 df = to_f3(dd);   // single-precision travel direction
                 const PointQ q = point(xf);
                 const float sig = sigma_t_of(q, df);
                 if (capped) {
@@ -423,7 +515,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                             if (ADJ && (flags & kReplay)) {   // null collision: every remaining contribution
                                 const float Lrem = cs_f[kL][lt] + cs_f[kLlo][lt];
                                 if (Lrem != 0.0f)
-                                    add_dlog_sigma_t(S, sg.o + sg.t * sg.d, q, df, -cs_f[kWpix][lt] * Lrem * sig / (sg.maj - sig),
+                                    add_dlog_sigma_t(S, xd, q, df, -cs_f[kWpix][lt] * Lrem * sig / (sg.maj - sig),
                                                      io.grad_off, acc);
                             }
                             sg.redraw(rng);
@@ -431,7 +523,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                         }
                     } else {
                         if (ADJ && (flags & kGradPass))   // shadow-ray factor of this connection
-                            add_dlog_sigma_t(S, sg.o + sg.t * sg.d, q, df, -coef * sig / (sg.maj - sig), io.grad_off, acc);
+                            add_dlog_sigma_t(S, xd, q, df, -coef * sig / (sg.maj - sig), io.grad_off, acc);
                         Tr *= null_ratio(sig, sg.maj);
                         if (!roulette(Tr, rng)) {
                             Tr = 0.0f;
@@ -492,16 +584,16 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                 flags &= ~kGradPass;
                 ++conn;
                 const float3 din = f3(cs_f[kDin][lt], cs_f[kDin + 1][lt], cs_f[kDin + 2][lt]);
-                const float3 h = to_f3(sg.d) - din;
+                const float3 h = to_f3(seg_dir()) - din;
                 const float hn = sqrtf(dot(h, h));
                 float3 dG;
                 float ds;
                 if (hn >= 1e-7f) {
-                    const float3 xf = to_f3(sg.o);
-                    const PointQ q = point(xf);
+                    const D3 o = origin();
+                    const PointQ q = point(to_f3(o));
                     if (dlog_ndf(q.G, q.s, (1.0f / hn) * h, dG, ds)) {
                         const float c = cs_f[kWpix][lt] * cs_f[kE][lt];
-                        scatter_grad(S, sg.o, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
+                        scatter_grad(S, o, q, 0.0f, c * dG, 0.0f, c * ds, io.grad_off, acc, true);
                     }
                 }
             }

@@ -8,7 +8,7 @@
 
 namespace gpss {
 
-constexpr uint32_t kChunk = 64;   // queue items taken per atomic
+constexpr uint32_t kChunk = 64;   // queue items taken per atomic (default)
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
 
@@ -27,11 +27,12 @@ __device__ __forceinline__ void wave_push(bool want, uint32_t item, uint32_t* __
 // Persistent-wave chunked queue reader.
 // ---------------------------------------------------------------------------
 struct ChunkReader {
-    uint32_t pos, end, n;
+    uint32_t pos, end, n, step;   // step: items per claim (wave-uniform)
     bool exhausted;
-    __device__ __forceinline__ void init(uint32_t n_items) {
+    __device__ __forceinline__ void init(uint32_t n_items, uint32_t items_per_claim = kChunk) {
         pos = end = 0;
         n = n_items;
+        step = items_per_claim;
         exhausted = false;
     }
     // Give each lane with `idle` the index of a queue item (true) while items remain.
@@ -41,11 +42,11 @@ struct ChunkReader {
         while (m && !exhausted) {
             if (pos >= end) {
                 uint32_t base = 0;
-                if ((threadIdx.x & 63) == 0) base = atomicAdd(head, kChunk);
+                if ((threadIdx.x & 63) == 0) base = atomicAdd(head, step);
                 base = __shfl(base, 0, 64);
                 if (base >= n) { exhausted = true; break; }
                 pos = base;
-                end = min(base + kChunk, n);
+                end = min(base + step, n);
             }
             const uint32_t avail = end - pos;
             const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
