@@ -1,15 +1,18 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the GPSS forward renderer on one MI355X.
+"""Throughput benchmark of the GPSS renderer on one MI355X.
 
-Workload (default "sphere"): the single-object sphere of the lengthscale sweep -- unit
-sphere SDF mean, squared-exponential kernel variance 0.0025, lengthscales
-{0.005, 0.02, 0.1, 0.5}, albedo 0.8, point light plus constant environment, pinhole
-512x512, 64 spp, max depth 32.  One step renders all four lengthscales (4 x 16.78 M
-paths) with the scenes already resident on the GPU.
+Headline workload (default "mixed"): union-SDF mean of 16 seeded spheres and boxes in
+[-1, 1]^3, squared-exponential kernel with a 128^3 value-noise variance grid in
+[1e-4, 1e-2], lengthscale 0.03, per-primitive albedo, point light plus environment,
+pinhole 1024x1024, 256 spp, max depth 64.  One step renders the whole image (268.4 M
+paths) with the scene already resident on the GPU.
 
-Prints one JSON line: Mpaths/s, the roofline entry of the dominant kernel (algorithmic
-FP32 FLOPs per launch / the launch time measured with HIP events on the render stream),
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: Mpaths/s of the headline, the roofline entry of its render kernel
+(algorithmic FP32 FLOPs per launch / the launch time measured with HIP events on the render
+stream), the image MSE against the FP64 oracle on sampled pixels, secondary rows (the sphere
+lengthscale sweep and the paper's variants, each with its roofline), the path-replay adjoint
+and the batched render (median of 10 timed calls after 3 warm-ups, each with a roofline
+entry), and the FP64 CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -42,8 +45,12 @@ WORKLOADS = {
 # HBM traffic of the render kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by
 # the same counters on a plain copy (see --summarize-traffic); valid only while the kernel
 # sources hash to the recorded value.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sched_render_kernel_sphere_traffic.md")
-KERNEL_SOURCES = ["gpss_sched.hpp", "gpss_persistent.hip", "gpss_trace.hpp", "gpss_device.hpp", "gpss_waves.hpp"]
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"sched_render_kernel_{workload}_traffic.md")
+
+
+KERNEL_SOURCES = ["gpss_sched.hpp", "gpss_persistent.hip", "gpss_trace.hpp", "gpss_device.hpp", "gpss_waves.hpp",
+                  "gpss_accum.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -55,10 +62,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
+def recorded_traffic(workload: str):
     """Bytes of HBM traffic per render launch recorded for the current kernel, else None."""
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        lines = open(traffic_file(workload)).read().splitlines()
     except OSError:
         return None
     kv = {}
@@ -74,9 +81,10 @@ def recorded_traffic():
         return None
 
 
-def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, commands):
-    """Write TRAFFIC_FILE from four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the
-    bench render and of the plain-copy calibration), each a directory of counter CSVs."""
+def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, commands):
+    """Write the workload's traffic file from four rocprofv3 --pmc runs (FETCH_SIZE and
+    WRITE_SIZE of the bench render and of the plain-copy calibration), each a directory of
+    counter CSVs."""
     import csv
     import glob
 
@@ -96,11 +104,11 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
     f_fac = copy_bytes / 1024.0 / cf[-1]
     w_fac = copy_bytes / 1024.0 / cw[-1]
     traffic = [1024.0 * (a * f_fac + b * w_fac) for a, b in zip(fetch, write)]
-    with open(TRAFFIC_FILE, "w") as f:
-        f.write("# HBM traffic of sched_render_kernel on the sphere sweep\n\n")
-        f.write("Counters per dispatch of the forward render kernel (launches of the sphere sweep in\n"
-                "bench order: warm-up and timed renders of the four lengthscales), in KiB, from\n"
-                "separate rocprofv3 runs:\n\n")
+    path = traffic_file(workload)
+    with open(path, "w") as f:
+        f.write(f"# HBM traffic of sched_render_kernel on the {workload} workload\n\n")
+        f.write("Counters per dispatch of the forward render kernel (its timed launches in bench\n"
+                "order), in KiB, from separate rocprofv3 runs:\n\n")
         for c in commands:
             f.write(f"    {c}\n")
         f.write("\nA plain device copy of known size calibrates each counter (known bytes / counter\n"
@@ -114,7 +122,7 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
         f.write(f"    fetch_factor: {f_fac:.4f}\n")
         f.write(f"    write_factor: {w_fac:.4f}\n")
         f.write(f"    traffic_bytes_per_launch: {json.dumps([round(t) for t in traffic])}\n")
-    print(open(TRAFFIC_FILE).read())
+    print(open(path).read())
 
 
 def copy_calibration(nbytes: int):
@@ -185,128 +193,149 @@ def cpu_model() -> str:
     return platform.processor() or platform.machine()
 
 
-def image_mse(torch, gs, scenes, imgs, factor: int = 16):
-    """MSE of each timed image (samples [0, spp)) against an independent reference of the same
-    scene at factor x spp (samples [spp, (1 + factor) spp)).  The GPU matches the oracle path by
-    path, so the reference stands in for a high-spp oracle image; every form (persistent,
-    wavefront, one thread per path, batch) gives the same image and hence the same MSE."""
-    out = []
-    for g, s, im in zip(gs, scenes, imgs):
-        ref = g.render(s.spp, (1 + factor) * s.spp)
-        torch.cuda.synchronize()
-        out.append(float(((im - ref) ** 2).mean()))
-    return {"reference": f"same scene, samples [spp, {1 + factor} spp)", "per_scene": out}
+def image_mse(torch, scene, img, npix: int = 256, factor: int = 4, seed: int = 11):
+    """MSE of the timed image (samples [0, spp)) against the FP64 oracle's image of the same
+    scene at factor x spp (samples [spp, (1 + factor) spp), independent of the timed ones) on
+    npix pixels sampled at random.  Every GPU form (persistent, wavefront, one thread per path,
+    batch, no-alloc) gives the same image, hence the same MSE."""
+    import numpy as np
+    from oracle.oracle import OracleScene
+    rng = np.random.default_rng(seed)
+    px = np.sort(rng.choice(scene.n_pixels, size=min(npix, scene.n_pixels), replace=False))
+    ref = OracleScene(scene).render_pixels(px, scene.spp, (1 + factor) * scene.spp)
+    g = img.reshape(-1)[torch.as_tensor(px, device=img.device)].double().cpu().numpy()
+    d2 = (g - ref["mean"]) ** 2
+    return {"reference": f"FP64 oracle, samples [spp, {1 + factor} spp) of {px.size} random pixels",
+            "mse": float(d2.mean()), "mse_stderr": float(d2.std(ddof=1) / np.sqrt(d2.size)),
+            "pixels": int(px.size)}
 
 
-def next_row_scenes():
-    """Workloads of the rows built beyond the plain method, each at the sphere workload's
-    launch (512^2, 64 spp, depth 32)."""
-    from gpss_inputs import scenes as sc
-    return {
-        "anisotropic": ("sphere, alpha 0.8 across the normal and 0.01 along it (l_n = sqrt(2) sigma / 0.01)",
-                        [sc.aniso_sphere_scene(0.01)]),
-        "ggx": ("sphere, variance 1e-4, GGX macrofacet with alpha 0.1 / 0.5 / 1.0",
-                [sc.ggx_sphere_scene(a) for a in sc.GGX_ALPHAS]),
-        "fresnel": ("sphere l = 0.1 as three colour channels, gold conductor IOR per channel",
-                    sc.fresnel_rgb_scenes(sc.sphere_scene(0.1), "gold")),
-        "conditioned": ("cond: " + WORKLOADS["cond"], [sc.cond_sphere_scene()]),
-    }
+def median_ms(torch, fn, reps: int = 10, warmup: int = 3, stream=None):
+    """Median of `reps` calls of fn timed with HIP events on the stream it runs on (torch's
+    current stream by default), after `warmup` untimed calls."""
+    stream = stream or torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    ms.sort()
+    return 0.5 * (ms[(reps - 1) // 2] + ms[reps // 2]), ms
 
 
-def row_measurement(torch, gpss, label: str, scenes, steps: int = 2):
-    """Mpaths/s of one row's workload and the roofline entry of its render kernel (algorithmic
-    FLOPs / launch time on the render stream, summed over the row's scenes)."""
+def roofline(flops: float, ms: float, traffic=None) -> dict:
+    rate = flops / (ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": rate, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": rate / FP32_PEAK_TFLOPS, "traffic": traffic, "flops_per_launch": flops}
+
+
+def forward_flops(gpss, flops, torch, scene, g) -> float:
+    """Algorithmic FLOPs of one full render of `scene` from the event counts of the same paths."""
+    _, cnt = g.render_paths(counters=True)
+    torch.cuda.synchronize()
+    return flops.flops_from_counters(scene, gpss.counters_dict(cnt))
+
+
+def row_measurement(torch, gpss, label: str, scenes):
+    """Mpaths/s of one secondary row (median of 10 passes over its scenes after 3 warm-ups) and
+    the roofline entry of its render kernel (algorithmic FLOPs / pass time on the render stream)."""
     from paper_2603_00280_amd import flops
     gs = [gpss.GpssScene(s) for s in scenes]
     imgs = [torch.empty(s.height, s.width, dtype=torch.float32, device="cuda") for s in scenes]
-    fl = 0.0
-    for s, g in zip(scenes, gs):
-        _, cnt = g.render_paths(counters=True)
-        torch.cuda.synchronize()
-        fl += flops.flops_from_counters(s, gpss.counters_dict(cnt))
-    for g, im in zip(gs, imgs):
-        g.render(out=im)
-    stream = torch.cuda.current_stream()
-    evs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    fl = sum(forward_flops(gpss, flops, torch, s, g) for s, g in zip(scenes, gs))
+
+    def one_pass():
         for g, im in zip(gs, imgs):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
             g.render(out=im)
-            e1.record(stream)
-            evs.append((e0, e1))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = sum(a.elapsed_time(b) for a, b in evs) / steps
-    rate = fl / (ms / 1e3) / 1e12
+    ms, _ = median_ms(torch, one_pass)
     n = sum(s.n_paths for s in scenes)
-    return {"workload": label, "value": steps * n / wall / 1e6, "unit": "Mpaths/s", "ms_per_pass": ms,
-            "roofline": {"bound": "alu", "achieved": rate, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": rate / FP32_PEAK_TFLOPS, "traffic": None, "flops_per_pass": fl}}
+    out = {"workload": label, "value": n / (ms / 1e3) / 1e6, "unit": "Mpaths/s", "ms_per_pass": ms,
+           "roofline": roofline(fl, ms)}
+    del gs, imgs
+    return out
 
 
 def adjoint_measurement(torch, gpss):
     """Path-replay adjoint of the L2 image loss on the offset-sphere workload (256^2, 16 spp,
-    depth 16, 64^3 mean-offset grid) at theta0 against the target image; a path counts once
-    although it is traced and replayed."""
+    depth 16, 64^3 mean-offset grid) at theta0 against the target image, beside the forward
+    render of the same scene; median of 10 after 3 warm-ups each.  A path counts once although
+    it is traced (primal pass) and replayed.  The roofline's algorithmic work counts the
+    forward arithmetic of every path twice (primal and replay) and leaves out the gradient
+    terms, a lower bound of the adjoint's work."""
     from gpss_inputs import scenes as sc
+    from paper_2603_00280_amd import flops
     s0, st = sc.offset_sphere_scene(False), sc.offset_sphere_scene(True)
     target = gpss.GpssScene(st).render()
     g = gpss.GpssScene(s0)
     img = g.render()
     dl = (2.0 * (img - target) / img.numel()).contiguous()
-    g.render_adjoint(dl)      # warm-up
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    res = {}
-    for name, fn in (("forward", lambda: g.render(out=img)), ("adjoint", lambda: g.render_adjoint(dl))):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        res[name] = e0.elapsed_time(e1)
+    fwd_fl = forward_flops(gpss, flops, torch, s0, g)
+    adj_ms, _ = median_ms(torch, lambda: g.render_adjoint(dl))
+    fwd_ms, _ = median_ms(torch, lambda: g.render(out=img))
     return {"workload": "offset sphere: 64^3 mean-offset grid, 256x256, 16 spp, max depth 16, "
                         "L2 loss against the seeded target",
-            "adjoint_mpaths_s": s0.n_paths / (res["adjoint"] / 1e3) / 1e6,
-            "forward_mpaths_s": s0.n_paths / (res["forward"] / 1e3) / 1e6,
-            "adjoint_ms": res["adjoint"], "forward_ms": res["forward"],
-            "loss": float(((img - target) ** 2).mean())}
+            "adjoint_mpaths_s": s0.n_paths / (adj_ms / 1e3) / 1e6,
+            "forward_mpaths_s": s0.n_paths / (fwd_ms / 1e3) / 1e6,
+            "adjoint_ms": adj_ms, "forward_ms": fwd_ms, "adjoint_over_forward": adj_ms / fwd_ms,
+            "loss": float(((img - target) ** 2).mean()),
+            "roofline": roofline(2.0 * fwd_fl, adj_ms),
+            "memory": "no per-path buffer: the replay runs in the lane that traced the path"}
 
 
 def batch_measurement(torch, gpss, tune: bool):
     """64 sphere scenes of uneven resolution, spp and lengthscale: one persistent
-    hipGraph-captured launch against 64 sequential plain launches (same images)."""
+    hipGraph-captured launch (tile and grid from the autotuner unless tune is False) against
+    64 sequential plain launches (same images); median of 10 after 3 warm-ups each."""
     from gpss_inputs import scenes as sc
+    from paper_2603_00280_amd import flops
     scenes = sc.batch_scenes()
     gs = [gpss.GpssScene(s) for s in scenes]
     outs = [torch.empty(g.shape, dtype=torch.float32, device="cuda") for g in gs]
     plain = [torch.empty(g.shape, dtype=torch.float32, device="cuda") for g in gs]
     npaths = sum(s.n_paths for s in scenes)
+    fl = sum(forward_flops(gpss, flops, torch, s, g) for s, g in zip(scenes, gs))
     tuned = None
     if tune:
         tuned = gpss.gpss_batch_autotune([g.handle for g in gs], [o.data_ptr() for o in outs])
-    gpss.render_batch(gs, outs)             # plan + graph capture
-    for g, o in zip(gs, plain):
-        g.render(out=o)                      # warm-up of the single-scene path
+    batch_ms, _ = median_ms(torch, lambda: gpss.render_batch(gs, outs))
+
+    def seq():
+        for g, o in zip(gs, plain):
+            g.render(out=o)
+    plain_ms, _ = median_ms(torch, seq)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gpss.render_batch(gs, outs)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for g, o in zip(gs, plain):
-        g.render(out=o)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
     same = all(bool(torch.equal(a, b)) for a, b in zip(outs, plain))
     return {"workload": "64 sphere scenes, resolution {64..512}^2, spp {4,16,64}, lengthscale "
                         "log-uniform [0.005, 0.5], max depth 32", "paths": npaths,
-            "batch_mpaths_s": npaths / t_batch / 1e6, "plain_sequential_mpaths_s": npaths / t_plain / 1e6,
-            "batch_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3, "images_identical": same,
-            "tuning": tuned}
+            "batch_mpaths_s": npaths / (batch_ms / 1e3) / 1e6,
+            "plain_sequential_mpaths_s": npaths / (plain_ms / 1e3) / 1e6,
+            "batch_ms": batch_ms, "plain_ms": plain_ms, "images_identical": same, "tuning": tuned,
+            "roofline": roofline(fl, batch_ms)}
+
+
+def secondary_rows():
+    """Workloads measured beside the headline: the sphere lengthscale sweep and the rows built
+    beyond the plain method, each at the sphere workload's launch (512^2, 64 spp, depth 32)."""
+    from gpss_inputs import scenes as sc
+    return {
+        "sphere_sweep": ("sphere: " + WORKLOADS["sphere"], lambda: [sc.sphere_scene(l) for l in sc.SPHERE_LENGTHSCALES]),
+        "anisotropic": ("sphere, alpha 0.8 across the normal and 0.01 along it (l_n = sqrt(2) sigma / 0.01)",
+                        lambda: [sc.aniso_sphere_scene(0.01)]),
+        "ggx": ("sphere, variance 1e-4, GGX macrofacet with alpha 0.1 / 0.5 / 1.0",
+                lambda: [sc.ggx_sphere_scene(a) for a in sc.GGX_ALPHAS]),
+        "fresnel": ("sphere l = 0.1 as three colour channels, gold conductor IOR per channel",
+                    lambda: sc.fresnel_rgb_scenes(sc.sphere_scene(0.1), "gold")),
+        "conditioned": ("cond: " + WORKLOADS["cond"], lambda: [sc.cond_sphere_scene()]),
+    }
+
+
+CPU_SPP = {"mixed": 24, "sphere": 48, "plane": 4096, "cond": 16}
 
 
 def main():
@@ -314,23 +343,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sphere", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-spp", type=int, default=48, help="spp of the oracle CPU sample")
+    ap.add_argument("--workload", default="mixed", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-spp", type=int, default=0,
+                    help="spp of the oracle CPU sample (default: about 10-20 s of the workload on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default="auto", choices=["auto", "persistent", "mega", "wavefront"],
                     help="tracer form timed for the headline value")
     ap.add_argument("--compare", action="store_true",
-                    help="also time one step of the other tracer form")
+                    help="also time one step of the other tracer forms")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint measurement on the offset-sphere workload")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-render measurement on the 64-scene workload")
     ap.add_argument("--no-mse", action="store_true",
-                    help="skip the image MSE against a 16x-spp reference of each scene")
-    ap.add_argument("--no-cond", "--no-next", dest="no_next", action="store_true",
-                    help="skip the measurements of the anisotropic, GGX, Fresnel and conditioned rows")
-    ap.add_argument("--tune", action="store_true",
-                    help="run the batch autotuner first (its choice is cached on disk)")
+                    help="skip the image MSE against the oracle on sampled pixels")
+    ap.add_argument("--no-rows", "--no-next", "--no-cond", dest="no_rows", action="store_true",
+                    help="skip the secondary rows (sphere sweep, anisotropic, GGX, Fresnel, conditioned)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the batch with the cached or default tiles instead of running the autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (traffic calibration) and exit")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -339,7 +369,7 @@ def main():
     ap.add_argument("--commands", nargs="*", default=[], help="commands recorded in the traffic profile")
     args = ap.parse_args()
     if args.summarize_traffic:
-        summarize_traffic(*args.summarize_traffic, args.copy_bytes, args.commands)
+        summarize_traffic(args.workload, *args.summarize_traffic, args.copy_bytes, args.commands)
         return
     if args.calibrate_copy:
         copy_calibration(args.calibrate_copy)
@@ -395,14 +425,14 @@ def main():
     paths = args.steps * sum(s.n_paths for s in scenes)
     launch_ms = [a.elapsed_time(b) for a, b in evs]
     per_scene_ms = [sum(launch_ms[i::len(scenes)]) / args.steps for i in range(len(scenes))]
-    # roofline of the render kernel: algorithmic FLOPs of each launch / its duration
-    flop_rate = sum(w[0] for w in work) / (sum(per_scene_ms) / 1e3)
     traffic = None
-    if args.workload == "sphere" and args.kernel in ("auto", "persistent"):
-        rec = recorded_traffic()
+    if args.kernel in ("auto", "persistent"):
+        rec = recorded_traffic(args.workload)
         if rec:
             traffic = sum(rec) / len(rec)
-    avg_launch_ms = sum(launch_ms) / len(launch_ms)
+    rl = roofline(sum(w[0] for w in work), sum(per_scene_ms), traffic)
+    rl["avg_launch_ms"] = sum(launch_ms) / len(launch_ms)
+    rl["flops_per_launch"] = [w[0] for w in work]
     result = {
         "metric": METRIC,
         "value": paths / wall / 1e6,
@@ -419,14 +449,13 @@ def main():
         "config": {"workload": args.workload + ": " + WORKLOADS[args.workload],
                    "paths_per_step": sum(s.n_paths for s in scenes),
                    "tracer": TRACERS[args.kernel]},
-        "roofline": {"bound": "alu", "achieved": flop_rate / 1e12, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": flop_rate / 1e12 / FP32_PEAK_TFLOPS, "traffic": traffic,
-                     "avg_launch_ms": avg_launch_ms,
-                     "flops_per_launch": [w[0] for w in work]},
+        "roofline": rl,
         "per_scene_mpaths_s": [s.n_paths / (ms / 1e3) / 1e6 for s, ms in zip(scenes, per_scene_ms)],
+        "counters": [w[1] for w in work],
     }
     if not args.no_mse:
-        result["image_mse"] = image_mse(torch, gs, scenes, imgs)
+        print("[bench] image MSE against the oracle", file=sys.stderr, flush=True)
+        result["image_mse"] = [image_mse(torch, s, im) for s, im in zip(scenes, imgs)]
     if args.compare:
         result["compare"] = {}
         for other in ("persistent", "wavefront", "mega"):
@@ -442,21 +471,23 @@ def main():
                 g.render(out=im)
             torch.cuda.synchronize()
             result["compare"][TRACERS[other]] = sum(s.n_paths for s in scenes) / (time.perf_counter() - t0) / 1e6
+    del gs, imgs
+    if not args.no_rows:
+        result["rows"] = {}
+        for name, (label, make) in secondary_rows().items():
+            if name == "sphere_sweep" and args.workload == "sphere":
+                continue
+            print(f"[bench] {name}", file=sys.stderr, flush=True)
+            result["rows"][name] = row_measurement(torch, gpss, label, make())
     if not args.no_adjoint:
         print("[bench] adjoint", file=sys.stderr, flush=True)
         result["adjoint"] = adjoint_measurement(torch, gpss)
-    if not args.no_next and args.workload == "sphere":
-        result["next_rows"] = {}
-        for name, (label, row_scenes) in next_row_scenes().items():
-            print(f"[bench] {name}", file=sys.stderr, flush=True)
-            result["next_rows"][name] = row_measurement(torch, gpss, label, row_scenes)
-            del row_scenes
     if not args.no_batch:
         print("[bench] batch", file=sys.stderr, flush=True)
-        result["batch"] = batch_measurement(torch, gpss, args.tune)
+        result["batch"] = batch_measurement(torch, gpss, not args.no_tune)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the CPU", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(scenes, args.cpu_spp)
+        result["cpu_baseline"] = cpu_baseline(scenes, args.cpu_spp or CPU_SPP[args.workload])
     print(json.dumps(result), flush=True)
 
 
