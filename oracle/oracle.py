@@ -15,7 +15,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# the sanitized build (oracle/build.py) when GPSS_SANITIZED is "oracle"
+LIB_PATH = os.path.join(HERE, "liboracle_san.so" if os.environ.get("GPSS_SANITIZED") == "oracle" else "liboracle.so")
 
 C_TRACK_STEPS, C_REAL, C_NEE_STEPS, C_VIOLATIONS, C_CAPPED, C_ESCAPED, C_TRUNCATED, \
     C_CELLS, C_PHASE, C_NEE = range(10)
@@ -50,7 +51,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             from . import build as _b  # noqa
-            _b.build()
+            _b.build(sanitize=LIB_PATH.endswith("_san.so"))
         L = C.CDLL(LIB_PATH)
         dp = C.POINTER(C.c_double)
         L.oracle_scene_create.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_void_p)]

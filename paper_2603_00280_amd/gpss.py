@@ -13,7 +13,8 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgpss.so")
+# the host-sanitized build (build.py) when GPSS_SANITIZED is "abi"
+LIB_PATH = os.path.join(HERE, "libgpss_san.so" if os.environ.get("GPSS_SANITIZED") == "abi" else "libgpss.so")
 
 GPSS_OK = 0
 GPSS_ERR_INVALID_ARG = -1

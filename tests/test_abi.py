@@ -114,3 +114,19 @@ def test_invalid_observations_are_rejected():
                dict(lengthscale_n=0.05), dict(offset_grid=np.zeros((2, 2, 2), np.float32))):
         rc, msg = _create(s.replace(**kw))
         assert rc == gpss.GPSS_ERR_UNSUPPORTED and "conditioning" in msg
+
+
+def test_sanitized_builds_are_the_ones_loaded():
+    """Under tests/run_sanitized.sh (GPSS_SANITIZED set): the sanitized library of the pass is
+    the one loaded, and the process runs an AddressSanitizer runtime."""
+    mode = os.environ.get("GPSS_SANITIZED")
+    if mode not in ("abi", "oracle"):
+        pytest.skip("plain builds (tests/run_sanitized.sh runs the suite against the sanitized ones)")
+    if mode == "abi":
+        assert gpss.LIB_PATH.endswith("libgpss_san.so")
+        gpss.lib()
+    else:
+        from oracle import oracle as orc
+        assert orc.LIB_PATH.endswith("liboracle_san.so")
+        orc.lib()
+    assert hasattr(ctypes.CDLL(None), "__asan_init")
