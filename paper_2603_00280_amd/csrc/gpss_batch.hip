@@ -65,7 +65,10 @@ struct TileSource {
 };
 
 // Persistent waves take tiles from a global cursor (one atomic per tile) and trace each
-// tile's paths with the scheduled loop; the scene record is wave-uniform.
+// tile's paths with the scheduled loop; the scene record is wave-uniform.  MED: the medium
+// kind every scene of the batch shares (that loop only), or kMedAny (the loop specialized for
+// each tile's scene, all three compiled in, which costs registers).
+template <int MED>
 __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const BatchScene* __restrict__ scenes,
                                                                          const Tile* __restrict__ tiles, uint32_t ntiles,
                                                                          uint32_t* cursor,
@@ -90,10 +93,14 @@ __global__ __launch_bounds__(256, GPSS_SCHED_MIN_WAVES) void batch_kernel(const 
         const AdjointIo io{};
         GradAcc gacc{0.0f, 0.0f, 0.0f};
         // the same specialization per medium as the single-scene kernel (identical images)
-        const int med = medium_of(S);
-        if (med == kMedGgx) run_scheduled<false, false, kMedGgx>(S, src, out, st, io, gacc, lds);
-        else if (med == kMedAniso) run_scheduled<false, false, kMedAniso>(S, src, out, st, io, gacc, lds);
-        else run_scheduled<false, false, kMedIso>(S, src, out, st, io, gacc, lds);
+        if constexpr (MED != kMedAny) {
+            run_scheduled<false, false, MED>(S, src, out, st, io, gacc, lds);
+        } else {
+            const int med = medium_of(S);
+            if (med == kMedGgx) run_scheduled<false, false, kMedGgx>(S, src, out, st, io, gacc, lds);
+            else if (med == kMedAniso) run_scheduled<false, false, kMedAniso>(S, src, out, st, io, gacc, lds);
+            else run_scheduled<false, false, kMedIso>(S, src, out, st, io, gacc, lds);
+        }
     }
 }
 
@@ -144,6 +151,7 @@ struct BatchPlan {
     int ring = 0;
     unsigned long long* d_acc = nullptr;   // fixed-point sums, two words per pixel of the batch
     uint64_t total_paths = 0, total_pix = 0;
+    int med = kMedAny;                  // batch_kernel instance in the captured graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -296,8 +304,12 @@ static int capture_graph(BatchPlan* P) {
         const uint64_t nw = 2 * P->total_pix;
         hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, cs, P->d_cursor);
         hipLaunchKernelGGL(batch_clear_kernel, dim3((uint32_t)((nw + 255) / 256)), dim3(256), 0, cs, P->d_acc, nw);
-        hipLaunchKernelGGL(batch_kernel, dim3(P->grid), dim3(256), 0, cs, P->d_scenes, P->d_tiles, P->ntiles,
-                           P->d_cursor, P->d_acc);
+        auto kernel = P->med == kMedIso     ? batch_kernel<kMedIso>
+                      : P->med == kMedGgx   ? batch_kernel<kMedGgx>
+                      : P->med == kMedAniso ? batch_kernel<kMedAniso>
+                                            : batch_kernel<kMedAny>;
+        hipLaunchKernelGGL(kernel, dim3(P->grid), dim3(256), 0, cs, P->d_scenes, P->d_tiles, P->ntiles, P->d_cursor,
+                           P->d_acc);
         hipLaunchKernelGGL(batch_image_kernel, dim3((uint32_t)((P->total_pix + 255) / 256)), dim3(256), 0, cs,
                            P->d_scenes, (uint32_t)P->scenes.size(), P->d_images, P->d_acc, P->total_pix);
         hipGraph_t g = nullptr;
@@ -346,6 +358,19 @@ static int run_plan(BatchPlan* P, float* const* images, hipStream_t stream) {
         if (rc) return rc;
         P->images_set.assign(images, images + n);
     }
+    // the medium kind the scenes share now (parameter changes can change it): the graph is
+    // captured again when it launches another batch_kernel instance
+    int med = medium_of(P->scenes[0]->dev);
+    for (uint32_t i = 1; i < n && med != kMedAny; ++i)
+        if (medium_of(P->scenes[i]->dev) != med) med = kMedAny;
+    if (P->exec && med != P->med) {
+        rc = check_hip(hipGraphExecDestroy(P->exec), "hipGraphExecDestroy");
+        if (!rc) rc = check_hip(hipGraphDestroy(P->graph), "hipGraphDestroy");
+        P->exec = nullptr;
+        P->graph = nullptr;
+        if (rc) return rc;
+    }
+    P->med = med;
     if (!P->exec) rc = capture_graph(P);
     if (!rc) rc = check_hip(hipGraphLaunch(P->exec, stream), "hipGraphLaunch");
     return rc;

@@ -24,8 +24,13 @@ constexpr int kGradCacheLanes = 256;
 // only when a slot changes cell, and once at the end, into the workgroup table below.  Slot
 // 0 follows the vertices, slot 1 the tentative collisions; a cell is held by at most one
 // slot.  Indexed [slot][corner][threadIdx.x]: consecutive threads hit consecutive banks.
-__device__ __forceinline__ float (&grad_cache())[2][8][kGradCacheLanes] {
-    __shared__ float cache[2][8][kGradCacheLanes];
+#ifndef GPSS_GRAD_SLOTS
+#define GPSS_GRAD_SLOTS 2
+#endif
+constexpr int kGradSlots = GPSS_GRAD_SLOTS;
+static_assert(kGradSlots == 1 || kGradSlots == 2, "one or two cached cells per thread");
+__device__ __forceinline__ float (&grad_cache())[kGradSlots][8][kGradCacheLanes] {
+    __shared__ float cache[kGradSlots][8][kGradCacheLanes];
     return cache;
 }
 
@@ -36,8 +41,11 @@ __device__ __forceinline__ float (&grad_cache())[2][8][kGradCacheLanes] {
 // (node + 1, float bits of its sum) in 64 bits (0: empty) and changes by compare-and-swap
 // only, so every value is added exactly once: either into the entry, or by the lane whose
 // swap evicted it, or (after kGradTableTries failed swaps under contention) directly.
-constexpr int kGradTableLog2 = 10;
-constexpr int kGradTable = 1 << kGradTableLog2;   // 8 KiB of LDS per workgroup
+#ifndef GPSS_GRAD_TABLE_LOG2
+#define GPSS_GRAD_TABLE_LOG2 10
+#endif
+constexpr int kGradTableLog2 = GPSS_GRAD_TABLE_LOG2;
+constexpr int kGradTable = 1 << kGradTableLog2;   // 8 bytes of LDS per entry
 constexpr int kGradTableTries = 4;
 
 __device__ __forceinline__ unsigned long long* grad_table() {
@@ -99,7 +107,7 @@ __device__ __forceinline__ void flush_grad_slot(const SceneDev& S, float* __rest
                                                 int k) {
     const int cell = k ? acc.cell1 : acc.cell0;
     if (cell < 0) return;
-    float (&cache)[2][8][kGradCacheLanes] = grad_cache();
+    float (&cache)[kGradSlots][8][kGradCacheLanes] = grad_cache();
     const int t = threadIdx.x;
     const int sy = S.off_res[0], sz = S.off_res[0] * S.off_res[1];
     int node[8];
@@ -108,7 +116,7 @@ __device__ __forceinline__ void flush_grad_slot(const SceneDev& S, float* __rest
     for (int n = 0; n < 8; ++n) {
         const int dx = n & 1, dy = (n >> 1) & 1, dz = n >> 2;
         node[n] = cell + dx + dy * sy + dz * sz;
-        val[n] = cache[k][n][t];
+        val[n] = cache[kGradSlots == 1 ? 0 : k][n][t];
     }
     grad_table_add8(grad_off, node, val);
     if (k) acc.cell1 = -1;
@@ -118,7 +126,7 @@ __device__ __forceinline__ void flush_grad_slot(const SceneDev& S, float* __rest
 // Move both cached cells into the workgroup table (at the end of the thread's work).
 __device__ __forceinline__ void flush_grad_cell(const SceneDev& S, float* __restrict__ grad_off, GradAcc& acc) {
     flush_grad_slot(S, grad_off, acc, 0);
-    flush_grad_slot(S, grad_off, acc, 1);
+    if (kGradSlots > 1) flush_grad_slot(S, grad_off, acc, 1);
 }
 
 // d log rho = dmu * dmu_coef + dsigma * dsig_coef,  rho = phi(z)/(sigma Phi(z)), z = mu/sigma:
@@ -229,14 +237,14 @@ __device__ __forceinline__ void scatter_grad(const SceneDev& S, D3 x, const Poin
                                              bool vertex) {
     if (S.offset && grad_off) {
         const TriCell c = tri_cell_d(S.off_res, S.off_scale_d, S.lo_d, x);
-        const bool same = c.base == acc.cell0 || c.base == acc.cell1;
-        const int k = c.base == acc.cell0 ? 0 : (c.base == acc.cell1 ? 1 : (vertex ? 0 : 1));
+        const bool same = c.base == acc.cell0 || (kGradSlots > 1 && c.base == acc.cell1);
+        const int k = kGradSlots == 1 ? 0 : (c.base == acc.cell0 ? 0 : (c.base == acc.cell1 ? 1 : (vertex ? 0 : 1)));
         if (!same) {
             flush_grad_slot(S, grad_off, acc, k);
             if (k) acc.cell1 = c.base;
             else acc.cell0 = c.base;
         }
-        float (&cache)[2][8][kGradCacheLanes] = grad_cache();
+        float (&cache)[kGradSlots][8][kGradCacheLanes] = grad_cache();
         const int t = threadIdx.x;
         const float fx = c.fx, fy = c.fy, fz = c.fz;
         const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;

@@ -136,6 +136,7 @@ struct AccTable {
     uint32_t px[kSchedWaves][kAccTable];   // pixel + 1 of the entry, 0 = empty
 };
 
+struct NoAccTable {};
 template <bool ADJ>
 struct SchedLds {
     uint32_t u[3][kSchedBlock];                     // output slot, pixel, sample
@@ -143,7 +144,7 @@ struct SchedLds {
     double d[3][kSchedBlock];                       // direction of the next track segment
     double o[3][kSchedBlock];                       // origin of the current segment
     double sd[3][kSchedBlock];                      // direction of the current segment
-    AccTable acc;                                   // forward form with a pixel accumulator
+    typename std::conditional<ADJ, NoAccTable, AccTable>::type acc;   // forward form's pixel table
 };
 
 template <bool STATS, bool ADJ, int MED, class Source>
@@ -158,7 +159,9 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
     const int lt = threadIdx.x;
     const int lane = lt & 63, wv = lt >> 6;
     const bool accumulate = !ADJ && !out.paths;   // wave-uniform
-    if (accumulate && lane < kAccTable) lds.acc.px[wv][lane] = 0u;
+    AccTable* tab = nullptr;   // the forward form's pixel table (the adjoint's LDS has none)
+    if constexpr (!ADJ) tab = &lds.acc;
+    if (accumulate && lane < kAccTable) tab->px[wv][lane] = 0u;
     enum { kSlot = 0, kPixel = 1, kSample = 2 };
     // forward: kL = radiance so far.  Adjoint: kL + kLlo = radiance so far (primal pass), then
     // the remaining radiance L_rem (replay), kept as a two-float sum (ff_add) so that L_rem
@@ -247,13 +250,13 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
     };
     // add one entry of the pixel table to the global accumulator and empty it (lane-local)
     auto flush_entry = [&](int e) {
-        const uint32_t p1 = lds.acc.px[wv][e];
+        const uint32_t p1 = tab->px[wv][e];
         if (p1 == 0u) return;
         unsigned long long* w = out.acc + 2ull * (p1 - 1u);
-        const unsigned long long lo = lds.acc.lo[wv][e], hi = lds.acc.hi[wv][e];
+        const unsigned long long lo = tab->lo[wv][e], hi = tab->hi[wv][e];
         if (lo) atomicAdd(w, lo);
         if (hi) atomicAdd(w + 1, hi);
-        lds.acc.px[wv][e] = 0u;
+        tab->px[wv][e] = 0u;
     };
     // a track segment left the medium: the environment it sees ends the path
     auto escape = [&]() {
@@ -281,17 +284,17 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
                 const int leader = __builtin_ctzll(mOut);
                 const uint32_t P = __shfl(cs_u[kPixel][lt], leader, 64);
                 const int e = (int)(P % (uint32_t)kAccTable);
-                if (lane == leader && lds.acc.px[wv][e] != P + 1u) {
+                if (lane == leader && tab->px[wv][e] != P + 1u) {
                     flush_entry(e);
-                    lds.acc.lo[wv][e] = 0ull;
-                    lds.acc.hi[wv][e] = 0ull;
-                    lds.acc.px[wv][e] = P + 1u;
+                    tab->lo[wv][e] = 0ull;
+                    tab->hi[wv][e] = 0ull;
+                    tab->px[wv][e] = P + 1u;
                 }
                 const bool mine = op == kOpOut && cs_u[kPixel][lt] == P;
                 if (mine) {
                     const uint64_t v = acc_fixed(cs_f[kL][lt]);
-                    if (v & 0xFFFFFFFFull) atomicAdd(&lds.acc.lo[wv][e], (unsigned long long)(v & 0xFFFFFFFFull));
-                    if (v >> 32) atomicAdd(&lds.acc.hi[wv][e], (unsigned long long)(v >> 32));
+                    if (v & 0xFFFFFFFFull) atomicAdd(&tab->lo[wv][e], (unsigned long long)(v & 0xFFFFFFFFull));
+                    if (v >> 32) atomicAdd(&tab->hi[wv][e], (unsigned long long)(v >> 32));
                     op = kOpIdle;
                 }
                 mOut &= ~__ballot(mine);
