@@ -125,6 +125,139 @@ def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write
     print(open(path).read())
 
 
+def _csv_rows(d, pattern):
+    import csv
+    import glob
+    out = []
+    for f in sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True)):
+        out += list(csv.DictReader(open(f)))
+    return out
+
+
+def summarize_trace(workload, kt_dir, bench_json, commands):
+    """Write profiles/sched_render_kernel_<workload>.md from a rocprofv3 --kernel-trace --stats
+    run of bench.py: the per-kernel summary of the whole run, and the headline render's launches
+    (the dispatches of the default render kernel longer than half its longest) against the
+    launch time bench.py measured with HIP events in the same run."""
+    stats = _csv_rows(kt_dir, "*kernel_stats.csv")
+    trace = _csv_rows(kt_dir, "*kernel_trace.csv")
+    res = json.loads([ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1])
+    kern = "sched_render_kernel<false, 0>"
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in trace if kern in r["Kernel_Name"]]
+    top = max(durs)
+    head = [d for d in durs if d > 0.5 * top]
+    path = os.path.join(ROOT, "profiles", f"sched_render_kernel_{workload}.md")
+    with open(path, "w") as f:
+        f.write(f"# sched_render_kernel<false, 0> on the {workload} workload: kernel trace of the default bench run\n\n")
+        f.write("Command (repo root):\n\n")
+        for c in commands:
+            f.write(f"    {c}\n")
+        f.write(f"\nWorkload: {res['config']['workload']}.\n\n")
+        f.write(f"Headline render launches (warm-up and timed, {len(head)} dispatches of `{kern}` longer than "
+                f"half the longest):\n\n")
+        f.write("    " + ", ".join(f"{d:.2f}" for d in head) + " ms\n")
+        f.write(f"    kernel-trace average: {sum(head) / len(head):.2f} ms\n")
+        f.write(f"    bench.py HIP-event average over its timed launches (same run): "
+                f"{res['roofline']['avg_launch_ms']:.2f} ms (clear, render, finalize)\n")
+        f.write(f"    value: {res['value']:.1f} {res['unit']}, roofline frac {100 * res['roofline']['frac']:.2f} % "
+                f"of {res['roofline']['peak']} {res['roofline']['unit']}\n\n")
+        f.write("Whole run, kernels by total time:\n\n")
+        f.write("| Kernel | Calls | Total (ms) | Average (ms) | Max (ms) | % |\n|---|--:|--:|--:|--:|--:|\n")
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
+            name = r["Name"].split("(")[0].replace("void ", "")
+            f.write(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                    f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |\n")
+    print(open(path).read())
+
+
+def summarize_counters(workload, dirs, kt_dir, commands):
+    """Write profiles/sched_render_kernel_<workload>_counters.md from rocprofv3 --pmc runs of
+    bench.py (SQ counters, any split over the runs) and the kernel trace of the default run
+    (for launch times): the headline render (the longest dispatch of the default render
+    kernel), the adjoint's forward render (the other dispatches of that kernel, median), the
+    adjoint and the batch kernel (medians)."""
+    import statistics
+    per = {}
+    for d in dirs:
+        for r in _csv_rows(d, "*counter_collection.csv"):
+            key = (d, int(r["Dispatch_Id"]))
+            e = per.setdefault(key, {"kernel": r["Kernel_Name"]})
+            e[r["Counter_Name"]] = float(r["Counter_Value"])
+    groups = {"headline render": [], "adjoint's forward render": [], "adjoint": [], "batch": []}
+    for d in dirs:
+        mine = sorted(((k[1], v) for k, v in per.items() if k[0] == d), key=lambda kv: kv[0])
+        fwd = [(i, v) for i, v in mine if "sched_render_kernel<false, 0>" in v["kernel"]]
+        adj = [i for i, v in mine if "sched_adjoint_kernel" in v["kernel"]]
+        bat = [i for i, v in mine if "batch_kernel" in v["kernel"]]
+        if fwd:
+            groups["headline render"].append(max((v for _, v in fwd), key=lambda v: v.get("SQ_INSTS_VALU", 0.0)))
+        if adj:
+            # bench.py times the adjoint's forward render right after the adjoint, before the batch
+            hi = min(bat) if bat else float("inf")
+            groups["adjoint's forward render"] += [v for i, v in fwd if max(adj) < i < hi]
+        groups["adjoint"] += [v for i, v in mine if i in adj]
+        groups["batch"] += [v for i, v in mine if i in bat]
+    trace = _csv_rows(kt_dir, "*kernel_trace.csv")
+
+    def durs(pat):
+        return sorted((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in trace if pat in r["Kernel_Name"])
+    fwd_d = durs("sched_render_kernel<false, 0>")
+    times = {"headline render": fwd_d[-1] if fwd_d else None, "adjoint's forward render": None,
+             "adjoint": None, "batch": None}
+    # the adjoint's forward render: the default render kernel's dispatches between the last
+    # adjoint dispatch and the first batch dispatch of the traced run
+    order = sorted(trace, key=lambda r: int(r["Dispatch_Id"]))
+    ai = [int(r["Dispatch_Id"]) for r in order if "sched_adjoint_kernel" in r["Kernel_Name"]]
+    bi = [int(r["Dispatch_Id"]) for r in order if "batch_kernel" in r["Kernel_Name"]]
+    if ai:
+        hi = min(bi) if bi else float("inf")
+        fd = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in order
+              if "sched_render_kernel<false, 0>" in r["Kernel_Name"] and max(ai) < int(r["Dispatch_Id"]) < hi]
+        times["adjoint's forward render"] = statistics.median(fd) if fd else None
+    adj_d, bat_d = durs("sched_adjoint_kernel"), durs("batch_kernel")
+    times["adjoint"] = statistics.median(adj_d) if adj_d else None
+    times["batch"] = statistics.median(bat_d) if bat_d else None
+
+    def med(vs, c):
+        xs = [v[c] for v in vs if c in v]
+        return statistics.median(xs) if xs else float("nan")
+    path = os.path.join(ROOT, "profiles", f"sched_render_kernel_{workload}_counters.md")
+    with open(path, "w") as f:
+        f.write(f"# Scheduled tracer kernels on the {workload} workload, the adjoint and the batch: SQ counters\n\n")
+        f.write("Commands (repo root; counter passes within the per-block limits, and the kernel trace of the\n"
+                "default bench run for launch times):\n\n")
+        for c in commands:
+            f.write(f"    {c}\n")
+        f.write("\nPer dispatch (medians over a group's dispatches).  The FP32 FLOP instruction counter counts\n"
+                "per wave instruction (FMA as 2); times 64 lanes it gives the issued FP32 rate, masked lanes\n"
+                "included.  Lane utilization = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU).  VALU busy =\n"
+                "VALU wave instructions x 4 cycles / (1024 SIMDs x 2.4 GHz x launch time).\n\n")
+        f.write("| Kernel (group) | Launch (ms) | VALU instr. | lane util. | VALU busy | FP32 FLOP instr. x 64 "
+                "(TFLOP/s) | FP64 FLOP instr. | SALU instr. | LDS instr. | vector loads | scalar loads | "
+                "waits / wave cycles | waves |\n")
+        f.write("|---|--:|--:|--:|--:|--:|--:|--:|--:|--:|--:|--:|--:|\n")
+        for g, vs in groups.items():
+            if not vs:
+                continue
+            valu = med(vs, "SQ_INSTS_VALU")
+            lu = med(vs, "SQ_THREAD_CYCLES_VALU") / (64.0 * med(vs, "SQ_ACTIVE_INST_VALU"))
+            t = times[g]
+            fp32 = med(vs, "SQ_INSTS_VALU_FLOPS_FP32") * 64.0
+            busy = f"{100 * valu * 4 / (1024 * 2.4e9 * t / 1e3):.0f} %" if t else "-"
+            rate = f"{fp32 / (t / 1e3) / 1e12:.2f}" if t else "-"
+            f.write(f"| {g} | {t:.2f} | {valu:.3g} | {100 * lu:.1f} % | {busy} | {rate} | "
+                    f"{med(vs, 'SQ_INSTS_VALU_FLOPS_FP64'):.3g} | {med(vs, 'SQ_INSTS_SALU'):.3g} | "
+                    f"{med(vs, 'SQ_INSTS_LDS'):.3g} | {med(vs, 'SQ_INSTS_VMEM_RD'):.3g} | "
+                    f"{med(vs, 'SQ_INSTS_SMEM'):.3g} | "
+                    f"{med(vs, 'SQ_WAIT_INST_ANY') / med(vs, 'SQ_WAVE_CYCLES'):.2f} | {med(vs, 'SQ_WAVES'):.0f} |\n"
+                    if t else
+                    f"| {g} | - | {valu:.3g} | {100 * lu:.1f} % | - | - | {med(vs, 'SQ_INSTS_VALU_FLOPS_FP64'):.3g} | "
+                    f"{med(vs, 'SQ_INSTS_SALU'):.3g} | {med(vs, 'SQ_INSTS_LDS'):.3g} | {med(vs, 'SQ_INSTS_VMEM_RD'):.3g} | "
+                    f"{med(vs, 'SQ_INSTS_SMEM'):.3g} | "
+                    f"{med(vs, 'SQ_WAIT_INST_ANY') / med(vs, 'SQ_WAVE_CYCLES'):.2f} | {med(vs, 'SQ_WAVES'):.0f} |\n")
+    print(open(path).read())
+
+
 def copy_calibration(nbytes: int):
     """One plain device-to-device copy of nbytes (the calibration kernel of the traffic runs)."""
     import torch
@@ -365,11 +498,22 @@ def main():
                     help="only run one plain device copy of BYTES (traffic calibration) and exit")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic profile from four rocprofv3 --pmc output directories and exit")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("KERNEL_TRACE_DIR", "BENCH_JSON"),
+                    help="write the kernel-trace profile of a rocprofv3 --kernel-trace --stats bench run and exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="write the SQ-counter profile from rocprofv3 --pmc output directories; the last "
+                         "directory is the kernel trace of the default run (launch times); then exit")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
-    ap.add_argument("--commands", nargs="*", default=[], help="commands recorded in the traffic profile")
+    ap.add_argument("--commands", nargs="*", default=[], help="commands recorded in a profile summary")
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(args.workload, *args.summarize_traffic, args.copy_bytes, args.commands)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.workload, *args.summarize_trace, args.commands)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.workload, args.summarize_counters[:-1], args.summarize_counters[-1], args.commands)
         return
     if args.calibrate_copy:
         copy_calibration(args.calibrate_copy)

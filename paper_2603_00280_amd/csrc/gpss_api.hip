@@ -381,14 +381,20 @@ float aniso_k(const gpss_scene_desc& D) {
     return r * r - 1.0f;
 }
 
-// Scheduling policy from the largest gradient spread sigma / l of the scene (the variance
-// grid's largest node, the shorter of the two lengthscales).
+// Scheduling policy from the scene's typical gradient spread sigma / l: the variance, or the
+// median node of the variance grid (where most of a grid's medium is; its largest node picked
+// the rough policy for the 1024^2 mixed scene, 4 % slower there than the smooth one), over the
+// shorter of the two lengthscales.
 void set_policy(gpss_scene* s) {
     const gpss_scene_desc& D = s->desc;
-    float vmax = D.variance;
-    if (!s->var_h.empty()) vmax = *std::max_element(s->var_h.begin(), s->var_h.end());
+    float v = D.variance;
+    if (!s->var_h.empty()) {
+        std::vector<float> t(s->var_h);
+        std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+        v = t[t.size() / 2];
+    }
     const float l = D.lengthscale_n > 0.0f ? std::min(D.lengthscale, D.lengthscale_n) : D.lengthscale;
-    const gpss::SchedPolicy p = gpss::sched_policy(std::sqrt(vmax) / l);
+    const gpss::SchedPolicy p = gpss::sched_policy(std::sqrt(v) / l);
     s->dev.walk_steps = p.walk_steps;
     s->dev.scatter_min = p.scatter_min;
 }

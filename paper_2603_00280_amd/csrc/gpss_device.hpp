@@ -33,16 +33,16 @@ constexpr int kCondTriEntries = cond_tri_entries(kMaxObs);
 static_assert(kMaxObs % 4 == 0, "observations are processed four at a time");
 
 // Scheduling policy of the persistent tracer for one scene: cell steps per walk operation and
-// the lanes a scatter operation waits for.  Rough media (largest gradient spread
+// the lanes a scatter operation waits for.  Rough media (typical gradient spread
 // s = sigma / l of at least sqrt(2), roughness alpha >= 2) scatter at most tentative
 // collisions and run faster with short walks and fuller scatter operations (4, 24); smooth
-// ones with longer walks (6, 16).  Measured on the sphere workloads; the choice reorders work
-// across lanes only, never within a path, so images do not depend on it.
+// ones with longer walks (6, 16).  Measured on the sphere and mixed workloads; the choice
+// reorders work across lanes only, never within a path, so images do not depend on it.
 struct SchedPolicy {
     int walk_steps, scatter_min;
 };
-inline SchedPolicy sched_policy(float s_max) {
-    return s_max >= 1.41421356f ? SchedPolicy{4, 24} : SchedPolicy{6, 16};
+inline SchedPolicy sched_policy(float s_typical) {
+    return s_typical >= 1.41421356f ? SchedPolicy{4, 24} : SchedPolicy{6, 16};
 }
 constexpr int kStepCap = 1 << 16;           // tentative collisions per segment
 constexpr float kRRThreshold = 0.0625f;     // shadow-ray Russian roulette below this transmittance
