@@ -47,7 +47,8 @@ def build(verbose: bool = False, extra=None, sanitize: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", lib + ".tmp", *objs]
+    # roctx: the entry points' host-side ranges
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", lib + ".tmp", *objs, "-lrocprofiler-sdk-roctx"]
     if sanitize:
         cmd += SANITIZE + ["-shared-libasan"]
     if verbose:

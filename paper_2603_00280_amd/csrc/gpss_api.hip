@@ -359,6 +359,7 @@ int upload(const float* src, size_t n, float** dst) {
 void free_scene(gpss_scene* s) {
     if (!s) return;
     (void)hipFree(s->d_prims);
+    (void)hipFree(s->d_cand);
     (void)hipFree(s->d_offset);
     (void)hipFree(s->d_var);
     (void)hipFree(s->d_maj);
@@ -397,6 +398,72 @@ void set_policy(gpss_scene* s) {
     const gpss::SchedPolicy p = gpss::sched_policy(std::sqrt(v) / l);
     s->dev.walk_steps = p.walk_steps;
     s->dev.scatter_min = p.scatter_min;
+}
+
+// Per majorant cell, the primitives that can be the union's minimum somewhere in the cell
+// (SceneDev::prim_cand).  Each primitive's SDF is 1-Lipschitz, so over the cell widened by a
+// margin it stays within r of its value at the centre (r: half the widened cell's diagonal).
+// A primitive whose lower bound d_p - r exceeds the smallest upper bound min_q d_q + r by more
+// than the margin is above the minimum everywhere in the cell, so it can neither be the
+// minimum nor tie with it.  The margins (1e-4 of the box) are far above the single-precision
+// rounding of a point's cell index and of its distances.  Cells with more than seven
+// candidates, and unions of fewer than four or more than sixteen primitives, take all.
+constexpr uint32_t kCandMinPrims = 4, kCandMaxPrims = 16, kCandMax = 7;
+
+static double sdf_host(const float* p, const double x[3]) {
+    double v[3], q[3];
+    for (int a = 0; a < 3; ++a) v[a] = x[a] - (double)p[1 + a];
+    if (p[0] < 0.5f) return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - (double)p[4];
+    double out = 0.0, qmax = -INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        q[a] = std::fabs(v[a]) - (double)p[4 + a];
+        qmax = std::max(qmax, q[a]);
+        out += q[a] > 0.0 ? q[a] * q[a] : 0.0;
+    }
+    return qmax > 0.0 ? std::sqrt(out) : qmax;
+}
+
+static int build_candidates(gpss_scene* s) {
+    const gpss_scene_desc& D = s->desc;
+    const uint32_t n = D.n_prims;
+    if (D.mean_kind != GPSS_MEAN_SDF || n < kCandMinPrims || n > kCandMaxPrims) return GPSS_OK;
+    const uint32_t M[3] = {D.majorant_res[0], D.majorant_res[1], D.majorant_res[2]};
+    double lo[3], cw[3], ext_max = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double ext = (double)D.bounds[3 + a] - (double)D.bounds[a];
+        lo[a] = D.bounds[a];
+        cw[a] = ext / M[a];
+        ext_max = std::max(ext_max, ext);
+    }
+    const double margin = 1e-4 * ext_max;
+    double r2 = 0.0;
+    for (int a = 0; a < 3; ++a) r2 += (0.5 * cw[a] + margin) * (0.5 * cw[a] + margin);
+    const double r = std::sqrt(r2);
+    std::vector<uint32_t> tab((size_t)M[0] * M[1] * M[2]);
+    std::vector<double> d(n);
+    size_t cell = 0;
+    for (uint32_t iz = 0; iz < M[2]; ++iz)
+        for (uint32_t iy = 0; iy < M[1]; ++iy)
+            for (uint32_t ix = 0; ix < M[0]; ++ix, ++cell) {
+                const double c[3] = {lo[0] + (ix + 0.5) * cw[0], lo[1] + (iy + 0.5) * cw[1], lo[2] + (iz + 0.5) * cw[2]};
+                double dmin = INFINITY;
+                for (uint32_t p = 0; p < n; ++p) {
+                    d[p] = sdf_host(s->prims_h.data() + 8 * p, c);
+                    dmin = std::min(dmin, d[p]);
+                }
+                uint32_t word = 0, cnt = 0;
+                for (uint32_t p = 0; p < n; ++p) {
+                    if (d[p] - r > dmin + r + margin) continue;
+                    if (cnt < kCandMax) word |= p << (4 + 4 * cnt);
+                    ++cnt;
+                }
+                tab[cell] = cnt <= kCandMax ? (word | cnt) : 15u;
+            }
+    int rc = check_hip(hipMalloc(&s->d_cand, tab.size() * sizeof(uint32_t)), "hipMalloc(candidates)");
+    if (!rc)
+        rc = check_hip(hipMemcpy(s->d_cand, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+                       "hipMemcpy(candidates)");
+    return rc;
 }
 
 void fill_dev(gpss_scene* s) {
@@ -442,6 +509,7 @@ void fill_dev(gpss_scene* s) {
         V.var_scale_d[a] = s->d_var ? (D.var_res[a] - 1) / ext : 0.0;
     }
     V.maj = s->d_maj;
+    V.prim_cand = s->d_cand;
     V.R = D.mix_R;
     for (int k = 0; k < 4; ++k) {
         V.dl[k] = D.dir_light[k];
@@ -506,6 +574,7 @@ extern "C" {
 const char* gpss_last_error(void) { return g_last_error.c_str(); }
 
 int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out) {
+    gpss::Range range("gpss_scene_create");
     try {
         if (!out) return set_error(GPSS_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
@@ -519,6 +588,7 @@ int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out) {
         if (!rc && D.mean_kind == GPSS_MEAN_SDF) {
             s->prims_h.assign(D.prims, D.prims + 8 * D.n_prims);
             rc = upload(s->prims_h.data(), s->prims_h.size(), &s->d_prims);
+            if (!rc) rc = build_candidates(s);
         }
         if (!rc && D.mean_offset) {
             const size_t n = (size_t)D.off_res[0] * D.off_res[1] * D.off_res[2];
@@ -605,6 +675,7 @@ int gpss_scene_get_majorants(gpss_scene_t scene, float* out, uint64_t n) {
 
 int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_dev, uint32_t s0, uint32_t s1,
                       gpss_stream_t stream) {
+    gpss::Range range("gpss_render_paths");
     if (!scene || !paths_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
     if (int rc = gpss::check_path_count(scene, s0, s1)) return rc;
     return gpss::launch_render_paths(scene, paths_dev, counters_dev, s0, s1 - s0,
@@ -612,6 +683,7 @@ int gpss_render_paths(gpss_scene_t scene, float* paths_dev, uint64_t* counters_d
 }
 
 int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream) {
+    gpss::Range range("gpss_render");
     if (!scene || !image_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
     if (int rc = gpss::check_path_count(scene, s0, s1)) return rc;
     const uint32_t ns = s1 - s0;
@@ -633,6 +705,7 @@ int gpss_render(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1, 
 
 int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, float variance, float lengthscale,
                           float albedo, gpss_stream_t stream) {
+    gpss::Range range("gpss_scene_set_params");
     if (!scene) return set_error(GPSS_ERR_INVALID_ARG, "scene is NULL");
     if (scene->dev.n_obs > 0)
         return set_error(GPSS_ERR_UNSUPPORTED, "parameters of a conditioned GP are fixed at creation");
@@ -668,6 +741,7 @@ int gpss_scene_set_params(gpss_scene_t scene, const float* mean_offset_dev, floa
 
 int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float* grad_offset_dev,
                         float* grad_scalars_dev, uint32_t s0, uint32_t s1, gpss_stream_t stream) {
+    gpss::Range range("gpss_render_adjoint");
     if (!scene || !dloss_dimage_dev || !grad_scalars_dev) return set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
     if (int rc = gpss::check_path_count(scene, s0, s1)) return rc;
     if (scene->d_offset && !grad_offset_dev)
@@ -680,6 +754,7 @@ int gpss_render_adjoint(gpss_scene_t scene, const float* dloss_dimage_dev, float
 }
 
 int gpss_render_batch(const gpss_scene_t* scenes, uint32_t n, float* const* images_dev, gpss_stream_t stream) {
+    gpss::Range range("gpss_render_batch");
     try {
         return gpss::render_batch(scenes, n, images_dev, reinterpret_cast<hipStream_t>(stream));
     } catch (...) {
@@ -689,6 +764,7 @@ int gpss_render_batch(const gpss_scene_t* scenes, uint32_t n, float* const* imag
 
 int gpss_batch_autotune(const gpss_scene_t* scenes, uint32_t n, float* const* images_dev, gpss_stream_t stream,
                         uint32_t* tile, uint32_t* waves_per_cu, float* ms) {
+    gpss::Range range("gpss_batch_autotune");
     try {
         return gpss::autotune_batch(scenes, n, images_dev, reinterpret_cast<hipStream_t>(stream), tile,
                                     waves_per_cu, ms);

@@ -86,6 +86,9 @@ struct SceneDev {
     double off_scale_d[3], var_scale_d[3];          // the grid scales in double
     int M[3];
     const float* maj;             // majorant grid, x fastest
+    const uint32_t* prim_cand;    // per majorant cell: the primitives that can be the union's minimum
+                                  // there (count in bits 0-3, up to 7 indices of 4 bits above, in
+                                  // increasing order; count 15: all); null: every cell takes all
     float R;
     float dl[4], pl[4], env;
     int cam_kind;
@@ -101,6 +104,9 @@ struct SceneDev {
 // of the scheduled loop behind a memory access.
 __device__ __forceinline__ float ld_global(const float* p) {
     return *(const __attribute__((address_space(1))) float*)p;
+}
+__device__ __forceinline__ uint32_t ld_global(const uint32_t* p) {
+    return *(const __attribute__((address_space(1))) uint32_t*)p;
 }
 __device__ __forceinline__ float4 ld_global(const float4* p) {
     typedef float v4 __attribute__((ext_vector_type(4)));
@@ -275,16 +281,42 @@ __device__ __forceinline__ float sdf_prim(float4 a, float4 b, float3 x, float3& 
     return qmax;
 }
 
+// Candidate word of the majorant cell holding x (see SceneDev::prim_cand; the scene has a
+// table), or 15 (every primitive) where x lies outside the grid.  The table's bounds hold on
+// each cell widened by a margin far above the rounding of this cell index, so a point on a
+// cell boundary may take either neighbour.
+__device__ __forceinline__ uint32_t prim_candidates(const SceneDev& S, float3 x) {
+    const int ix = (int)floorf((x.x - S.lo[0]) * S.inv_cw[0]);
+    const int iy = (int)floorf((x.y - S.lo[1]) * S.inv_cw[1]);
+    const int iz = (int)floorf((x.z - S.lo[2]) * S.inv_cw[2]);
+    if ((unsigned)ix >= (unsigned)S.M[0] || (unsigned)iy >= (unsigned)S.M[1] || (unsigned)iz >= (unsigned)S.M[2])
+        return 15u;
+    return ld_global(S.prim_cand + (iz * S.M[1] + iy) * S.M[0] + ix);
+}
+
+// Union of the primitives' SDFs: the smallest distance, its primitive's gradient and index
+// (the lower index on ties).  Only the cell's candidates can be that primitive (nor tie with
+// it), so visiting them in increasing order gives the full loop's result exactly.
 __device__ __forceinline__ void mean_geom(const SceneDev& S, float3 x, float& f, float3& g, int& which) {
     which = -1;
     if (S.mean_kind == 0) { f = x.z; g = f3(0.0f, 0.0f, 1.0f); return; }
     if (S.mean_kind == 2) { f = S.mean_const; g = f3(0.0f, 0.0f, 0.0f); return; }
     float best = INFINITY;
     float3 bg = f3(0.0f, 0.0f, 1.0f);
-    for (int i = 0; i < S.n_prims; ++i) {
-        float3 gi;
-        const float fi = sdf_prim(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
-        if (fi < best) { best = fi; bg = gi; which = i; }
+    const uint32_t cand = S.prim_cand ? prim_candidates(S, x) : 15u;
+    if (cand != 15u) {
+        for (int k = 0; k < (int)(cand & 15u); ++k) {
+            const int i = (int)((cand >> (4 + 4 * k)) & 15u);
+            float3 gi;
+            const float fi = sdf_prim(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
+            if (fi < best) { best = fi; bg = gi; which = i; }
+        }
+    } else {
+        for (int i = 0; i < S.n_prims; ++i) {
+            float3 gi;
+            const float fi = sdf_prim(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
+            if (fi < best) { best = fi; bg = gi; which = i; }
+        }
     }
     f = best;
     g = bg;
@@ -943,10 +975,21 @@ __device__ __forceinline__ GeomD eval_geom_d(const SceneDev& S, D3 x) {
     } else {
         double best = INFINITY;
         q.G = d3(0.0, 0.0, 1.0);
-        for (int i = 0; i < S.n_prims; ++i) {
-            D3 gi;
-            const double fi = sdf_prim_dd(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
-            if (fi < best) { best = fi; q.G = gi; }
+        // the cell's candidates (prim_candidates; the table's margin covers the rounding of x)
+        const uint32_t cand = S.prim_cand ? prim_candidates(S, to_f3(x)) : 15u;
+        if (cand != 15u) {
+            for (int k = 0; k < (int)(cand & 15u); ++k) {
+                const int i = (int)((cand >> (4 + 4 * k)) & 15u);
+                D3 gi;
+                const double fi = sdf_prim_dd(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
+                if (fi < best) { best = fi; q.G = gi; }
+            }
+        } else {
+            for (int i = 0; i < S.n_prims; ++i) {
+                D3 gi;
+                const double fi = sdf_prim_dd(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
+                if (fi < best) { best = fi; q.G = gi; }
+            }
         }
     }
     if (S.offset) {

@@ -8,10 +8,21 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/gpss.h"
 #include "gpss_device.hpp"
 
 namespace gpss {
+
+// A roctx range over the host side of an entry point (argument checks and enqueue, not the
+// device's execution): rocprofv3 --marker-trace shows it on the calling thread's timeline.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 // Structure-of-arrays path state and queues of the wavefront tracer (device pointers).
 struct WfState {
     double *ox, *oy, *oz, *dx, *dy, *dz;   // ray origin (collision point after track) and direction
@@ -35,6 +46,7 @@ struct gpss_scene {
     float* d_offset = nullptr;
     float* d_var = nullptr;
     float* d_maj = nullptr;
+    uint32_t* d_cand = nullptr;        // per majorant cell: the union's candidate primitives (or null)
     float* d_obs = nullptr;            // conditioned GP: kMaxObs float4 (position, alpha) + packed L^-1 rows
     double* d_obs_d = nullptr;         // the same in double for the majorant: 3n positions, n alpha, n x n L^-1
     float* d_scratch = nullptr;        // per-path radiances of the wavefront and one-thread forms

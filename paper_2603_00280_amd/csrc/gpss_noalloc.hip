@@ -73,6 +73,7 @@ int render_noalloc(gpss_scene* s, float* image, uint32_t s0, uint32_t s1, hipStr
 
 extern "C" int gpss_render_noalloc(gpss_scene_t scene, float* image_dev, uint32_t s0, uint32_t s1,
                                    gpss_stream_t stream) {
+    gpss::Range range("gpss_render_noalloc");
     if (!scene || !image_dev) return gpss::set_error(GPSS_ERR_INVALID_ARG, "NULL argument");
     if (int rc = gpss::check_path_count(scene, s0, s1)) return rc;
     return gpss::render_noalloc(scene, image_dev, s0, s1, reinterpret_cast<hipStream_t>(stream));

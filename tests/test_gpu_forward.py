@@ -96,6 +96,43 @@ def test_medium_evaluation_matches_oracle(G):
         assert worst["proj"] < 1e-4 and worst["sigma_t"] < 1e-4 and worst["ndf"] < 1e-4
 
 
+def test_union_candidate_table_equals_full_union(G):
+    """The per-cell candidate primitives of a union mean give the full union's result bit for
+    bit: the mixed scene with its 64^3 majorant grid (about 1.4 candidates per cell) against
+    the same scene with one majorant cell (more than seven candidates: every primitive), at
+    random points, points on cell boundaries and one float step either side of them, and
+    points near the primitives' surfaces (the union's argmin changes there)."""
+    rng = np.random.default_rng(21)
+    s = sc.mixed_scene(width=8, height=8)
+    lo, hi = s.bounds[:3].astype(np.float64), s.bounds[3:].astype(np.float64)
+    M = np.array(s.majorant_res)
+    cw = (hi - lo) / M
+    n = 6000
+    pts = [lo + rng.random((n, 3)) * (hi - lo)]
+    b = lo + rng.random((n, 3)) * (hi - lo)
+    ax = rng.integers(0, 3, n)
+    b[np.arange(n), ax] = lo[ax] + rng.integers(1, M[ax]) * cw[ax]     # on a cell face
+    pts.append(b)
+    c = lo + (rng.integers(1, M, (n, 3))) * cw                          # on cell corners
+    pts.append(c)
+    # near the primitives' surfaces: from a primitive's centre along a random direction
+    prim = s.prims[rng.integers(0, len(s.prims), n)].astype(np.float64)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pts.append(prim[:, 1:4] + d * (prim[:, 4:5] + rng.normal(0.0, 0.02, (n, 1))))
+    p32 = np.concatenate(pts).astype(np.float32)
+    p32 = np.concatenate([p32, np.nextafter(p32, np.float32(np.inf)), np.nextafter(p32, np.float32(-np.inf))])
+    p32 = p32[np.all((p32 >= lo) & (p32 <= hi), axis=1)]
+    dirs = rng.normal(size=p32.shape)
+    dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+    a = G.GpssScene(s).eval_medium(p32, dirs).cpu().numpy()
+    full = G.GpssScene(s.replace(majorant_res=(1, 1, 1))).eval_medium(p32, dirs).cpu().numpy()
+    print(f"[union table] {p32.shape[0]} points", flush=True)
+    assert a.shape == full.shape
+    bad = np.nonzero(np.any(a.view(np.uint32) != full.view(np.uint32), axis=1))[0]
+    assert bad.size == 0, (bad[:5], p32[bad[:5]], a[bad[:5]], full[bad[:5]])
+
+
 def test_parity_plane_full_size(G):
     """The tiny planar workload at its full size: 64x64, 16 spp, depth 8."""
     _parity(G, sc.plane_scene(), "plane")
