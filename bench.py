@@ -35,7 +35,7 @@ WORKLOADS = {
     "plane": "planar GPSS m(x)=z, variance 0.01, lengthscale 0.05, |z|<0.4, albedo 0.9, "
              "directional light 30 deg, ortho 64x64 at 45 deg, 16 spp, max depth 8",
     "mixed": "union SDF of 16 seeded spheres/boxes, 128^3 value-noise variance grid in "
-             "[1e-4,1e-2], lengthscale 0.03, 1024x1024, 256 spp, max depth 64",
+             "[1e-4,1e-2], lengthscale 0.03, 1024x1024, 256 spp, max depth 64, 80^3 majorant grid",
     "cond": "unit-sphere SDF prior conditioned on 32 noisy point observations (Fibonacci directions, "
             "radii jittered +-0.08, value 0, noise 0.05 x variance), variance 0.0025, lengthscale 0.25, "
             "pinhole 512x512, 64 spp, max depth 32",

@@ -283,7 +283,7 @@ def value_noise_grid(res: int, lattice: int, rng: np.random.Generator) -> np.nda
 def mixed_scene(width: int = 1024, height: int = 1024, spp: int = 256, max_depth: int = 64,
                 seed: int = 3, n_prims: int = 16, var_res: int = 128,
                 lengthscale: float = 0.03, var_lo: float = 1e-4, var_hi: float = 1e-2,
-                majorant_res=(64, 64, 64)) -> Scene:
+                majorant_res=(80, 80, 80)) -> Scene:
     rng = np.random.default_rng(seed)
     prims = []
     for _ in range(n_prims):
