@@ -360,6 +360,7 @@ void free_scene(gpss_scene* s) {
     if (!s) return;
     (void)hipFree(s->d_prims);
     (void)hipFree(s->d_cand);
+    (void)hipFree(s->d_maj16);
     (void)hipFree(s->d_offset);
     (void)hipFree(s->d_var);
     (void)hipFree(s->d_maj);
@@ -406,9 +407,9 @@ void set_policy(gpss_scene* s) {
 // A primitive whose lower bound d_p - r exceeds the smallest upper bound min_q d_q + r by more
 // than the margin is above the minimum everywhere in the cell, so it can neither be the
 // minimum nor tie with it.  The margins (1e-4 of the box) are far above the single-precision
-// rounding of a point's cell index and of its distances.  Cells with more than seven
+// rounding of a point's cell index and of its distances.  Cells with more than three
 // candidates, and unions of fewer than four or more than sixteen primitives, take all.
-constexpr uint32_t kCandMinPrims = 4, kCandMaxPrims = 16, kCandMax = 7;
+constexpr uint32_t kCandMinPrims = 4, kCandMaxPrims = 16, kCandMax = 3;
 
 static double sdf_host(const float* p, const double x[3]) {
     double v[3], q[3];
@@ -439,7 +440,7 @@ static int build_candidates(gpss_scene* s) {
     double r2 = 0.0;
     for (int a = 0; a < 3; ++a) r2 += (0.5 * cw[a] + margin) * (0.5 * cw[a] + margin);
     const double r = std::sqrt(r2);
-    std::vector<uint32_t> tab((size_t)M[0] * M[1] * M[2]);
+    std::vector<uint16_t> tab((size_t)M[0] * M[1] * M[2]);
     std::vector<double> d(n);
     size_t cell = 0;
     for (uint32_t iz = 0; iz < M[2]; ++iz)
@@ -454,14 +455,14 @@ static int build_candidates(gpss_scene* s) {
                 uint32_t word = 0, cnt = 0;
                 for (uint32_t p = 0; p < n; ++p) {
                     if (d[p] - r > dmin + r + margin) continue;
-                    if (cnt < kCandMax) word |= p << (4 + 4 * cnt);
+                    if (cnt < kCandMax) word |= p << (2 + 4 * cnt);
                     ++cnt;
                 }
-                tab[cell] = cnt <= kCandMax ? (word | cnt) : 15u;
+                tab[cell] = (uint16_t)(cnt <= kCandMax ? (word | cnt) : 0u);
             }
-    int rc = check_hip(hipMalloc(&s->d_cand, tab.size() * sizeof(uint32_t)), "hipMalloc(candidates)");
+    int rc = check_hip(hipMalloc(&s->d_cand, tab.size() * sizeof(uint16_t)), "hipMalloc(candidates)");
     if (!rc)
-        rc = check_hip(hipMemcpy(s->d_cand, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+        rc = check_hip(hipMemcpy(s->d_cand, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice),
                        "hipMemcpy(candidates)");
     return rc;
 }
@@ -508,7 +509,7 @@ void fill_dev(gpss_scene* s) {
         V.off_scale_d[a] = D.mean_offset || s->d_offset ? (D.off_res[a] - 1) / ext : 0.0;
         V.var_scale_d[a] = s->d_var ? (D.var_res[a] - 1) / ext : 0.0;
     }
-    V.maj = s->d_maj;
+    V.maj16 = s->d_maj16;
     V.prim_cand = s->d_cand;
     V.R = D.mix_R;
     for (int k = 0; k < 4; ++k) {
@@ -603,6 +604,7 @@ int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out) {
         if (!rc && D.n_obs > 0) rc = prepare_observations(s, D);
         const size_t nmaj = (size_t)D.majorant_res[0] * D.majorant_res[1] * D.majorant_res[2];
         if (!rc) rc = check_hip(hipMalloc(&s->d_maj, nmaj * sizeof(float)), "hipMalloc(majorants)");
+        if (!rc) rc = check_hip(hipMalloc(&s->d_maj16, nmaj * sizeof(uint16_t)), "hipMalloc(majorants16)");
         s->desc.prims = nullptr;
         s->desc.mean_offset = nullptr;
         s->desc.variance_grid = nullptr;

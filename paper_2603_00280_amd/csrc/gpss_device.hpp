@@ -85,10 +85,11 @@ struct SceneDev {
     double lo_d[3], hi_d[3], cw_d[3], inv_cw_d[3];  // the same box and cells in double
     double off_scale_d[3], var_scale_d[3];          // the grid scales in double
     int M[3];
-    const float* maj;             // majorant grid, x fastest
-    const uint32_t* prim_cand;    // per majorant cell: the primitives that can be the union's minimum
-                                  // there (count in bits 0-3, up to 7 indices of 4 bits above, in
-                                  // increasing order; count 15: all); null: every cell takes all
+    const uint16_t* maj16;        // majorant grid, x fastest, as the top 16 bits of each float: the
+                                  // majorants have five significant bits, so this is exact
+    const uint16_t* prim_cand;    // per majorant cell: the primitives that can be the union's minimum
+                                  // there (count 1-3 in bits 0-1, 4-bit indices above in increasing
+                                  // order; count 0: all); null: every cell takes all
     float R;
     float dl[4], pl[4], env;
     int cam_kind;
@@ -105,8 +106,8 @@ struct SceneDev {
 __device__ __forceinline__ float ld_global(const float* p) {
     return *(const __attribute__((address_space(1))) float*)p;
 }
-__device__ __forceinline__ uint32_t ld_global(const uint32_t* p) {
-    return *(const __attribute__((address_space(1))) uint32_t*)p;
+__device__ __forceinline__ uint32_t ld_global(const uint16_t* p) {
+    return *(const __attribute__((address_space(1))) uint16_t*)p;
 }
 __device__ __forceinline__ float4 ld_global(const float4* p) {
     typedef float v4 __attribute__((ext_vector_type(4)));
@@ -282,7 +283,7 @@ __device__ __forceinline__ float sdf_prim(float4 a, float4 b, float3 x, float3& 
 }
 
 // Candidate word of the majorant cell holding x (see SceneDev::prim_cand; the scene has a
-// table), or 15 (every primitive) where x lies outside the grid.  The table's bounds hold on
+// table), or 0 (every primitive) where x lies outside the grid.  The table's bounds hold on
 // each cell widened by a margin far above the rounding of this cell index, so a point on a
 // cell boundary may take either neighbour.
 __device__ __forceinline__ uint32_t prim_candidates(const SceneDev& S, float3 x) {
@@ -290,7 +291,7 @@ __device__ __forceinline__ uint32_t prim_candidates(const SceneDev& S, float3 x)
     const int iy = (int)floorf((x.y - S.lo[1]) * S.inv_cw[1]);
     const int iz = (int)floorf((x.z - S.lo[2]) * S.inv_cw[2]);
     if ((unsigned)ix >= (unsigned)S.M[0] || (unsigned)iy >= (unsigned)S.M[1] || (unsigned)iz >= (unsigned)S.M[2])
-        return 15u;
+        return 0u;
     return ld_global(S.prim_cand + (iz * S.M[1] + iy) * S.M[0] + ix);
 }
 
@@ -303,10 +304,10 @@ __device__ __forceinline__ void mean_geom(const SceneDev& S, float3 x, float& f,
     if (S.mean_kind == 2) { f = S.mean_const; g = f3(0.0f, 0.0f, 0.0f); return; }
     float best = INFINITY;
     float3 bg = f3(0.0f, 0.0f, 1.0f);
-    const uint32_t cand = S.prim_cand ? prim_candidates(S, x) : 15u;
-    if (cand != 15u) {
-        for (int k = 0; k < (int)(cand & 15u); ++k) {
-            const int i = (int)((cand >> (4 + 4 * k)) & 15u);
+    const uint32_t cand = S.prim_cand ? prim_candidates(S, x) : 0u;
+    if (cand != 0u) {
+        for (int k = 0; k < (int)(cand & 3u); ++k) {
+            const int i = (int)((cand >> (2 + 4 * k)) & 15u);
             float3 gi;
             const float fi = sdf_prim(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
             if (fi < best) { best = fi; bg = gi; which = i; }
@@ -976,10 +977,10 @@ __device__ __forceinline__ GeomD eval_geom_d(const SceneDev& S, D3 x) {
         double best = INFINITY;
         q.G = d3(0.0, 0.0, 1.0);
         // the cell's candidates (prim_candidates; the table's margin covers the rounding of x)
-        const uint32_t cand = S.prim_cand ? prim_candidates(S, to_f3(x)) : 15u;
-        if (cand != 15u) {
-            for (int k = 0; k < (int)(cand & 15u); ++k) {
-                const int i = (int)((cand >> (4 + 4 * k)) & 15u);
+        const uint32_t cand = S.prim_cand ? prim_candidates(S, to_f3(x)) : 0u;
+        if (cand != 0u) {
+            for (int k = 0; k < (int)(cand & 3u); ++k) {
+                const int i = (int)((cand >> (2 + 4 * k)) & 15u);
                 D3 gi;
                 const double fi = sdf_prim_dd(ld_const(S.prims + 2 * i), ld_const(S.prims + 2 * i + 1), x, gi);
                 if (fi < best) { best = fi; q.G = gi; }
@@ -1169,13 +1170,16 @@ struct Walker {
             s = 0;
         }
     }
-    __device__ __forceinline__ float majorant(const SceneDev& S) const { return ld_global(S.maj + idx); }
+    __device__ __forceinline__ static float maj_at(const SceneDev& S, int c) {
+        return __uint_as_float(ld_global(S.maj16 + c) << 16);
+    }
+    __device__ __forceinline__ float majorant(const SceneDev& S) const { return maj_at(S, idx); }
     // majorant of the cell that step(ax) would enter (of the current cell if it leaves the grid)
     __device__ __forceinline__ float next_majorant(const SceneDev& S, int ax) const {
         const int m0 = -(int)(ax == 0), m1 = -(int)(ax == 1), m2 = -(int)(ax == 2);
         const int left = (nx & m0) | (ny & m1) | (nz & m2);
         const int n = left > 0 ? idx + ((stx & m0) | (sty & m1) | (stz & m2)) : idx;
-        return ld_global(S.maj + n);
+        return maj_at(S, n);
     }
     // distance along the ray to the exit of the current cell and the axis crossed (ties go
     // to the lower axis)

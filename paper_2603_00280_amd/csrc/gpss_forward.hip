@@ -302,6 +302,13 @@ __global__ void majorant_kernel(MajArgs A, float* __restrict__ out) {
     out[cell] = (float)quantize_majorant(rho_max * proj_max);
 }
 
+// The walk's copy of the majorant grid (SceneDev::maj16): the top 16 bits of each float,
+// exact because quantize_majorant keeps five significant bits (and 0 and infinity).
+__global__ void majorant16_kernel(const float* __restrict__ maj, uint16_t* __restrict__ out, int n) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) out[c] = (uint16_t)(__float_as_uint(maj[c]) >> 16);
+}
+
 int launch_majorants(gpss_scene* s, hipStream_t stream) {
     const gpss_scene_desc& D = s->desc;
     MajArgs A{};
@@ -327,7 +334,8 @@ int launch_majorants(gpss_scene* s, hipStream_t stream) {
     A.obs_noise = D.obs_noise;
     const int n = A.M[0] * A.M[1] * A.M[2];
     hipLaunchKernelGGL(majorant_kernel, dim3((n + 127) / 128), dim3(128), 0, stream, A, s->d_maj);
-    return check_hip(hipGetLastError(), "majorant_kernel launch");
+    hipLaunchKernelGGL(majorant16_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, s->d_maj, s->d_maj16, n);
+    return check_hip(hipGetLastError(), "majorant kernels launch");
 }
 
 // ---------------------------------------------------------------------------

@@ -46,7 +46,8 @@ struct gpss_scene {
     float* d_offset = nullptr;
     float* d_var = nullptr;
     float* d_maj = nullptr;
-    uint32_t* d_cand = nullptr;        // per majorant cell: the union's candidate primitives (or null)
+    uint16_t* d_maj16 = nullptr;       // the walk's copy of the majorants (SceneDev::maj16)
+    uint16_t* d_cand = nullptr;        // per majorant cell: the union's candidate primitives (or null)
     float* d_obs = nullptr;            // conditioned GP: kMaxObs float4 (position, alpha) + packed L^-1 rows
     double* d_obs_d = nullptr;         // the same in double for the majorant: 3n positions, n alpha, n x n L^-1
     float* d_scratch = nullptr;        // per-path radiances of the wavefront and one-thread forms

@@ -99,7 +99,7 @@ def test_medium_evaluation_matches_oracle(G):
 def test_union_candidate_table_equals_full_union(G):
     """The per-cell candidate primitives of a union mean give the full union's result bit for
     bit: the mixed scene with its 80^3 majorant grid (about 1.3 candidates per cell) against
-    the same scene with one majorant cell (more than seven candidates: every primitive), at
+    the same scene with one majorant cell (more than three candidates: every primitive), at
     random points, points on cell boundaries and one float step either side of them, and
     points near the primitives' surfaces (the union's argmin changes there)."""
     rng = np.random.default_rng(21)
