@@ -58,6 +58,9 @@ def test_majorants_match_oracle_bitwise(G):
         assert gm.shape == om.shape
         diff = np.flatnonzero(gm.view(np.uint32) != om.view(np.uint32))
         assert diff.size == 0, (s.name, diff[:5], gm[diff[:5]], om[diff[:5]])
+        # five significant bits (or 0, or infinity): the walk's copy of the grid, the top 16
+        # bits of each float, holds every majorant exactly
+        assert not np.any(gm.view(np.uint32) & np.uint32(0xFFFF)), s.name
 
 
 def test_medium_evaluation_matches_oracle(G):
@@ -96,41 +99,66 @@ def test_medium_evaluation_matches_oracle(G):
         assert worst["proj"] < 1e-4 and worst["sigma_t"] < 1e-4 and worst["ndf"] < 1e-4
 
 
-def test_union_candidate_table_equals_full_union(G):
-    """The per-cell candidate primitives of a union mean give the full union's result bit for
-    bit: the mixed scene with its 80^3 majorant grid (about 1.3 candidates per cell) against
-    the same scene with one majorant cell (more than three candidates: every primitive), at
-    random points, points on cell boundaries and one float step either side of them, and
-    points near the primitives' surfaces (the union's argmin changes there)."""
-    rng = np.random.default_rng(21)
-    s = sc.mixed_scene(width=8, height=8)
+def _union_points(s, rng, n=6000):
+    """Random points, points on majorant-cell faces and corners, and points near the
+    primitives' surfaces, each also one float step either side; all inside the box."""
     lo, hi = s.bounds[:3].astype(np.float64), s.bounds[3:].astype(np.float64)
     M = np.array(s.majorant_res)
     cw = (hi - lo) / M
-    n = 6000
     pts = [lo + rng.random((n, 3)) * (hi - lo)]
     b = lo + rng.random((n, 3)) * (hi - lo)
     ax = rng.integers(0, 3, n)
     b[np.arange(n), ax] = lo[ax] + rng.integers(1, M[ax]) * cw[ax]     # on a cell face
     pts.append(b)
-    c = lo + (rng.integers(1, M, (n, 3))) * cw                          # on cell corners
-    pts.append(c)
-    # near the primitives' surfaces: from a primitive's centre along a random direction
+    pts.append(lo + (rng.integers(1, M, (n, 3))) * cw)                  # on cell corners
     prim = s.prims[rng.integers(0, len(s.prims), n)].astype(np.float64)
     d = rng.normal(size=(n, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     pts.append(prim[:, 1:4] + d * (prim[:, 4:5] + rng.normal(0.0, 0.02, (n, 1))))
     p32 = np.concatenate(pts).astype(np.float32)
     p32 = np.concatenate([p32, np.nextafter(p32, np.float32(np.inf)), np.nextafter(p32, np.float32(-np.inf))])
-    p32 = p32[np.all((p32 >= lo) & (p32 <= hi), axis=1)]
+    return p32[np.all((p32 >= lo) & (p32 <= hi), axis=1)]
+
+
+def _tie_scene():
+    """Seven primitives with exact ties (a duplicated sphere, a duplicated box) and a cluster
+    of small spheres closer together than a majorant cell (cells with more than three
+    candidates take every primitive)."""
+    P = sc.PRIM_SPHERE, sc.PRIM_BOX
+    prims = np.array([[P[0], 0.2, 0.1, 0.0, 0.3, 0, 0, 0.9],
+                      [P[1], -0.4, 0.3, 0.2, 0.2, 0.25, 0.15, 0.7],
+                      [P[0], 0.2, 0.1, 0.0, 0.3, 0, 0, 0.6],          # same sphere as 0
+                      [P[1], -0.4, 0.3, 0.2, 0.2, 0.25, 0.15, 0.5],   # same box as 1
+                      [P[0], 0.70, -0.6, 0.5, 0.02, 0, 0, 0.8],
+                      [P[0], 0.71, -0.6, 0.5, 0.02, 0, 0, 0.65],
+                      [P[0], 0.70, -0.59, 0.51, 0.02, 0, 0, 0.55]], np.float32)
+    return sc.mixed_scene(width=8, height=8, n_prims=7).replace(prims=prims)
+
+
+@pytest.mark.parametrize("name", ["mixed", "ties"])
+def test_union_candidate_table_equals_full_union(G, name):
+    """The per-cell candidate primitives of a union mean give the full union's result bit for
+    bit: the scene with its majorant grid (the mixed scene: 80^3, about 1.3 candidates per
+    cell) against the same scene with one majorant cell (more than three candidates: every
+    primitive), at random points, points on cell boundaries and one float step either side
+    of them, and points near the primitives' surfaces (the union's argmin changes there).
+    The tie scene has exact ties, where the lower index must win in both loops."""
+    rng = np.random.default_rng(21)
+    s = sc.mixed_scene(width=8, height=8) if name == "mixed" else _tie_scene()
+    p32 = _union_points(s, rng)
     dirs = rng.normal(size=p32.shape)
     dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
     a = G.GpssScene(s).eval_medium(p32, dirs).cpu().numpy()
     full = G.GpssScene(s.replace(majorant_res=(1, 1, 1))).eval_medium(p32, dirs).cpu().numpy()
-    print(f"[union table] {p32.shape[0]} points", flush=True)
+    print(f"[union table] {name}: {p32.shape[0]} points", flush=True)
     assert a.shape == full.shape
     bad = np.nonzero(np.any(a.view(np.uint32) != full.view(np.uint32), axis=1))[0]
     assert bad.size == 0, (bad[:5], p32[bad[:5]], a[bad[:5]], full[bad[:5]])
+    if name == "ties":
+        # on the duplicated sphere's surface region the lower index (albedo 0.9) wins
+        x = np.array([[0.2, 0.1, 0.31]], np.float32)
+        out = G.GpssScene(s).eval_medium(x, np.array([[0, 0, 1]], np.float32)).cpu().numpy()
+        assert out[0, 7] == np.float32(0.9)
 
 
 def test_parity_plane_full_size(G):
