@@ -118,7 +118,12 @@ typedef struct {
 
 /* Create a scene: validates `desc`, uploads primitives and grids, and builds the
  * conservative majorant grid on the device (double precision, rounded up to five
- * significant bits).  Synchronous.  *out receives the handle. */
+ * significant bits; the tracer reads a 16-bit copy, which holds every such value exactly).
+ * For a union of 4 to 16 primitives it also lists, per majorant cell, the primitives that can
+ * be the union's minimum there (2 bytes per cell), so that a medium evaluation visits only
+ * those; the results equal the full union's bit for bit.  Device memory beyond the inputs:
+ * 6 bytes per majorant cell (8 with such a union), and a ~0.5 KiB scene record.
+ * Synchronous.  *out receives the handle. */
 int gpss_scene_create(const gpss_scene_desc* desc, gpss_scene_t* out);
 int gpss_scene_destroy(gpss_scene_t scene);
 

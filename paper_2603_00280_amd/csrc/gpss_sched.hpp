@@ -13,7 +13,9 @@
 // operation for all lanes waiting on it.  Expensive operations wait until enough lanes
 // are ready, so that they run with most lanes active; while they wait, the other lanes
 // keep walking.  Every decision is wave-uniform, so the only divergence left is inside an
-// operation.
+// operation.  Paths that ended in the previous iteration are first added to their pixels,
+// one pixel at a time, through the wave's LDS pixel table (forward form with a pixel
+// accumulator).
 //
 // Per path the operations run in the same order, with the same random-number streams and
 // the same floating-point roundings as the one-thread-per-path routine trace_path; the
