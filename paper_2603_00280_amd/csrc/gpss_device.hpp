@@ -1170,17 +1170,17 @@ struct Walker {
             s = 0;
         }
     }
-    __device__ __forceinline__ static float maj_at(const SceneDev& S, int c) {
-        return __uint_as_float(ld_global(S.maj16 + c) << 16);
-    }
-    __device__ __forceinline__ float majorant(const SceneDev& S) const { return maj_at(S, idx); }
-    // majorant of the cell that step(ax) would enter (of the current cell if it leaves the grid)
-    __device__ __forceinline__ float next_majorant(const SceneDev& S, int ax) const {
+    // majorants as their top 16 bits (SceneDev::maj16); majorant_of turns them into floats
+    __device__ __forceinline__ uint32_t majorant_bits(const SceneDev& S) const { return ld_global(S.maj16 + idx); }
+    // bits of the majorant of the cell that step(ax) would enter (of the current cell if it
+    // leaves the grid)
+    __device__ __forceinline__ uint32_t next_majorant_bits(const SceneDev& S, int ax) const {
         const int m0 = -(int)(ax == 0), m1 = -(int)(ax == 1), m2 = -(int)(ax == 2);
         const int left = (nx & m0) | (ny & m1) | (nz & m2);
         const int n = left > 0 ? idx + ((stx & m0) | (sty & m1) | (stz & m2)) : idx;
-        return maj_at(S, n);
+        return ld_global(S.maj16 + n);
     }
+    __device__ __forceinline__ static float majorant_of(uint32_t bits) { return __uint_as_float(bits << 16); }
     // distance along the ray to the exit of the current cell and the axis crossed (ties go
     // to the lower axis)
     __device__ __forceinline__ double exit(int& ax) const {

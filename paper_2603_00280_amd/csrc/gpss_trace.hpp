@@ -17,7 +17,8 @@ struct Segment {
     D3 o, d;
     double t, t1, tau;
     Walker w;
-    float maj;      // majorant of the current cell (of the tentative collision after kTentative)
+    float maj;      // majorant of the tentative collision (set when step() returns kTentative)
+    uint32_t majb;  // the current cell's majorant as its top 16 bits (Walker::majorant_of)
     int steps;      // tentative collisions so far
     template <bool STATS>
     __device__ __forceinline__ void begin(const SceneDev& S, D3 o_, D3 d_, D3 inv, double t0, double t1_,
@@ -27,7 +28,7 @@ struct Segment {
         t = t0;
         t1 = t1_;
         w.init(S, o, d, inv, t0);
-        maj = w.majorant(S);
+        majb = w.majorant_bits(S);
         tau = -(double)logf(1.0f - rng.uniform());
         steps = 0;
         if (STATS) st.cells++;
@@ -48,18 +49,22 @@ struct Segment {
     __device__ __forceinline__ int step(const SceneDev& S, PathStats& st) {
         int ax;
         const double tn = w.exit(ax);
-        // the next cell's majorant is requested before this cell's work, to arrive by the
-        // time the walk enters that cell
-        const float mn = w.next_majorant(S, ax);
-        const double tc = fmin(tn, t1);
-        const float m = maj;
+        // the next cell's majorant is requested before this cell's work and kept as loaded
+        // (converted at its use in the next step), so that the load can complete while the
+        // walk finishes this cell and starts the next
+        const uint32_t mn = w.next_majorant_bits(S, ax);
+        const double tc = tn < t1 ? tn : t1;
+        const float m = Walker::majorant_of(majb);
         const double seg = fmax(0.0, tc - t);
-        if (m > 0.0f && tau < (double)m * seg) return kTentative;
+        if (m > 0.0f && tau < (double)m * seg) {
+            maj = m;
+            return kTentative;
+        }
         if (m > 0.0f) tau -= (double)m * seg;
         t = tc;
         if (tn >= t1) return kEnd;
         if (!w.step(ax)) return kEnd;
-        maj = mn;
+        majb = mn;
         if (STATS) st.cells++;
         return kCell;
     }
