@@ -130,6 +130,25 @@ void sdf_prim(const Prim& p, const double x[3], double& f, double g[3]) {
     }
 }
 
+// Lower bound of a primitive's signed distance over the box [blo, bhi] (the majorant's mean
+// bound; any lower bound keeps the majorant valid, a tight one keeps it small).  Sphere: the
+// distance from its centre to the box, minus the radius (exact).  Box (centre c, half extents
+// h): along each axis m_a is the smallest |x_a - c_a| - h_a over the box; the signed distance
+// is never below max_a of |x_a - c_a| - h_a, and where some m_a > 0 the whole box lies outside
+// the primitive, where the distance is the length of the positive parts.
+double sdf_prim_min(const Prim& p, const double blo[3], const double bhi[3]) {
+    double m[3];
+    for (int a = 0; a < 3; ++a) {
+        const double gap = p.c[a] < blo[a] ? blo[a] - p.c[a] : (p.c[a] > bhi[a] ? p.c[a] - bhi[a] : 0.0);
+        m[a] = p.kind == 0 ? gap : gap - p.h[a];
+    }
+    if (p.kind == 0) return std::sqrt(dot3(m, m)) - p.h[0];
+    const double mmax = std::max(m[0], std::max(m[1], m[2]));
+    if (!(mmax > 0.0)) return mmax;
+    const double mp[3] = {std::max(m[0], 0.0), std::max(m[1], 0.0), std::max(m[2], 0.0)};
+    return std::sqrt(dot3(mp, mp));
+}
+
 double sdf_union(const Scene& S, const double x[3], double g[3], int& which) {
     double best = INFINITY;
     which = -1;
@@ -832,7 +851,6 @@ void build_majorants(Scene& S) {
     S.maj.assign(n, 0.0);
     double cwv[3];
     for (int a = 0; a < 3; ++a) cwv[a] = S.ext[a] / S.M[a];
-    const double hdiag = 0.5 * std::sqrt(cwv[0] * cwv[0] + cwv[1] * cwv[1] + cwv[2] * cwv[2]);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int kz = 0; kz < S.M[2]; ++kz)
         for (int ky = 0; ky < S.M[1]; ++ky)
@@ -884,10 +902,14 @@ void build_majorants(Scene& S) {
                     mu_min = S.mean_const;
                     gmax = 0.0;
                 } else {
-                    double c[3], g[3];
-                    for (int a = 0; a < 3; ++a) c[a] = S.lo[a] + (k[a] + 0.5) * cwv[a];
-                    int which;
-                    mu_min = sdf_union(S, c, g, which) - hdiag;
+                    // the union's minimum over the cell: the smallest primitive bound
+                    double blo[3], bhi[3];
+                    for (int a = 0; a < 3; ++a) {
+                        blo[a] = S.lo[a] + k[a] * cwv[a];
+                        bhi[a] = S.lo[a] + (k[a] + 1) * cwv[a];
+                    }
+                    mu_min = INFINITY;
+                    for (const Prim& p : S.prims) mu_min = std::min(mu_min, sdf_prim_min(p, blo, bhi));
                     gmax = 1.0;
                 }
                 mu_min += off_min;

@@ -12,7 +12,8 @@ namespace gpss {
 //   rho(mu, sigma) = r(mu / sigma) / sigma with r = phi / Phi decreasing, so
 //     rho <= r(mu_min / (mu_min > 0 ? sigma_max : sigma_min)) / sigma_min;
 //   sigma_proj <= E[max(0, X)], X ~ N(gmax, s_max^2) = g Phi(g/s) + s phi(g/s);
-//   mu_min = mu(centre) - half diagonal for 1-Lipschitz SDF unions (exact for the plane),
+//   mu_min = the smallest of the primitives' exact minima over the cell (sdf_prim_min_d;
+//   exact for the plane),
 //   plus the minimum offset node reaching the cell, gmax = |grad sdf| + bound of the
 //   trilinear offset gradient.
 // The bound times (1 + 2^-10) is rounded up to five significant bits; bounds below
@@ -47,6 +48,28 @@ __device__ double sdf_prim_d(float4 a, float4 b, const double x[3]) {
         return sqrt(p0 * p0 + p1 * p1 + p2 * p2);
     }
     return qmax;
+}
+
+// Lower bound of a primitive's signed distance over the box [blo, bhi]: for a sphere the
+// distance from its centre to the box minus the radius; for a box, with m_a the smallest
+// |x_a - c_a| - h_a over the box, the length of the positive m_a when one is positive (the
+// cell lies outside the primitive), else max_a m_a (the distance is never below it).  The
+// oracle's arithmetic, operation for operation (no contraction), so that both grids agree.
+__device__ double sdf_prim_min_d(float4 a, float4 b, const double blo[3], const double bhi[3]) {
+#pragma clang fp contract(off)
+    const double c[3] = {(double)a.y, (double)a.z, (double)a.w};
+    const double h[3] = {(double)b.x, (double)b.y, (double)b.z};
+    const bool sphere = a.x < 0.5f;
+    double m[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const double gap = c[ax] < blo[ax] ? blo[ax] - c[ax] : (c[ax] > bhi[ax] ? c[ax] - bhi[ax] : 0.0);
+        m[ax] = sphere ? gap : gap - h[ax];
+    }
+    if (sphere) return sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) - h[0];
+    const double mmax = fmax(m[0], fmax(m[1], m[2]));
+    if (!(mmax > 0.0)) return mmax;
+    const double p0 = fmax(m[0], 0.0), p1 = fmax(m[1], 0.0), p2 = fmax(m[2], 0.0);
+    return sqrt(p0 * p0 + p1 * p1 + p2 * p2);
 }
 
 __device__ double quantize_majorant(double B) {
@@ -272,11 +295,18 @@ __global__ void majorant_kernel(MajArgs A, float* __restrict__ out) {
         mu_centre = mu_min;
         gmax = 0.0;
     } else {
-        double c[3];
-        for (int a = 0; a < 3; ++a) c[a] = (double)A.lo[a] + (k[a] + 0.5) * cw[a];
+        double c[3], blo[3], bhi[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = (double)A.lo[a] + (k[a] + 0.5) * cw[a];
+            blo[a] = __dadd_rn((double)A.lo[a], __dmul_rn((double)k[a], cw[a]));
+            bhi[a] = __dadd_rn((double)A.lo[a], __dmul_rn((double)(k[a] + 1), cw[a]));
+        }
         double best = INFINITY;
-        for (int i = 0; i < A.n_prims; ++i) best = fmin(best, sdf_prim_d(A.prims[2 * i], A.prims[2 * i + 1], c));
-        mu_min = best - hdiag;
+        mu_min = INFINITY;
+        for (int i = 0; i < A.n_prims; ++i) {
+            best = fmin(best, sdf_prim_d(A.prims[2 * i], A.prims[2 * i + 1], c));
+            mu_min = fmin(mu_min, sdf_prim_min_d(A.prims[2 * i], A.prims[2 * i + 1], blo, bhi));
+        }
         mu_centre = best;
         gmax = 1.0;
     }
