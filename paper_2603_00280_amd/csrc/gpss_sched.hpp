@@ -47,6 +47,16 @@ enum LaneOp : int { kOpIdle = 0, kOpWalk = 1, kOpEval = 2, kOpScatter = 3, kOpBe
 #ifndef GPSS_SCHED_REFILL_MIN
 #define GPSS_SCHED_REFILL_MIN 8
 #endif
+// Drain (adjoint form): once the path source is exhausted and at most this many lanes are
+// busy, the wave runs every pending operation as soon as one lane needs it, for the latency
+// of its last paths rather than for full operations.  The adjoint traces each path twice in
+// one lane, so on its million-path launches the last paths' latency is much of the call.
+// The forward form keeps the throughput policy throughout: the same drain in it shortened
+// small launches but changed the headline kernel's register allocation, which then either
+// spilled in the scatter operation or ran 1.3 % slower.
+#ifndef GPSS_SCHED_DRAIN
+#define GPSS_SCHED_DRAIN 32
+#endif
 // The scatter threshold and the cell steps per walk come from the scene record (walk_steps,
 // scatter_min): see sched_policy in gpss_device.hpp.
 #ifndef GPSS_SCHED_MIN_WAVES
@@ -338,9 +348,13 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
             if (accumulate && lane < kAccTable) flush_entry(lane);
             break;
         }
+        // wave-uniform, and read through a scalar register so that the compiler knows it: a
+        // condition it takes for divergent turns the operations' branches into masked code
+        const bool drain =
+            ADJ && __builtin_amdgcn_readfirstlane((int)(src.exhausted() && nBusy <= GPSS_SCHED_DRAIN)) != 0;
 
         // ---- phase sampling and light-connection set-up at real collisions ----
-        if (nScat > 0 && (nScat >= S.scatter_min || nWalk + nEval + nBegin == 0)) {
+        if (nScat > 0 && (drain || nScat >= S.scatter_min || nWalk + nEval + nBegin == 0)) {
             if (op == kOpScatter) {
                 ++b;
                 const D3 d = seg_dir();
@@ -406,7 +420,7 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
         }
 
         // ---- segment starts: next track segment or shadow ray ----
-        if (nBegin > 0 && (nBegin >= GPSS_SCHED_BEGIN_MIN || nWalk + nEval == 0)) {
+        if (nBegin > 0 && (drain || nBegin >= GPSS_SCHED_BEGIN_MIN || nWalk + nEval == 0)) {
             if (op == kOpBegin) {
                 const uint32_t pixel = cs_u[kPixel][lt], sample = cs_u[kSample][lt];
                 if (mode == 0) {
@@ -473,7 +487,8 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
         // ---- medium evaluation at tentative collisions ----
         bool nee_done = false;
         constexpr int kEvalMin = MED == kMedCond ? GPSS_SCHED_EVAL_MIN_COND : GPSS_SCHED_EVAL_MIN;
-        if (nEval > 0 && (nEval >= kEvalMin || nWalk == 0)) {
+        const bool run_eval = nEval > 0 && (drain || nEval >= kEvalMin || nWalk == 0);
+        if (run_eval) {
             if (op == kOpEval) {
                 sg.advance();
                 // the generator's key and address words are recomputed here rather than kept
