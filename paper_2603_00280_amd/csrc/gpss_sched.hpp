@@ -487,7 +487,8 @@ __device__ __forceinline__ void run_scheduled(const SceneDev& S, Source& src, co
         // ---- medium evaluation at tentative collisions ----
         bool nee_done = false;
         constexpr int kEvalMin = MED == kMedCond ? GPSS_SCHED_EVAL_MIN_COND : GPSS_SCHED_EVAL_MIN;
-        const bool run_eval = nEval > 0 && (drain || nEval >= kEvalMin || nWalk == 0);
+        // with fewer than 8 lanes walking, waiting for fuller evaluations gains little
+        const bool run_eval = nEval > 0 && (drain || nEval >= kEvalMin || nWalk < 8);
         if (run_eval) {
             if (op == kOpEval) {
                 sg.advance();
